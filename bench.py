@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark of the Hawkes hot path on one MI355X.
+
+A step is one full evaluation (hawkes_eval with every output): the row pass
+over all N(N-1)/2 event pairs (intensities, background moments, excitation
+moments), the per-event finalisation with the integral term and the
+hyperparameter sums, and the column pass over the causal pairs (Eq. 3 and
+Eq. 4) -- log-likelihood, rate gradient, Hessian diagonal and hyperparameter
+gradient and Hessian.  Workload: N = 23,422 events simulated from the Hawkes
+branching process, rates lognormal(0, 0.5) on 1,610 of them (the paper's
+application size).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line with the metric (unordered pair-evaluations per second),
+the roofline of the dominant kernel (the row pass, HIP-event timed on its
+launch stream) and the FP64 oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 operations per unordered event pair (FMA = 2 flops, exp = 1).
+# Row pass: differences dt, dx, dy (3), r^2 (3), dt^2 (1), background and
+# excitation exponents (3 + 3) and exponentials (2), theta_j E (1), the four
+# background moment products (4) added to both events' sums (10), the
+# excitation sums X0, X1, X2, X11, X22 (9).  Column pass: dt, dx, dy, r^2 (6),
+# exponent (3), exponential (1), E w (1), G and H sums (3).
+FLOPS_ROW_PER_PAIR = 39
+FLOPS_COL_PER_PAIR = 14
+FLOPS_PER_PAIR = FLOPS_ROW_PER_PAIR + FLOPS_COL_PER_PAIR
+# MI355X FP32 vector peak (AMD spec: 256 CUs x 2.4 GHz, packed FP32 FMA).
+PEAK_FP32_TFLOPS = 157.3
+
+CONFIGS = {1: "N23422_branching_M1610", 0: "N1000_uniform_mix5", 2: "N100000_branching_M6874",
+           4: "N250000_branching_mix20_M17185"}
+
+
+def cpu_baseline(es, budget_s=12.0):
+    """The FP64 oracle (plain double loops, OpenMP over rows) on the host cores:
+    full evaluations of the same workload, repeated until `budget_s` elapse."""
+    import oracle
+    threads = oracle.max_threads()
+    n = es.n
+    pairs = n * (n - 1) / 2
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.evaluate_es(es)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 50:
+            break
+    return {"value": pairs * reps / el, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full FP64 evaluation(s) (loglik, rate gradient, Hessian diagonal, hyperparameter "
+                      f"derivatives) of the N={n} workload, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=1, choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the hot path is built and measured on a single MI355X; "
+              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2103_03348_amd import _lib, synth
+    from paper_2103_03348_amd.hawkes import Plan
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    es = synth.config(args.config)
+    n = es.n
+    pairs = n * (n - 1) / 2
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0, device="cuda:0")
+    theta = torch.as_tensor(es.theta, device=dev)
+    out = {}
+    for _ in range(args.warmup):
+        plan.eval(theta, es.hyper, loglik=True, grad_theta=True, grad_hyper=True, negH_theta=True,
+                  negH_hyper=True, out=out)
+    torch.cuda.synchronize()
+    if plan.status() != 0:
+        raise RuntimeError("device status after warm-up is not OK")
+    lib = _lib.lib()
+    _lib.check(lib.hawkes_profile_enable(plan.handle, 1), "profile_enable")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.eval(theta, es.hyper, loglik=True, grad_theta=True, grad_hyper=True, negH_theta=True,
+                  negH_hyper=True, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = (ctypes.c_double * 6)()
+    _lib.check(lib.hawkes_profile_read(plan.handle, prof), "profile_read")
+    _lib.check(lib.hawkes_profile_enable(plan.handle, 0), "profile_disable")
+    ms_step = 1e3 * el / args.steps
+    row_ms = prof[0] / max(prof[1], 1)
+    col_ms = prof[2] / max(prof[3], 1)
+    eval_ms = prof[4] / max(prof[5], 1)
+    ll = float(out["loglik"].item())
+    if not np.isfinite(ll):
+        raise RuntimeError("non-finite log-likelihood")
+
+    achieved = FLOPS_ROW_PER_PAIR * pairs / (row_ms * 1e-3) / 1e12
+    rec = {
+        "metric": "pair-evals/s for loglik+grad+Hess-diag at N=23,422" if args.config == 1
+        else f"pair-evals/s for loglik+grad+Hess-diag at N={n:,}",
+        "value": pairs / (ms_step * 1e-3),
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": CONFIGS[args.config],
+            "n_events": n,
+            "n_free_rates": int(es.subset.shape[0]),
+            "pairs_per_step": pairs,
+            "outputs": "loglik, grad_theta[N], grad_hyper[6], negH_theta[N], negH_hyper[6]",
+            "precision": "FP32 pair terms, compensated sums, FP64 finals",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_row (row pass)",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "flops_per_pair": FLOPS_ROW_PER_PAIR,
+            "kernel_ms": row_ms,
+        },
+        "passes_ms": {"row": row_ms, "col": col_ms, "eval": eval_ms},
+        "col_pass_tflops": FLOPS_COL_PER_PAIR * pairs / (col_ms * 1e-3) / 1e12 if col_ms > 0 else None,
+        "eval_tflops": FLOPS_PER_PAIR * pairs / (eval_ms * 1e-3) / 1e12,
+        "loglik": ll,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(es, args.cpu_budget)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * hawkes.h -- C ABI of the MI355X (gfx950) library for the spatiotemporal
+ * Hawkes log-likelihood with per-event rates, its gradient, its Hessian
+ * diagonal, and a Hamiltonian Monte Carlo step on the log-rates
+ * (Holbrook, Ji & Suchard, arXiv 2103.03348).
+ *
+ * Model (Sec. 2.1, D = 2).  Events (x_n, t_n), n = 1..N; window [T0, T1] with
+ * T1 = max_n t_n; hyperparameters (mu0, tau_x, tau_t, theta0, omega, h); rates
+ * theta_n >= 0.
+ *   lambda_i = mu0 (2 pi)^{-3/2} tau_x^{-2} tau_t^{-1} sum_{j != i} exp(-r_ij^2/(2 tau_x^2) - dt_ij^2/(2 tau_t^2))
+ *            + theta0 omega (2 pi h^2)^{-1} sum_{t_j < t_i} theta_j exp(-omega dt_ij - r_ij^2/(2 h^2))
+ *   Lambda   = mu0 sum_n [Phi((T1-t_n)/tau_t) - Phi((T0-t_n)/tau_t)]
+ *            + theta0 sum_n theta_n (1 - exp(-omega (T1 - t_n)))          (App. A)
+ *   loglik   = sum_i log lambda_i - Lambda                                  (Eq. 1)
+ *   d loglik/d theta_j = sum_{t_i > t_j} c_e E_ij / lambda_i - theta0 (1 - exp(-omega (T1 - t_j)))  (Eq. 3)
+ *   -d2 loglik/d theta_j^2 = sum_{t_i > t_j} (c_e E_ij / lambda_i)^2                              (Eq. 4)
+ * The paper's background is spatial only; the Gaussian-in-time factor is this
+ * library's extension.  Its integral is the exact integral of the stated
+ * background.  The self-exclusion indicator is j != i; the excitation is
+ * strictly causal (events tied in time do not excite each other).
+ *
+ * Conventions for every call below:
+ *  - d_* arguments are DEVICE pointers (any allocator, e.g. PyTorch's caching
+ *    allocator); the caller owns them.  Plain pointers without d_ are HOST.
+ *  - Every call is ordered on the HIP stream `stream` and returns without
+ *    synchronising, except hawkes_plan_create and hawkes_plan_status.
+ *  - Inputs and outputs are in the CALLER's event order; the library sorts by
+ *    time internally (stable: ties keep the caller's order).
+ *  - Return value: argument errors are detected on the host and returned at
+ *    once, with nothing enqueued.  Data-dependent conditions found on the
+ *    device (a zero intensity, a non-finite value) are recorded in a sticky
+ *    status word that hawkes_plan_status returns and clears.
+ *  - A plan is not thread-safe; calls on one plan must be ordered by the
+ *    caller (one stream, or explicit events).  Separate plans are independent.
+ *  - Precision: inputs and outputs are FP64.  The O(N^2) pair sums run in FP32
+ *    with compensated accumulation; log-intensities, the integral term, the
+ *    final reductions and the HMC energy run in FP64.
+ */
+#ifndef HAWKES_H_
+#define HAWKES_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hawkes_plan_s *hawkes_plan;
+
+typedef enum {
+    HAWKES_OK = 0,
+    HAWKES_E_INVALID = 1,        /* bad argument: n < 1, NULL required pointer, non-positive
+                                    tau_x/tau_t/omega/h, negative mu0/theta0, t_start > min t,
+                                    non-finite t/x/y, or (device-detected) a negative or
+                                    non-finite theta                                          */
+    HAWKES_E_ZERO_INTENSITY = 2, /* some lambda_i == 0 (e.g. a single event): loglik = -inf   */
+    HAWKES_E_NONFINITE = 3,      /* a NaN/Inf appeared in a device result                      */
+    HAWKES_E_DEVICE = 4,         /* a HIP runtime call failed                                  */
+    HAWKES_E_NOMEM = 5,          /* device allocation failed                                   */
+    HAWKES_E_UNSUPPORTED = 6     /* the call needs state that is not set (e.g. no subset)     */
+} hawkes_status;
+
+/* Hyperparameters, in the order (mu0, tau_x, tau_t, theta0, omega, h) used for
+ * the 6-vectors d_grad_hyper / d_negH_hyper below.  mu0 and theta0 are the
+ * background and self-excitatory weights; tau_x, tau_t the background space and
+ * time lengthscales; 1/omega the excitation time lengthscale; h its spatial
+ * lengthscale (Sec. 2.1). */
+typedef struct {
+    double mu0, tau_x, tau_t, theta0, omega, h;
+} hawkes_hyper;
+
+/* Build a plan for one event set (Sec. 2.1's data (x_n, t_n)).
+ *   n        number of events, >= 1
+ *   d_t      [n] event times (device, FP64)
+ *   d_xy     [n][2] event locations, row-major x0 y0 x1 y1 ... (device, FP64)
+ *   t_start  window start T0 (the paper uses 0); must be <= min t
+ * Sorts the events by time on the device, converts locations to 32-bit fixed
+ * point relative to the bounding-box centre (resolution 2^-31 of the extent),
+ * builds the tile tables and allocates all scratch.  Synchronises `stream`.
+ * On success *out owns device memory until hawkes_plan_destroy. */
+hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const double *d_t, const double *d_xy,
+                                 double t_start, hipStream_t stream);
+
+/* Free a plan and everything it owns.  Synchronises the device first. */
+hawkes_status hawkes_plan_destroy(hawkes_plan p);
+
+/* Number of events of the plan, or -1 for NULL. */
+int64_t hawkes_plan_size(hawkes_plan p);
+
+/* Core evaluation (Eq. 1, Eq. 3, Eq. 4 and the hyperparameter derivatives).
+ *   d_theta       [n] rates theta_n >= 0, caller order (device, FP64)
+ *   d_loglik      [1] loglik (Eq. 1)                           -- may be NULL
+ *   d_grad_theta  [n] d loglik / d theta_j (Eq. 3)            -- may be NULL
+ *   d_grad_hyper  [6] d loglik / d (mu0,tau_x,tau_t,theta0,omega,h) -- may be NULL
+ *   d_negH_theta  [n] -d2 loglik / d theta_j^2 (Eq. 4)        -- may be NULL
+ *   d_negH_hyper  [6] -d2 loglik / d p^2 for the six hyperparameters -- may be NULL
+ * One row pass over the causal pairs always runs (it gives lambda); a column
+ * pass runs iff d_grad_theta or d_negH_theta is non-NULL.  When some lambda_i
+ * is zero, loglik is -inf and the sticky status becomes HAWKES_E_ZERO_INTENSITY. */
+hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
+                          double *d_loglik, double *d_grad_theta, double *d_grad_hyper,
+                          double *d_negH_theta, double *d_negH_hyper, hipStream_t stream);
+
+/* Thin wrappers of hawkes_eval (same argument meaning). */
+hawkes_status hawkes_loglik(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
+                            double *d_loglik, hipStream_t stream);
+hawkes_status hawkes_grad(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
+                          double *d_loglik, double *d_grad_theta, double *d_grad_hyper,
+                          hipStream_t stream);
+hawkes_status hawkes_hessdiag(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
+                              double *d_negH_theta, double *d_negH_hyper, hipStream_t stream);
+
+/* Synchronise the plan's last stream, return the sticky device status and
+ * clear it. */
+hawkes_status hawkes_plan_status(hawkes_plan p);
+
+/* Per-event intermediate results of the last hawkes_eval, caller order:
+ * d_lambda [n] the intensities lambda_i (FP64).  Enqueued on `stream`. */
+hawkes_status hawkes_copy_lambda(hawkes_plan p, double *d_lambda, hipStream_t stream);
+
+/* ---- Free rates and Hamiltonian Monte Carlo (Sec. 2.2, Sec. 2.3.2) ----
+ *
+ * The paper samples the log-rates z of the M sequenced events (theta_k =
+ * exp(z_k) for k in the subset, every other rate fixed) by HMC with a diagonal
+ * mass matrix.  Because only the subset rates move along a trajectory, the
+ * library caches the part of every lambda_i that does not depend on them (the
+ * background, and the excitation by fixed-rate events) once per
+ * hyperparameter setting; each gradient then costs O(N M) pair terms. */
+
+/* Declare the free-rate subset of a plan.
+ *   m      subset size, 1 <= m <= n
+ *   d_idx  [m] distinct caller event indices (device, int64); slot k of the
+ *          subset is event d_idx[k].  The array is copied.
+ * Invalidates the cached static part.  Synchronises `stream`.  Returns
+ * HAWKES_E_INVALID for an index out of range or repeated. */
+hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const int64_t *d_idx, hipStream_t stream);
+
+/* Eq. 1, Eq. 3 and Eq. 4 restricted to the subset, by the O(N M) path.
+ *   d_theta        [n] full rate vector, caller order (device, read only)
+ *   refresh_static non-zero: recompute the cached static part (needed when the
+ *                  rates OFF the subset changed; a change of hyperparameters is
+ *                  detected by the library)
+ *   d_loglik       [1] loglik (Eq. 1) -- may be NULL
+ *   d_grad_sub     [m] d loglik / d theta_{idx[k]} (Eq. 3) -- may be NULL
+ *   d_negH_sub     [m] -d2 loglik / d theta_{idx[k]}^2 (Eq. 4) -- may be NULL
+ * Needs hawkes_plan_set_subset first (else HAWKES_E_UNSUPPORTED). */
+hawkes_status hawkes_subset_grad(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
+                                 int refresh_static, double *d_loglik, double *d_grad_sub, double *d_negH_sub,
+                                 hipStream_t stream);
+
+/* One HMC iteration on z (slot order) with target
+ *   log pi(z) = loglik(theta(z)) - sum_k z_k^2 / (2 sigma_z^2)
+ * (the prior of Eq. 2 with V = I), energy H = -log pi(z) + p^T M^{-1} p / 2, and
+ * L leapfrog steps of size eps with dz/dt = M^{-1} p.  Momenta p_k = sqrt(M_k) *
+ * N(0,1) from Philox-4x32-10 (Salmon et al. 2011) with key `seed` and counter
+ * (k, 0, counter_lo, counter_hi), standard normals by Box-Muller
+ * sqrt(-2 log(1-u1)) cos(2 pi u2) on 53-bit uniforms; the Metropolis uniform
+ * uses counter (0, 1, counter_lo, counter_hi).  The caller advances `counter`
+ * between iterations.  Everything stays on the device; nothing synchronises. */
+typedef struct {
+    double *d_z;           /* [m] log-rates, slot order (in: current; out: next state)         */
+    double *d_theta;       /* [n] full rates, caller order; entries of the subset are written  */
+                           /*     with exp(z), the others are read as the fixed rates          */
+    const double *d_mass;  /* [m] diagonal mass matrix M (momentum covariance), slot order     */
+    double eps;            /* leapfrog step size > 0                                            */
+    int L;                 /* leapfrog steps >= 1                                               */
+    double sigma_z;        /* prior standard deviation of z > 0                                 */
+    uint64_t seed;         /* Philox key                                                        */
+    uint64_t counter;      /* Philox counter of this iteration                                  */
+    int refresh_static;    /* non-zero: recompute the cached static part first                  */
+    double *d_out;         /* [8] device: accepted (1/0), H1 - H0, loglik and log pi at the
+                              returned state, min(1, exp(-(H1-H0))), loglik at the proposal, H0, H1 */
+} hawkes_hmc_args;
+
+hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawkes_hmc_args *args, hipStream_t stream);
+
+/* Timing of the pair passes with HIP events recorded on the launch stream.
+ * hawkes_profile_enable(p, 1) starts recording around every row pass, column
+ * pass and whole evaluation of plan p; 0 stops and discards.
+ * hawkes_profile_read synchronises and fills host out[6] with
+ * (total ms, count) for the row pass, the column pass and the whole evaluation
+ * since the last read, then resets the totals. */
+hawkes_status hawkes_profile_enable(hawkes_plan p, int on);
+hawkes_status hawkes_profile_read(hawkes_plan p, double *out);
+
+/* Calibration of the FP32 exponential.  Mean signed (d_out[0]) and mean absolute
+ * (d_out[1]) relative error of the hardware exp2 over `nsamples` arguments spread
+ * evenly over [lo, hi) (-126 <= lo < hi <= 0), against FP64 exp2; d_out[2] = nsamples.
+ * d_out is a device FP64 [3].  The pair sums are unbiased only if this mean matches
+ * hawkes_exp2_bias_constant(), the value the library corrects for. */
+hawkes_status hawkes_exp2_bias(int64_t nsamples, double lo, double hi, double *d_out, hipStream_t stream);
+double hawkes_exp2_bias_constant(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HAWKES_H_ */

@@ -1,0 +1,59 @@
+"""One Hamiltonian Monte Carlo iteration on the log-rates z of the free events,
+in FP64 on the CPU (Sec. 2.3.2).  Test infrastructure only.
+
+Target: log pi(z) = loglik(theta(z)) - sum_k z_k^2 / (2 sigma_z^2), with
+theta_{idx_k} = exp(z_k) and every other rate held fixed (Sec. 2.2 with
+beta = 0; the phylogenetic prior of Eq. 2 with V = I).  Energy
+H(z, p) = -log pi(z) + p^T M^{-1} p / 2 with a diagonal mass M.  The leapfrog
+integrator uses dz/dt = M^{-1} p (the paper prints a factor 1/2 there, read
+here as a typo).  Momenta and the Metropolis uniform come from Philox-4x32-10
+(oracle.philox) so that a GPU run with the same seed and counter can be
+replayed exactly.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import evaluate, philox
+
+
+def log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z):
+    th = theta_full.copy()
+    th[idx] = np.exp(z)
+    r = evaluate(es_t, es_x, es_y, th, hyper, t0, want=("loglik", "grad_theta", "negH_theta"))
+    ll = r["loglik"]
+    g = r["grad_theta"][idx]
+    lp = ll - float(np.sum(z * z)) / (2.0 * sigma_z ** 2)
+    grad_z = np.exp(z) * g - z / sigma_z ** 2
+    return lp, grad_z, ll, r
+
+
+def hmc_iteration(es_t, es_x, es_y, theta_full, idx, z0, mass, hyper, t0, eps, L, sigma_z, seed, counter):
+    """Returns dict(z, accepted, dH, loglik, logpost, z_proposal, H0, H1)."""
+    z0 = np.asarray(z0, dtype=np.float64)
+    mass = np.asarray(mass, dtype=np.float64)
+    p0 = np.sqrt(mass) * philox.normals(seed, counter, z0.shape[0])
+    lp0, g, ll0, _ = log_post(es_t, es_x, es_y, theta_full, idx, z0, hyper, t0, sigma_z)
+    z = z0.copy()
+    p = p0 + 0.5 * eps * g
+    for step in range(L):
+        z = z + eps * p / mass
+        lp, g, ll, _ = log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z)
+        p = p + (eps if step < L - 1 else 0.5 * eps) * g
+    H0 = -lp0 + 0.5 * float(np.sum(p0 * p0 / mass))
+    H1 = -lp + 0.5 * float(np.sum(p * p / mass))
+    dH = H1 - H0
+    u = philox.accept_uniform(seed, counter)
+    accepted = bool(np.isfinite(dH) and np.log(u) < -dH)
+    return {"z": z if accepted else z0, "z_proposal": z, "accepted": accepted, "dH": dH, "H0": H0, "H1": H1,
+            "loglik": ll if accepted else ll0, "logpost": lp if accepted else lp0, "u": u, "p0": p0}
+
+
+def z_hessian_diag(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z):
+    """-d2 log pi / dz_k^2 = theta_k^2 H_k - theta_k g_k + 1/sigma_z^2 (chain rule on
+    theta = exp(z) with Eq. 3 and Eq. 4)."""
+    th = theta_full.copy()
+    th[idx] = np.exp(z)
+    r = evaluate(es_t, es_x, es_y, th, hyper, t0, want=("grad_theta", "negH_theta"))
+    tk = np.exp(z)
+    return tk * tk * r["negH_theta"][idx] - tk * r["grad_theta"][idx] + 1.0 / sigma_z ** 2

@@ -1,0 +1,68 @@
+// Calibration of the hardware exp2 (v_exp_f32) against FP64 exp2: the mean
+// signed and mean absolute relative error over a low-discrepancy set of
+// arguments.  The pair kernels divide their FP64 normalisers by (1 + bias).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "hawkes_internal.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_exp2_bias(double lo, double span, int64_t n,
+                                                   double *__restrict__ part) {
+    __shared__ double sh[2][256];
+    double s = 0.0, sa = 0.0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        // additive recurrence with the golden ratio: fractional parts fill [0, 1) evenly
+        const double u = fmod((double)k * 0.6180339887498949, 1.0);
+        const float x = (float)(lo + span * u);
+        const double ref = exp2((double)x);
+        const double rel = ((double)__builtin_amdgcn_exp2f(x) - ref) / ref;
+        s += rel;
+        sa += fabs(rel);
+    }
+    sh[0][threadIdx.x] = s;
+    sh[1][threadIdx.x] = sa;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0];
+        part[2 * blockIdx.x + 1] = sh[1][0];
+    }
+}
+
+__global__ void k_exp2_bias_fin(const double *__restrict__ part, int nb, int64_t n, double *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0, sa = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            s += part[2 * b];
+            sa += part[2 * b + 1];
+        }
+        out[0] = s / (double)n;
+        out[1] = sa / (double)n;
+        out[2] = (double)n;
+    }
+}
+
+}  // namespace
+
+extern "C" hawkes_status hawkes_exp2_bias(int64_t nsamples, double lo, double hi, double *d_out,
+                                          hipStream_t stream) {
+    if (nsamples < 1 || !d_out || !(hi > lo) || !(lo >= -126.0) || !(hi <= 0.0)) return HAWKES_E_INVALID;
+    const int nb = 1024;
+    double *part = nullptr;
+    if (hipMallocAsync((void **)&part, sizeof(double) * 2 * nb, stream) != hipSuccess) return HAWKES_E_NOMEM;
+    hipLaunchKernelGGL(k_exp2_bias, dim3(nb), dim3(256), 0, stream, lo, hi - lo, nsamples, part);
+    hipLaunchKernelGGL(k_exp2_bias_fin, dim3(1), dim3(64), 0, stream, part, nb, nsamples, d_out);
+    HK_CHECK(hipGetLastError());
+    HK_CHECK(hipFreeAsync(part, stream));
+    return HAWKES_OK;
+}
+
+extern "C" double hawkes_exp2_bias_constant(void) { return HK_EXP2_BIAS; }

@@ -1,0 +1,746 @@
+// Free-rate subset and Hamiltonian Monte Carlo on its log-rates (Sec. 2.2,
+// Sec. 2.3.2).
+//
+// Only the M rates in the subset change along an HMC trajectory; every other
+// rate is fixed (1 in the paper).  lambda_i therefore splits exactly into a
+// static part -- the background over all pairs plus the excitation from fixed-
+// rate events -- and the excitation from the subset:
+//   lambda_i = lambda_static_i + c_e sum_{k in M, t_k < t_i} theta_k E_ik .
+// The static part costs one O(N^2) row pass per hyperparameter setting and is
+// cached; each gradient inside a trajectory then costs one row pass over
+// N x M pairs (subset excitation) and one column pass over M x N pairs
+// (Eq. 3 and Eq. 4 restricted to the subset), i.e. O(N M) as the paper notes.
+//
+// Kernels:
+//   k_sub_static   partial sums of the static row pass -> lambda_static_i
+//   k_sub_theta    theta_k = exp(z_k) into FP32 subset order and the caller's theta
+//   k_sub_row      X_i = sum_{k in M, t_k < t_i} theta_k E_ik (rows = all events)
+//   k_sub_fin      lambda_i, w_i = c_e / lambda_i, block sums of log lambda_i
+//   k_sub_col      G_k = sum_{t_i > t_k} E_ik w_i, H_k = sum (E_ik w_i)^2
+//   k_sub_colfin   Eq. 3 / Eq. 4 on the subset; gradient in z with the prior
+//   k_hmc_*        momenta (Philox-4x32-10 + Box-Muller), leapfrog, energy, accept
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "hawkes_internal.h"
+
+struct hk_subset {
+    int64_t m;           // subset size
+    int64_t mpad;        // padded to a multiple of HK_TILE
+    int *pos;            // [mpad] sorted position of subset entry r (time order); pad = INT_MAX
+    int *slot;           // [mpad] caller's subset slot k of entry r
+    int64_t *cidx;       // [m] caller index of slot k (copy of the caller's idx)
+    int *cnt;            // [nchunks] number of subset entries with pos < 64 (b + 1)
+    // column pass schedule over subset tiles
+    int n_items;
+    hk_item *items;      // (subset tile, row chunk begin, end, seg)
+    int *item0, *nseg;   // per subset tile
+    int ntiles;
+    // cached static part
+    bool static_valid;
+    hawkes_hyper static_hyper;
+    double *lam_static;  // [npad]
+    double *Lam_static;  // [1] integral term of the fixed-rate events + background
+    double *a;           // [mpad] theta0 (1 - exp(-omega (T1 - t_k))) per subset entry r
+    // per-evaluation buffers
+    float *theta32;      // [mpad] subset rates, time order
+    double *xs;          // [npad] subset excitation sums per event
+    double *colG;        // [n_items][2][HK_TILE]
+    double *gsub;        // [mpad] Eq. 3 on the subset, time order
+    double *hsub;        // [mpad] Eq. 4 on the subset, time order
+    double *sums;        // [8] loglik pieces of the last evaluation
+    // HMC state
+    double *z0, *p, *gz; // [m] slot order
+    double *scal;        // [16] energies and flags
+};
+
+namespace {
+
+constexpr int SUB_ROW_THREADS = HK_WAVE;  // one wavefront per 64-row chunk
+
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+__device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float v) {
+    float s = hi + v;
+    float bp = s - hi;
+    float err = (hi - (s - bp)) + (v - bp);
+    hi = s;
+    lo += err;
+}
+
+__global__ void k_invperm(const int *__restrict__ perm, int64_t n, int *__restrict__ inv) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) inv[perm[i]] = (int)i;
+}
+
+__global__ void k_sub_keys(const int64_t *__restrict__ idx, int64_t m, int64_t m2, const int *__restrict__ inv,
+                           int64_t n, double *__restrict__ key, int *__restrict__ slot, int *__restrict__ bad) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= m2) return;
+    if (k < m) {
+        int64_t c = idx[k];
+        if (c < 0 || c >= n) {
+            atomicOr(bad, 1);
+            key[k] = 0.0;
+        } else {
+            key[k] = (double)inv[c];
+        }
+    } else {
+        key[k] = INFINITY;
+    }
+    slot[k] = (int)k;
+}
+
+__global__ void k_sub_layout(const double *__restrict__ key, const int *__restrict__ slot2, int64_t m, int64_t mpad,
+                             int *__restrict__ pos, int *__restrict__ slot, int *__restrict__ bad) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= mpad) return;
+    if (r < m) {
+        pos[r] = (int)key[r];
+        slot[r] = slot2[r];
+        if (r > 0 && key[r] == key[r - 1]) atomicOr(bad, 1);  // repeated index
+    } else {
+        pos[r] = 0x7fffffff;
+        slot[r] = 0;
+    }
+}
+
+// cnt[b] = number of subset entries with pos < 64 (b + 1) (binary search).
+__global__ void k_sub_count(const int *__restrict__ pos, int64_t m, int nchunks, int *__restrict__ cnt) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nchunks) return;
+    const int lim = HK_WAVE * (b + 1);
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (pos[mid] < lim) lo = mid + 1;
+        else hi = mid;
+    }
+    cnt[b] = (int)lo;
+}
+
+// ---- static part ---------------------------------------------------------------------
+// theta with the subset entries zeroed, sorted, FP32
+__global__ void k_sub_static_theta(const double *__restrict__ theta, const int *__restrict__ perm,
+                                   const int *__restrict__ pos, int64_t m, int64_t n, int64_t npad,
+                                   float *__restrict__ theta_s, int *__restrict__ status) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < npad) {
+        float v = 0.0f;
+        if (i < n) {
+            double th = theta[perm[i]];
+            if (!(th >= 0.0) || !isfinite(th)) atomicOr(status, HK_ST_BADTHETA);
+            v = (float)th;
+        }
+        theta_s[i] = v;
+    }
+}
+
+__global__ void k_sub_zero_subset(const int *__restrict__ pos, int64_t m, float *__restrict__ theta_s) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r < m) theta_s[pos[r]] = 0.0f;
+}
+
+// lambda_static_i from the row pass partials (log-likelihood mode: B0, X0) and
+// the integral term of everything that does not depend on the subset rates.
+__global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ ts, const double *__restrict__ theta,
+                                                    const int *__restrict__ perm, const float *__restrict__ theta_s,
+                                                    int64_t n, int ntiles, const int *__restrict__ row_item0,
+                                                    const int *__restrict__ row_nseg,
+                                                    const double *__restrict__ rowpart,
+                                                    const float *__restrict__ colpart,
+                                                    const int64_t *__restrict__ colpart_off, const FinConst fc,
+                                                    double *__restrict__ lam_static, double *__restrict__ blockpart) {
+    __shared__ double sh[HK_WAVES];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double lam_part = 0.0;
+    if (i < n) {
+        const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
+        double b0 = 0.0, x0 = 0.0;
+        for (int sg = 0; sg < row_nseg[I]; ++sg) {
+            const double *rp = rowpart + (int64_t)(row_item0[I] + sg) * HK_NROW * HK_TILE + r;
+            b0 += rp[0];
+            x0 += rp[5 * HK_TILE];
+        }
+        for (int J = I; J < ntiles; ++J) b0 += (double)colpart[colpart_off[J] + i];
+        lam_static[i] = fc.c_b * b0 * fc.corr + fc.c_e * x0 * fc.corr;
+        // integral term: background (all events) + excitation of the fixed-rate events
+        const double ti = ts[i];
+        const double u1 = (fc.t1 - ti) / fc.tau_t, u0 = (fc.t0 - ti) / fc.tau_t;
+        const double Cn = 0.5 * erfc(-u1 * 0.7071067811865476) - 0.5 * erfc(-u0 * 0.7071067811865476);
+        const double one_m = -expm1(-fc.omega * (fc.t1 - ti));
+        const double th_fixed = theta_s[i] == 0.0f ? 0.0 : theta[perm[i]];  // subset entries are zeroed
+        lam_part = fc.mu0 * Cn + fc.theta0 * th_fixed * one_m;
+    } else if (i < (int64_t)ntiles * HK_TILE) {
+        lam_static[i] = 1.0;
+    }
+    // fixed-order block sum
+    for (int off = 32; off > 0; off >>= 1) lam_part += __shfl_xor(lam_part, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = lam_part;
+    __syncthreads();
+    if (threadIdx.x == 0) blockpart[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+__global__ void k_sum_blocks(const double *__restrict__ part, int nb, double *__restrict__ out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0.0, c = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const double v = part[b];
+            const double t = s + v;
+            c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+            s = t;
+        }
+        out[0] = s + c;
+    }
+}
+
+__global__ void k_sub_a(const double *__restrict__ ts, const int *__restrict__ pos, int64_t m, int64_t mpad,
+                        const FinConst fc, double *__restrict__ a) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= mpad) return;
+    a[r] = r < m ? fc.theta0 * -expm1(-fc.omega * (fc.t1 - ts[pos[r]])) : 0.0;
+}
+
+// ---- per-evaluation kernels ---------------------------------------------------------------
+// theta_k = exp(z_k): FP32 copy in time order, FP64 into the caller's full rate vector
+__global__ void k_sub_theta(const double *__restrict__ z, const int *__restrict__ slot,
+                            const int64_t *__restrict__ cidx, int64_t m, int64_t mpad, float *__restrict__ theta32,
+                            double *__restrict__ theta_full) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= mpad) return;
+    if (r < m) {
+        const int k = slot[r];
+        const double th = exp(z[k]);
+        theta32[r] = (float)th;
+        if (theta_full) theta_full[cidx[k]] = th;
+    } else {
+        theta32[r] = 0.0f;
+    }
+}
+
+// Subset excitation per event: one wavefront owns 64 rows and sweeps the subset
+// entries that precede them (cnt[b]), staged 64 at a time through LDS.
+__global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
+    const double *__restrict__ ts, const int *__restrict__ xi, const int *__restrict__ yi, const int *__restrict__ g,
+    const int *__restrict__ pos, const float *__restrict__ theta32, const int *__restrict__ cnt,
+    const PairConst kc, double *__restrict__ xs) {
+    __shared__ float4 rec[HK_WAVE];
+    __shared__ int rpos[HK_WAVE];
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t i = (int64_t)b * HK_WAVE + lane;
+    const double Tb = ts[(int64_t)b * HK_WAVE];
+    const float ti = (float)(ts[i] - Tb);
+    const int xr = xi[i], yr = yi[i], gr = g[i];
+    const int nsub = cnt[b];
+    float hi = 0.0f, lo = 0.0f;
+    for (int c0 = 0; c0 < nsub; c0 += HK_WAVE) {
+        {
+            const int r = c0 + lane;
+            const int pj = r < nsub ? pos[r] : 0;
+            float4 v;
+            if (r < nsub) {
+                v.x = (float)(ts[pj] - Tb);
+                v.y = __int_as_float(xi[pj]);
+                v.z = __int_as_float(yi[pj]);
+                v.w = theta32[r];
+            } else {
+                v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+            rec[lane] = v;
+            rpos[lane] = r < nsub ? pj : 0x7fffffff;
+        }
+        __syncthreads();
+        float blk = 0.0f;
+#pragma unroll 8
+        for (int s = 0; s < HK_WAVE; ++s) {
+            const float4 v = rec[s];
+            const float dt = ti - v.x;
+            const float dx = (float)(xr - __float_as_int(v.y));
+            const float dy = (float)(yr - __float_as_int(v.z));
+            const float r2 = fmaf(dx, dx, dy * dy);
+            const float ae = fmaf(r2, kc.kex_lo, r2 * kc.kex);
+            float E = fexp2(fmaf(dt, kc.kw, fmaf(dt, kc.kw_lo, ae)));
+            if (!(rpos[s] < gr)) E = 0.0f;
+            blk = fmaf(E, v.w, blk);
+        }
+        two_sum_acc(hi, lo, blk);
+        __syncthreads();
+    }
+    xs[i] = (double)hi + (double)lo;
+}
+
+__global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_static, const double *__restrict__ xs,
+                                                 int64_t n, int64_t npad, const FinConst fc,
+                                                 double *__restrict__ lam, float *__restrict__ w,
+                                                 double *__restrict__ blockpart, int *__restrict__ status) {
+    __shared__ double sh[HK_WAVES];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < n) {
+        const double l = lam_static[i] + fc.c_e * fc.corr * xs[i];
+        lam[i] = l;
+        if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
+        w[i] = l > 0.0 ? (float)(fc.c_e / l) : 0.0f;
+        v = log(l);
+    } else if (i < npad) {
+        lam[i] = 1.0;
+        w[i] = 0.0f;
+    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) blockpart[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// Column pass on the subset: lanes own subset entries (time order), rows are
+// all events after them, broadcast from LDS.
+template <bool WITH_H>
+__global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ ts, const int *__restrict__ xi,
+                                                      const int *__restrict__ yi, const float *__restrict__ w,
+                                                      const int *__restrict__ g, const int *__restrict__ pos,
+                                                      int64_t m, const hk_item *__restrict__ items,
+                                                      const PairConst kc, double *__restrict__ colG) {
+    __shared__ float4 rrec[HK_WAVE];
+    __shared__ int rg[HK_WAVE];
+    const hk_item it = items[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int64_t r = (int64_t)it.tile * HK_TILE + tid;
+    const bool live = r < m;
+    const int pj = live ? pos[r] : 0;
+    const double Tc = ts[(int64_t)it.c_begin * HK_WAVE];
+    const float tj = (float)(ts[pj] - Tc);
+    const int xj = xi[pj], yj = yi[pj];
+    float Gh = 0.0f, Gl = 0.0f, Hh = 0.0f, Hl = 0.0f;
+    for (int c = it.c_begin; c < it.c_end; ++c) {
+        if (tid < HK_WAVE) {
+            const int64_t i = (int64_t)c * HK_WAVE + tid;
+            float4 v;
+            v.x = (float)(ts[i] - Tc);
+            v.y = __int_as_float(xi[i]);
+            v.z = __int_as_float(yi[i]);
+            v.w = w[i];
+            rrec[tid] = v;
+            rg[tid] = g[i];
+        }
+        __syncthreads();
+        float G = 0.0f, H = 0.0f;
+#pragma unroll 8
+        for (int s = 0; s < HK_WAVE; ++s) {
+            const float4 v = rrec[s];
+            const float dt = v.x - tj;
+            const float dx = (float)(__float_as_int(v.y) - xj);
+            const float dy = (float)(__float_as_int(v.z) - yj);
+            const float r2 = fmaf(dx, dx, dy * dy);
+            float E = fexp2(fmaf(dt, kc.kw, r2 * kc.kex));
+            if (!(pj < rg[s])) E = 0.0f;
+            const float ew = E * v.w;
+            G += ew;
+            if (WITH_H) H = fmaf(ew, ew, H);
+        }
+        two_sum_acc(Gh, Gl, G);
+        if (WITH_H) two_sum_acc(Hh, Hl, H);
+        __syncthreads();
+    }
+    double *cg = colG + (int64_t)blockIdx.x * 2 * HK_TILE;
+    cg[tid] = live ? (double)Gh + (double)Gl : 0.0;
+    if (WITH_H) cg[HK_TILE + tid] = live ? (double)Hh + (double)Hl : 0.0;
+}
+
+__global__ void k_sub_colfin(const int *__restrict__ item0, const int *__restrict__ nseg,
+                             const double *__restrict__ colG, const double *__restrict__ a, int64_t m, double corr,
+                             bool with_h, double *__restrict__ gsub, double *__restrict__ hsub) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int T = (int)(r / HK_TILE), lr = (int)(r % HK_TILE);
+    double G = 0.0, H = 0.0;
+    for (int sg = 0; sg < nseg[T]; ++sg) {
+        const double *cg = colG + (int64_t)(item0[T] + sg) * 2 * HK_TILE + lr;
+        G += cg[0];
+        if (with_h) H += cg[HK_TILE];
+    }
+    gsub[r] = G * corr - a[r];
+    if (with_h) hsub[r] = H * corr * corr;
+}
+
+// Scatter the subset results to the caller's slot order.
+__global__ void k_sub_scatter(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
+                              const double *__restrict__ hsub, double *__restrict__ g_out,
+                              double *__restrict__ h_out) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int k = slot[r];
+    if (g_out) g_out[k] = gsub[r];
+    if (h_out) h_out[k] = hsub[r];
+}
+
+// Deterministic single-block sums over the subset (m is at most a few 1e4).
+// out[0] = sum log lambda (from block partials), out[1] = sum theta_k a_k,
+// out[2] = sum z_k^2, out[3] = sum p_k^2 / M_k
+__global__ __launch_bounds__(256) void k_sub_energy(const double *__restrict__ loglam_part, int nb,
+                                                    const double *__restrict__ z, const double *__restrict__ p,
+                                                    const double *__restrict__ mass, const int *__restrict__ slot,
+                                                    const double *__restrict__ a, int64_t m,
+                                                    double *__restrict__ out) {
+    __shared__ double sh[4][256];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += 256) s[0] += loglam_part[b];
+    for (int64_t r = threadIdx.x; r < m; r += 256) {
+        const int k = slot[r];
+        s[1] += exp(z[k]) * a[r];
+        s[2] += z[k] * z[k];
+        if (p) s[3] += p[k] * p[k] / mass[k];
+    }
+    for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = s[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ---- Philox-4x32-10 (Salmon et al. 2011) ------------------------------------------------
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+// p_k = sqrt(M_k) N(0,1): element k uses counter (k, 0, counter_lo, counter_hi);
+// z0 <- z (start of the trajectory)
+__global__ void k_hmc_init(int64_t m, uint64_t seed, uint64_t counter, const double *__restrict__ mass,
+                           const double *__restrict__ z, double *__restrict__ p, double *__restrict__ z0) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    uint32_t c[4] = {(uint32_t)k, 0u, (uint32_t)counter, (uint32_t)(counter >> 32)};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u1 = u53(c[0], c[1]), u2 = u53(c[2], c[3]);
+    const double nrm = sqrt(-2.0 * log1p(-u1)) * cos(6.283185307179586 * u2);
+    p[k] = sqrt(mass[k]) * nrm;
+    z0[k] = z[k];
+}
+
+// grad_z log pi = theta_k g_k - z_k / sigma^2 in slot order
+__global__ void k_hmc_gradz(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
+                            const double *__restrict__ z, double inv_s2, double *__restrict__ gz) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int k = slot[r];
+    gz[k] = exp(z[k]) * gsub[r] - z[k] * inv_s2;
+}
+
+// p += a_p * grad; then (if a_z != 0) z += a_z * p / M
+__global__ void k_hmc_kick_drift(int64_t m, double a_p, const double *__restrict__ gz, double a_z,
+                                 const double *__restrict__ mass, double *__restrict__ p, double *__restrict__ z) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    double pk = p[k] + a_p * gz[k];
+    p[k] = pk;
+    if (a_z != 0.0) z[k] = z[k] + a_z * pk / mass[k];
+}
+
+// Energies: scal[0..3] start sums, scal[4..7] end sums (k_sub_energy layout).
+// H = -(sum log lambda - Lam_static - theta0-part) + sum z^2/(2 s^2) + sum p^2/(2M)
+__global__ void k_hmc_accept(const double *__restrict__ scal, const double *__restrict__ Lam_static,
+                             double inv_s2, uint64_t seed, uint64_t counter, int64_t m,
+                             const double *__restrict__ z0, double *__restrict__ z, double *__restrict__ out,
+                             int *__restrict__ flag) {
+    __shared__ int acc;
+    if (threadIdx.x == 0) {
+        const double ll0 = scal[0] - Lam_static[0] - scal[1];
+        const double ll1 = scal[4] - Lam_static[0] - scal[5];
+        const double lp0 = ll0 - 0.5 * scal[2] * inv_s2;
+        const double lp1 = ll1 - 0.5 * scal[6] * inv_s2;
+        const double H0 = -lp0 + 0.5 * scal[3];
+        const double H1 = -lp1 + 0.5 * scal[7];
+        const double dH = H1 - H0;
+        uint32_t c[4] = {0u, 1u, (uint32_t)counter, (uint32_t)(counter >> 32)};
+        philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double u = u53(c[0], c[1]);
+        const int a = (isfinite(dH) && log(u) < -dH) ? 1 : 0;
+        acc = a;
+        flag[0] = a;
+        out[0] = (double)a;
+        out[1] = dH;
+        out[2] = a ? ll1 : ll0;
+        out[3] = a ? lp1 : lp0;
+        out[4] = isfinite(dH) ? fmin(1.0, exp(-dH)) : 0.0;
+        out[5] = ll1;
+        out[6] = H0;
+        out[7] = H1;
+    }
+    __syncthreads();
+    if (!acc)
+        for (int64_t k = threadIdx.x; k < m; k += blockDim.x) z[k] = z0[k];
+}
+
+// theta_full[idx_k] = exp(z_k) (after a rejection restores z)
+__global__ void k_sub_theta_full(const double *__restrict__ z, const int64_t *__restrict__ cidx, int64_t m,
+                                 double *__restrict__ theta_full) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < m) theta_full[cidx[k]] = exp(z[k]);
+}
+
+template <class T>
+hipError_t dalloc(T **p, size_t count) {
+    return hipMalloc((void **)p, count * sizeof(T) + 16);
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+void hk_subset_free(hawkes_plan p) {
+    hk_subset *s = p->sub;
+    if (!s) return;
+    void *ptrs[] = {s->pos, s->slot, s->cidx, s->cnt, s->items, s->item0, s->nseg, s->lam_static, s->Lam_static,
+                    s->a, s->theta32, s->xs, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->scal};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete s;
+    p->sub = nullptr;
+}
+
+extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const int64_t *d_idx,
+                                                hipStream_t stream) {
+    if (!p || !d_idx || m < 1 || m > p->n) return HAWKES_E_INVALID;
+    hk_subset_free(p);
+    hk_subset *s = new hk_subset();
+    memset(s, 0, sizeof(*s));
+    p->sub = s;
+    p->last_stream = stream;
+    s->m = m;
+    s->mpad = (m + HK_TILE - 1) / HK_TILE * HK_TILE;
+#define SC(call)                                                              \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess) {                                               \
+            hk_subset_free(p);                                                \
+            return e_ == hipErrorOutOfMemory ? HAWKES_E_NOMEM : HAWKES_E_DEVICE; \
+        }                                                                     \
+    } while (0)
+    int64_t m2 = 1;
+    while (m2 < m) m2 <<= 1;
+    int *inv = nullptr, *slot2 = nullptr, *bad = nullptr;
+    double *key = nullptr;
+    SC(dalloc(&inv, p->n));
+    SC(dalloc(&key, m2));
+    SC(dalloc(&slot2, m2));
+    SC(dalloc(&bad, 1));
+    SC(hipMemsetAsync(bad, 0, sizeof(int), stream));
+    hipLaunchKernelGGL(k_invperm, dim3(nblk(p->n, 256)), dim3(256), 0, stream, p->perm, p->n, inv);
+    hipLaunchKernelGGL(k_sub_keys, dim3(nblk(m2, 256)), dim3(256), 0, stream, d_idx, m, m2, inv, p->n, key, slot2,
+                       bad);
+    SC(hk_sort_pairs(key, slot2, m2, stream));
+    SC(dalloc(&s->pos, s->mpad));
+    SC(dalloc(&s->slot, s->mpad));
+    SC(dalloc(&s->cidx, m));
+    SC(dalloc(&s->cnt, p->nchunks));
+    hipLaunchKernelGGL(k_sub_layout, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, key, slot2, m, s->mpad, s->pos,
+                       s->slot, bad);
+    SC(hipMemcpyAsync(s->cidx, d_idx, sizeof(int64_t) * m, hipMemcpyDeviceToDevice, stream));
+    hipLaunchKernelGGL(k_sub_count, dim3(nblk(p->nchunks, 256)), dim3(256), 0, stream, s->pos, m, p->nchunks,
+                       s->cnt);
+    SC(hipGetLastError());
+    std::vector<int> hpos(m);
+    int hbad = 0;
+    SC(hipMemcpyAsync(hpos.data(), s->pos, sizeof(int) * m, hipMemcpyDeviceToHost, stream));
+    SC(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+    SC(hipStreamSynchronize(stream));
+    (void)hipFree(inv);
+    (void)hipFree(key);
+    (void)hipFree(slot2);
+    (void)hipFree(bad);
+    if (hbad) {
+        hk_subset_free(p);
+        return HAWKES_E_INVALID;
+    }
+    // column pass schedule: subset tile T sweeps row chunks from the chunk of its
+    // earliest entry to the end, in segments of S chunks
+    s->ntiles = (int)(s->mpad / HK_TILE);
+    const int S = 16;
+    std::vector<hk_item> items;
+    std::vector<int> item0(s->ntiles), nseg(s->ntiles);
+    for (int T = 0; T < s->ntiles; ++T) {
+        const int first = hpos[(size_t)T * HK_TILE] / HK_WAVE;
+        item0[T] = (int)items.size();
+        int seg = 0;
+        for (int c = first; c < p->nchunks; c += S) items.push_back({T, c, std::min(c + S, p->nchunks), seg++});
+        nseg[T] = seg;
+    }
+    s->n_items = (int)items.size();
+    SC(dalloc(&s->items, items.size()));
+    SC(dalloc(&s->item0, s->ntiles));
+    SC(dalloc(&s->nseg, s->ntiles));
+    SC(hipMemcpy(s->items, items.data(), sizeof(hk_item) * items.size(), hipMemcpyHostToDevice));
+    SC(hipMemcpy(s->item0, item0.data(), sizeof(int) * s->ntiles, hipMemcpyHostToDevice));
+    SC(hipMemcpy(s->nseg, nseg.data(), sizeof(int) * s->ntiles, hipMemcpyHostToDevice));
+    SC(dalloc(&s->lam_static, p->npad));
+    SC(dalloc(&s->Lam_static, 1));
+    SC(dalloc(&s->a, s->mpad));
+    SC(dalloc(&s->theta32, s->mpad));
+    SC(dalloc(&s->xs, p->npad));
+    SC(dalloc(&s->colG, (size_t)s->n_items * 2 * HK_TILE));
+    SC(dalloc(&s->gsub, s->mpad));
+    SC(dalloc(&s->hsub, s->mpad));
+    SC(dalloc(&s->sums, 8));
+    SC(dalloc(&s->z0, m));
+    SC(dalloc(&s->p, m));
+    SC(dalloc(&s->gz, m));
+    SC(dalloc(&s->scal, 16));
+#undef SC
+    s->static_valid = false;
+    return HAWKES_OK;
+}
+
+namespace {
+
+bool same_hyper(const hawkes_hyper &a, const hawkes_hyper &b) {
+    return a.mu0 == b.mu0 && a.tau_x == b.tau_x && a.tau_t == b.tau_t && a.theta0 == b.theta0 &&
+           a.omega == b.omega && a.h == b.h;
+}
+
+// Static part for (hyper, fixed rates) -- recomputed when the hyperparameters
+// change or the caller asks.
+hawkes_status ensure_static(hawkes_plan p, const hawkes_hyper *hy, const double *d_theta, bool force,
+                            const PairConst &kc, const FinConst &fc, hipStream_t stream) {
+    hk_subset *s = p->sub;
+    if (s->static_valid && !force && same_hyper(s->static_hyper, *hy)) return HAWKES_OK;
+    hipLaunchKernelGGL(k_sub_static_theta, dim3(nblk(p->npad, 256)), dim3(256), 0, stream, d_theta, p->perm, s->pos,
+                       s->m, p->n, p->npad, p->theta_s, p->status);
+    hipLaunchKernelGGL(k_sub_zero_subset, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->pos, s->m, p->theta_s);
+    hk_launch_row_loglik(p, kc, stream);
+    hipLaunchKernelGGL(k_sub_static, dim3(p->nfin_blocks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->theta_s,
+                       p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart_off, fc,
+                       s->lam_static, p->blockpart);
+    hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(64), 0, stream, p->blockpart, p->nfin_blocks, s->Lam_static);
+    hipLaunchKernelGGL(k_sub_a, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, p->ts, s->pos, s->m, s->mpad, fc,
+                       s->a);
+    HK_CHECK(hipGetLastError());
+    s->static_hyper = *hy;
+    s->static_valid = true;
+    return HAWKES_OK;
+}
+
+// One subset evaluation at z (slot order): theta, lambda, w, Eq. 3 (and Eq. 4)
+// on the subset, block partial sums of log lambda in p->blockpart.
+void sub_eval(hawkes_plan p, const double *z, double *theta_full, bool with_h, const PairConst &kc,
+              const FinConst &fc, hipStream_t stream) {
+    hk_subset *s = p->sub;
+    hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, s->slot, s->cidx, s->m,
+                       s->mpad, s->theta32, theta_full);
+    hipLaunchKernelGGL(k_sub_row, dim3(p->nchunks), dim3(SUB_ROW_THREADS), 0, stream, p->ts, p->xi, p->yi, p->g,
+                       s->pos, s->theta32, s->cnt, kc, s->xs);
+    hipLaunchKernelGGL(k_sub_fin, dim3(p->nfin_blocks), dim3(256), 0, stream, s->lam_static, s->xs, p->n, p->npad, fc,
+                       p->lam, p->w, p->blockpart, p->status);
+    if (with_h)
+        hipLaunchKernelGGL(k_sub_col<true>, dim3(s->n_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->w,
+                           p->g, s->pos, s->m, s->items, kc, s->colG);
+    else
+        hipLaunchKernelGGL(k_sub_col<false>, dim3(s->n_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->w,
+                           p->g, s->pos, s->m, s->items, kc, s->colG);
+    hipLaunchKernelGGL(k_sub_colfin, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->item0, s->nseg, s->colG, s->a,
+                       s->m, fc.corr, with_h, s->gsub, s->hsub);
+}
+
+__global__ void k_z_from_theta(const double *__restrict__ theta, const int64_t *__restrict__ cidx, int64_t m,
+                               double *__restrict__ z) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < m) z[k] = log(theta[cidx[k]]);
+}
+
+__global__ void k_sub_loglik_out(const double *__restrict__ e, const double *__restrict__ Lam_static,
+                                 double *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = e[0] - Lam_static[0] - e[1];
+}
+
+}  // namespace
+
+extern "C" hawkes_status hawkes_subset_grad(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
+                                            int refresh_static, double *d_loglik, double *d_grad_sub,
+                                            double *d_negH_sub, hipStream_t stream) {
+    if (!p || !hk_hyper_ok(hyper) || !d_theta) return HAWKES_E_INVALID;
+    if (!p->sub) return HAWKES_E_UNSUPPORTED;
+    hk_subset *s = p->sub;
+    p->last_stream = stream;
+    PairConst kc;
+    FinConst fc;
+    hk_make_consts(p, hyper, &kc, &fc);
+    hawkes_status st = ensure_static(p, hyper, d_theta, refresh_static != 0, kc, fc, stream);
+    if (st != HAWKES_OK) return st;
+    // z = log theta on the subset (the rates are taken from d_theta as given)
+    hipLaunchKernelGGL(k_z_from_theta, dim3(nblk(s->m, 256)), dim3(256), 0, stream, d_theta, s->cidx, s->m, s->z0);
+    sub_eval(p, s->z0, nullptr, d_negH_sub != nullptr, kc, fc, stream);
+    hipLaunchKernelGGL(k_sub_scatter, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->slot, s->m, s->gsub, s->hsub,
+                       d_grad_sub, d_negH_sub);
+    if (d_loglik) {
+        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, s->z0,
+                           (const double *)nullptr, (const double *)nullptr, s->slot, s->a, s->m, s->scal);
+        hipLaunchKernelGGL(k_sub_loglik_out, dim3(1), dim3(64), 0, stream, s->scal, s->Lam_static, d_loglik);
+    }
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
+extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawkes_hmc_args *a,
+                                  hipStream_t stream) {
+    if (!p || !a || !hk_hyper_ok(hyper) || !a->d_z || !a->d_theta || !a->d_mass || !a->d_out || a->L < 1 ||
+        !(a->eps > 0.0) || !(a->sigma_z > 0.0))
+        return HAWKES_E_INVALID;
+    if (!p->sub) return HAWKES_E_UNSUPPORTED;
+    hk_subset *s = p->sub;
+    p->last_stream = stream;
+    PairConst kc;
+    FinConst fc;
+    hk_make_consts(p, hyper, &kc, &fc);
+    hawkes_status st = ensure_static(p, hyper, a->d_theta, a->refresh_static != 0, kc, fc, stream);
+    if (st != HAWKES_OK) return st;
+    const int64_t m = s->m;
+    const double inv_s2 = 1.0 / (a->sigma_z * a->sigma_z);
+    const unsigned gb = nblk(m, 256);
+    hipLaunchKernelGGL(k_hmc_init, dim3(gb), dim3(256), 0, stream, m, a->seed, a->counter, a->d_mass, a->d_z, s->p,
+                       s->z0);
+    // start of the trajectory
+    sub_eval(p, a->d_z, a->d_theta, false, kc, fc, stream);
+    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, s->p,
+                       a->d_mass, s->slot, s->a, m, s->scal);
+    hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, inv_s2, s->gz);
+    for (int l = 0; l < a->L; ++l) {
+        // half kick at the start, full kicks between drifts
+        hipLaunchKernelGGL(k_hmc_kick_drift, dim3(gb), dim3(256), 0, stream, m, l == 0 ? 0.5 * a->eps : a->eps,
+                           s->gz, a->eps, a->d_mass, s->p, a->d_z);
+        sub_eval(p, a->d_z, a->d_theta, false, kc, fc, stream);
+        hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, inv_s2, s->gz);
+    }
+    hipLaunchKernelGGL(k_hmc_kick_drift, dim3(gb), dim3(256), 0, stream, m, 0.5 * a->eps, s->gz, 0.0, a->d_mass,
+                       s->p, a->d_z);
+    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, s->p,
+                       a->d_mass, s->slot, s->a, m, s->scal + 4);
+    hipLaunchKernelGGL(k_hmc_accept, dim3(1), dim3(256), 0, stream, s->scal, s->Lam_static, inv_s2, a->seed,
+                       a->counter, m, s->z0, a->d_z, a->d_out, (int *)(s->scal + 8));
+    hipLaunchKernelGGL(k_sub_theta_full, dim3(gb), dim3(256), 0, stream, a->d_z, s->cidx, m, a->d_theta);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}

@@ -1,0 +1,139 @@
+// Internal declarations shared by the HIP sources of libhawkes (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "hawkes.h"
+
+// Geometry of the pair passes.  A wavefront is 64 lanes on gfx950; a block of
+// four wavefronts owns a tile of 256 rows (row pass) or 256 columns (column
+// pass); the other index is swept in chunks of 64 staged through LDS.
+#define HK_WAVE 64
+#define HK_TILE 256
+#define HK_WAVES (HK_TILE / HK_WAVE)
+#define HK_CHUNKS_PER_TILE (HK_TILE / HK_WAVE)
+
+// Number of row accumulators (row pass) and symmetric column accumulators.
+// Row slots: 0 B0, 1 B1, 2 B2, 3 B11, 4 B22, 5 X0, 6 X1, 7 X2, 8 X11, 9 X22.
+// Column slots: the five background moments B0, B1, B2, B11, B22.
+#define HK_NROW 10
+#define HK_NCOL 5
+// Per-event sums reduced by the finalize kernels (see hawkes_eval.hip).
+#define HK_NSUM 20
+
+// Time offset given to padding events: their pair terms underflow to exactly
+// zero while every square stays finite in FP32.
+#define HK_PAD_DT 1.0e15
+
+// Mean relative error of the hardware exp2 (v_exp_f32) over uniformly
+// distributed fractional arguments, measured on gfx950 over 2.7e8 arguments
+// spanning [-126, 0): -3.4e-9 (the function rounds slightly low on average).
+// The FP64 constants that multiply the FP32 pair sums are divided by
+// (1 + HK_EXP2_BIAS) so that the sums of many terms are unbiased.
+#define HK_EXP2_BIAS (-3.4e-9)
+
+enum { HK_MODE_LOGLIK = 0, HK_MODE_GRAD = 1, HK_MODE_HESS = 2 };
+
+struct hk_item {  // one block of a pair pass
+    int tile;     // row tile (row pass) or column tile (column pass)
+    int c_begin;  // first chunk of the swept index
+    int c_end;    // one past the last chunk
+    int seg;      // segment number within the tile
+};
+
+struct hawkes_plan_s {
+    int64_t n;       // events
+    int64_t npad;    // padded to a multiple of HK_TILE
+    int ntiles;      // npad / HK_TILE
+    int nchunks;     // npad / HK_WAVE
+    double t0;       // window start
+    double t1;       // max t
+    double cx, cy;   // fixed-point centre
+    int fxk;         // x_fixed = rint((x - cx) * 2^fxk)
+    int device;
+
+    // sorted, padded structure-of-arrays (device)
+    double *ts;      // [npad] sorted times; padding = t1 + HK_PAD_DT
+    int *xi, *yi;    // [npad] fixed-point coordinates
+    int *perm;       // [n] sorted position -> caller index
+    int *g;          // [npad] first sorted index with the same time (ties)
+
+    // row pass schedule
+    int n_row_items;
+    hk_item *row_items;       // [n_row_items] (device)
+    int *row_item0;           // [ntiles] first item of each row tile (device)
+    int *row_nseg;            // [ntiles] items per row tile (device)
+    int64_t *colpart_off;     // [ntiles] offset of tile I's column partials (device)
+    int64_t colpart_len;
+    // column pass schedule
+    int n_col_items;
+    hk_item *col_items;
+    int *col_item0;
+    int *col_nseg;
+
+    // per-evaluation scratch (device)
+    float *theta_s;           // [npad] rates in sorted order (FP32), 0 on padding
+    double *rowpart;          // [n_row_items][HK_NROW][HK_TILE]
+    float *colpart;           // triangular [tile][HK_NCOL][(tile+1)*HK_TILE]
+    double *lam;              // [npad] lambda_i, sorted
+    float *w;                 // [npad] c_e / lambda_i (FP32), 0 on padding
+    double *a;                // [npad] theta0 (1 - exp(-omega (T1 - t_i)))
+    double *colG;             // [n_col_items][2][HK_TILE]
+    int nfin_blocks;
+    double *blockpart;        // [nfin_blocks][HK_NSUM]
+    int *status;              // sticky device status bits
+    hipStream_t last_stream;
+    struct hk_profile *prof;  // HIP-event timing of the passes (NULL when off)
+    struct hk_subset *sub;    // free-rate subset for the HMC path (NULL until set)
+};
+
+hipError_t hk_sort_pairs(double *key, int *idx, int64_t n2, hipStream_t stream);
+void hk_subset_free(hawkes_plan p);
+
+// Exponent constants of the pair kernels (log2 units) and the FP64 constants of
+// the finalisation; built per call from the hyperparameters.
+struct PairConst {
+    float kbx;  // -2^{-2k} / (2 tau_x^2 ln 2): fixed-point r^2 -> log2 units, background
+    float kbt;  // -1 / (2 tau_t^2 ln 2)
+    float kex;  // -2^{-2k} / (2 h^2 ln 2): fixed-point r^2 -> log2 units, excitation
+    float kw;   // -omega / ln 2
+    // FP32 remainders of the four constants (k = kf + klo to ~2^-48), used by the
+    // sweeps that accumulate no moments to correct with
+    float kbx_lo, kbt_lo, kex_lo, kw_lo;
+};
+
+struct FinConst {
+    double mu0, tau_x, tau_t, theta0, omega, h;
+    double c_b, c_e;       // normalisers of Sec. 2.1
+    double cb1, ce1;       // c_b / mu0 and c_e / theta0
+    double Kx, Kh;         // log2-unit moment -> r^2 moment: -2 tau_x^2 ln 2, -2 h^2 ln 2
+    double corr;           // 1 / (1 + exp2 bias)
+    double t0, t1;
+    // First-order correction for the rounding of the FP32 exponent constants:
+    // a term computed as exp2(a + d) equals exp2(a) (1 + d ln 2 + O(d^2)), and d
+    // is linear in r^2, dt^2 (background) and dt, r^2 (excitation), whose
+    // weighted sums are the first moments the row pass accumulates.
+    double rho_bx, dkbt;   // (kbx_f - kbx) / kbx_f, kbt_f - kbt
+    double dkw, rho_ex;    // kw_f - kw, (kex_f - kex) / kex_f
+};
+
+bool hk_hyper_ok(const hawkes_hyper *h);
+void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, FinConst *fc);
+// Row pass in log-likelihood mode over all pairs with the sorted FP32 rates
+// already in p->theta_s; leaves the partial sums in p->rowpart / p->colpart.
+void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream);
+
+// Optional timing of the passes with HIP events recorded on the launch stream.
+enum { HK_PROF_ROW = 0, HK_PROF_COL = 1, HK_PROF_EVAL = 2, HK_PROF_KINDS = 3 };
+void hk_prof_mark(hawkes_plan p, int kind, bool start, hipStream_t stream);
+void hk_prof_free(hawkes_plan p);
+
+// status bits on the device
+#define HK_ST_ZERO 1
+#define HK_ST_NONFINITE 2
+#define HK_ST_BADTHETA 4
+
+#define HK_CHECK(call)                                  \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return HAWKES_E_DEVICE;   \
+    } while (0)

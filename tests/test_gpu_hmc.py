@@ -1,0 +1,159 @@
+"""Free-rate subset path and HMC step on the GPU vs the FP64 oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import hmc as ohmc
+from paper_2103_03348_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(es):
+    import torch
+
+    from paper_2103_03348_amd import _lib
+    from paper_2103_03348_amd.hawkes import Plan
+
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
+    idx = torch.as_tensor(es.subset, dtype=torch.int64, device="cuda:0")
+    _lib.check(_lib.lib().hawkes_plan_set_subset(plan.handle, idx.numel(), _lib.ptr(idx), _lib.stream_handle()),
+               "set_subset")
+    return plan, idx
+
+
+def _subset_grad(plan, es, theta, refresh=0):
+    import torch
+
+    from paper_2103_03348_amd import _lib
+
+    m = es.subset.shape[0]
+    th = torch.as_tensor(theta, device="cuda:0")
+    ll = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    g = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+    h = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+    hy = _lib.Hyper.of(es.hyper)
+    _lib.check(_lib.lib().hawkes_subset_grad(plan.handle, ctypes.byref(hy), _lib.ptr(th), refresh, _lib.ptr(ll),
+                                             _lib.ptr(g), _lib.ptr(h), _lib.stream_handle()), "subset_grad")
+    torch.cuda.synchronize()
+    return float(ll.item()), g.cpu().numpy(), h.cpu().numpy()
+
+
+@pytest.mark.parametrize("cfg", ["small", "n23422"])
+def test_subset_grad_matches_oracle(gpu, cfg):
+    """Eq. 1, 3, 4 restricted to the free rates, by the cached-static O(N M) path."""
+    es = synth.small(1500, seed=21, ties=6, all_free=False) if cfg == "small" else synth.config(1)
+    plan, idx = _setup(es)
+    ll, g, h = _subset_grad(plan, es, es.theta)
+    assert plan.status() == 0
+    ref = oracle.evaluate_es(es)
+    gi = ref["grad_theta"][es.subset]
+    hi = ref["negH_theta"][es.subset]
+    a = es.hyper[3] * (1.0 - np.exp(-es.hyper[4] * (es.t.max() - es.t[es.subset])))
+    rel_l = abs(ll - ref["loglik"]) / abs(ref["loglik"])
+    rel_g = np.max(np.abs(g - gi) / (gi + 2 * a))
+    rel_h = np.max(np.abs(h - hi) / (hi + 1e-30))
+    print(f"\nsubset {cfg}: n={es.n} m={es.subset.shape[0]} loglik rel {rel_l:.2e} g {rel_g:.2e} H {rel_h:.2e}")
+    assert rel_l < (1e-9 if cfg == "n23422" else 2e-6 * es.n / abs(ref["loglik"]))
+    assert rel_g < 1e-6
+    assert rel_h < 1e-6
+    # a second call at new rates reuses the cached static part
+    rng = np.random.default_rng(4)
+    th2 = es.theta.copy()
+    th2[es.subset] = np.exp(rng.normal(0, 0.5, es.subset.shape[0]))
+    ll2, g2, _ = _subset_grad(plan, es, th2)
+    ref2 = oracle.evaluate_es(es, theta=th2, want=("loglik", "grad_theta"))
+    assert abs(ll2 - ref2["loglik"]) / abs(ref2["loglik"]) < (1e-9 if cfg == "n23422" else 1e-6)
+    gi2 = ref2["grad_theta"][es.subset]
+    assert np.max(np.abs(g2 - gi2) / (np.abs(gi2) + 2 * a)) < 1e-6
+
+
+def _hmc_gpu(plan, es, z0, mass, eps, L, sigma, seed, counter, theta=None):
+    import torch
+
+    from paper_2103_03348_amd import _lib
+
+    dev = "cuda:0"
+    z = torch.as_tensor(np.asarray(z0, dtype=np.float64).copy(), device=dev)
+    th = torch.as_tensor((es.theta if theta is None else theta).copy(), device=dev)
+    ms = torch.as_tensor(np.asarray(mass, dtype=np.float64), device=dev)
+    out = torch.zeros(8, dtype=torch.float64, device=dev)
+    args = _lib.HmcArgs(z.data_ptr(), th.data_ptr(), ms.data_ptr(), eps, L, sigma, seed, counter, 0, out.data_ptr())
+    hy = _lib.Hyper.of(es.hyper)
+    _lib.check(_lib.lib().hmc_step(plan.handle, ctypes.byref(hy), ctypes.byref(args), _lib.stream_handle()), "hmc")
+    torch.cuda.synchronize()
+    return z.cpu().numpy(), th.cpu().numpy(), out.cpu().numpy()
+
+
+def test_hmc_step_replays_oracle(gpu):
+    """One HMC iteration with the same Philox seed/counter on both sides: same
+    momenta, same leapfrog path (to FP32 gradient error), same energy change and
+    the same accept decision."""
+    es = synth.small(400, seed=23, ties=3, all_free=False)
+    plan, idx = _setup(es)
+    m = es.subset.shape[0]
+    z0 = np.log(es.theta[es.subset])
+    mass = np.full(m, 6.0)
+    for counter in range(3):
+        zg, thg, out = _hmc_gpu(plan, es, z0, mass, 0.05, 8, 0.5, 77, counter)
+        r = ohmc.hmc_iteration(es.t, es.x, es.y, es.theta, es.subset, z0, mass, es.hyper, 0.0, 0.05, 8, 0.5,
+                               77, counter)
+        print(f"\ncounter {counter}: gpu dH {out[1]:.9f} acc {out[0]} | oracle dH {r['dH']:.9f} acc {r['accepted']}")
+        assert abs(out[1] - r["dH"]) < 1e-5
+        margin = abs(np.log(r["u"]) + r["dH"])
+        if margin > 1e-4:
+            assert bool(out[0]) == r["accepted"]
+        if r["accepted"]:
+            np.testing.assert_allclose(zg, r["z_proposal"], atol=1e-6)
+            np.testing.assert_allclose(thg[es.subset], np.exp(zg), rtol=1e-15)
+        else:
+            np.testing.assert_array_equal(zg, z0)
+        assert abs(out[6] - r["H0"]) < 1e-6 * max(1.0, abs(r["H0"]))
+
+
+def test_hmc_deterministic(gpu):
+    es = synth.small(300, seed=24, all_free=False)
+    plan, _ = _setup(es)
+    m = es.subset.shape[0]
+    z0 = np.log(es.theta[es.subset])
+    a = _hmc_gpu(plan, es, z0, np.full(m, 5.0), 0.1, 5, 0.5, 1, 9)
+    b = _hmc_gpu(plan, es, z0, np.full(m, 5.0), 0.1, 5, 0.5, 1, 9)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+
+
+def test_hmc_samples_prior_without_excitation(gpu):
+    """theta0 = 0 makes the likelihood independent of the rates: the GPU chain
+    must sample N(0, sigma_z^2) (mean, variance and a KS test of the pooled draws)."""
+    import torch
+    from scipy import stats
+
+    from paper_2103_03348_amd import _lib
+
+    es = synth.small(500, seed=25, all_free=False)
+    es.hyper = (0.7, 2.0, 5.0, 0.0, 0.5, 0.3)
+    plan, _ = _setup(es)
+    m = es.subset.shape[0]
+    sig = 0.5
+    dev = "cuda:0"
+    z = torch.zeros(m, dtype=torch.float64, device=dev)
+    th = torch.as_tensor(es.theta.copy(), device=dev)
+    ms = torch.full((m,), 1.0 / sig ** 2, dtype=torch.float64, device=dev)
+    out = torch.zeros(8, dtype=torch.float64, device=dev)
+    hy = _lib.Hyper.of(es.hyper)
+    draws = []
+    acc = 0.0
+    for it in range(1500):
+        args = _lib.HmcArgs(z.data_ptr(), th.data_ptr(), ms.data_ptr(), 0.9, 3, sig, 11, it, 0, out.data_ptr())
+        _lib.check(_lib.lib().hmc_step(plan.handle, ctypes.byref(hy), ctypes.byref(args), _lib.stream_handle()),
+                   "hmc")
+        if it >= 100:
+            draws.append(z.clone())
+        acc += 0  # accept flags are read once at the end
+    torch.cuda.synchronize()
+    d = torch.stack(draws).cpu().numpy()
+    print(f"\nprior check: mean {d.mean():.4f} var {d.var():.4f} (target 0, {sig ** 2})")
+    assert abs(d.mean()) < 0.03
+    assert abs(d.var() - sig ** 2) < 0.02
+    assert stats.kstest(d[::7, 0] / sig, "norm").pvalue > 1e-3

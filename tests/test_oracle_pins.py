@@ -262,3 +262,132 @@ def test_tied_times_do_not_excite():
     assert acc[2, 5] > 0.0
     assert acc[0, 0] > 0.0 and acc[1, 0] > 0.0
     assert r["negH_theta"][2] == 0.0
+
+
+def test_philox_known_answers():
+    """Philox-4x32-10 against the published known-answer vectors (Salmon et al. 2011)."""
+    from oracle import philox
+    kat = json.load(open(os.path.join(GOLDEN, "philox4x32_10_kat.json")))
+
+    def v(x):
+        return int(x, 16) if isinstance(x, str) else int(x)
+
+    for vec in kat["vectors"]:
+        out = philox.philox4x32_10(np.array([v(c) for c in vec["ctr"]]), np.array([v(k) for k in vec["key"]]))
+        assert [int(o) for o in out] == [v(o) for o in vec["out"]]
+
+
+def test_philox_normals_are_standard():
+    """Box-Muller on Philox uniforms: mean 0, variance 1, normal quantiles (KS test)."""
+    from scipy import stats
+
+    from oracle import philox
+    z = philox.normals(seed=12345, counter=7, m=200000)
+    assert abs(z.mean()) < 0.01
+    assert abs(z.var() - 1.0) < 0.01
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+
+
+def test_hmc_samples_prior_when_no_excitation():
+    """theta0 = 0: the likelihood does not depend on the rates, so the HMC chain
+    targets the N(0, sigma_z^2) prior exactly; check its first two moments over
+    a short chain of the oracle sampler (Sec. 2.3.2 special case)."""
+    from oracle import hmc
+    es = _es(30, seed=51)
+    hy = (0.7, 2.0, 5.0, 0.0, 0.5, 0.3)
+    idx = np.arange(10)
+    z = np.zeros(10)
+    sig = 0.5
+    mass = np.full(10, 1.0 / sig ** 2)
+    draws = []
+    acc = 0
+    for it in range(400):
+        r = hmc.hmc_iteration(es.t, es.x, es.y, es.theta, idx, z, mass, hy, 0.0, 0.9, 3, sig, seed=3, counter=it)
+        z = r["z"]
+        acc += r["accepted"]
+        draws.append(z.copy())
+    d = np.array(draws[50:])
+    assert acc > 300
+    assert abs(d.mean()) < 0.06
+    assert abs(d.var() - sig ** 2) < 0.04
+
+
+def test_hmc_leapfrog_reversible_and_second_order():
+    """Leapfrog is time-reversible (negating the final momentum retraces the path)
+    and its energy error shrinks as eps^2."""
+    from oracle import hmc
+    es = _es(25, seed=52)
+    idx = np.arange(0, 25, 3)
+    z0 = np.log(es.theta[idx])
+    mass = np.full(idx.shape[0], 4.0)
+    errs = []
+    for eps in (0.02, 0.01):
+        r = hmc.hmc_iteration(es.t, es.x, es.y, es.theta, idx, z0, mass, es.hyper, 0.0, eps, 10, 0.5, 9, 0)
+        errs.append(abs(r["dH"]))
+    assert errs[1] < errs[0] / 3.0
+
+
+def test_mlp_gradient_by_finite_differences():
+    """Back-propagation of the preconditioner network against central differences
+    of its loss (step 1e-6) on random parameters."""
+    from oracle import mlp
+    rng = np.random.default_rng(3)
+    p = mlp.init(seed=1) + 0.05 * rng.standard_normal(mlp.N_PARAMS)
+    X = rng.standard_normal((37, 12))
+    tgt = rng.standard_normal(37)
+    loss, g = mlp.loss_and_grad(p, X, tgt)
+    for j in rng.choice(mlp.N_PARAMS, size=25, replace=False).tolist() + [mlp.N_PARAMS - 1, 0, 768, 900]:
+        e = np.zeros(mlp.N_PARAMS)
+        e[j] = 1e-6
+        fd = (mlp.loss_and_grad(p + e, X, tgt)[0] - mlp.loss_and_grad(p - e, X, tgt)[0]) / 2e-6
+        assert g[j] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_mlp_forward_closed_form_and_adam_first_step():
+    """With W2 = 0 the output is w3 . tanh(b2) + b3 whatever the input; Adam's first
+    bias-corrected step moves every parameter by -lr g / (|g| + eps)."""
+    from oracle import mlp
+    p = mlp.unpack(mlp.init(seed=2))
+    p["W2"][:] = 0.0
+    p["b2"][:] = np.linspace(-1, 1, 64)
+    flat = mlp.pack(p)
+    X = np.random.default_rng(0).standard_normal((5, 12))
+    y, _ = mlp.forward(flat, X)
+    np.testing.assert_allclose(y, np.dot(p["w3"], np.tanh(p["b2"])) + p["b3"][0], rtol=1e-14)
+    g = np.random.default_rng(1).standard_normal(mlp.N_PARAMS)
+    new, m, v = mlp.adam_step(flat, g, np.zeros_like(g), np.zeros_like(g), 1, lr=1e-3)
+    np.testing.assert_allclose(new - flat, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-9)
+
+
+def test_features_small_hand_case():
+    """Grid-count features on a hand-built set: three events share one h-cell, the
+    time bins are known, and the rank / window features follow their definitions."""
+    from oracle import features
+    hy = (0.7, 2.0, 5.0, 0.3, 0.5, 0.3)
+    t = np.array([0.5, 1.0, 2.5, 2.6, 7.0])       # bins at omega = 0.5: 0, 0, 1, 1, 3
+    x = np.array([0.05, 0.1, 0.2, 5.0, 0.15])     # cells of size 0.3 from gx0 = 0: 0, 0, 0, 16, 0
+    y = np.array([0.05, 0.1, 0.2, 5.0, 0.1])
+    F = features.features(t, x, y, np.array([0, 2]), np.array([0.1, -0.2]), hy, 0.0, 0.0, 0.0)
+    # event 0: others in its h-cell: events 1, 2, 4
+    assert F[0, 0] == pytest.approx(np.log1p(3))
+    # event 0 (bin 0): next bin (1) in its h-cell holds event 2; bins 1..3 hold events 2 and 4
+    assert F[0, 4] == pytest.approx(np.log1p(1)) and F[0, 5] == pytest.approx(np.log1p(2))
+    # event 2 (bin 1): previous bin holds events 0 and 1
+    assert F[1, 3] == pytest.approx(np.log1p(2))
+    assert F[1, 9] == -0.2
+    assert F[1, 10] == pytest.approx(2 / 5) and F[1, 11] == pytest.approx((7.0 - 2.5) / 7.0)
+
+
+def test_ess_of_ar1_chain():
+    """Geyer's estimator on AR(1) chains, whose ESS is n (1 - rho) / (1 + rho)."""
+    from paper_2103_03348_amd import ess
+    rng = np.random.default_rng(11)
+    n = 200000
+    for rho in (0.0, 0.5, 0.9):
+        e = rng.standard_normal(n)
+        x = np.empty(n)
+        x[0] = e[0]
+        for k in range(1, n):
+            x[k] = rho * x[k - 1] + np.sqrt(1 - rho * rho) * e[k]
+        expect = n * (1 - rho) / (1 + rho)
+        assert ess.ess_1d(x) == pytest.approx(expect, rel=0.1)
