@@ -175,6 +175,57 @@ typedef struct {
 
 hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawkes_hmc_args *args, hipStream_t stream);
 
+/* ---- Learned preconditioner (a small network predicting Eq. 4) ----
+ *
+ * Network 12 -> 64 -> 64 -> 1, tanh hidden layers, FP32.  Parameter vector
+ * (hawkes_mlp_num_params() = 5057 floats, device): W1 [64][12], b1 [64],
+ * W2 [64][64], b2 [64], w3 [64], b3 [1]; y = w3 . tanh(W2 tanh(W1 x + b1) + b2) + b3.
+ * Inputs X are [rows][12] FP32, row-major. */
+int64_t hawkes_mlp_num_params(void);
+/* Floats of device workspace that hawkes_mlp_grad / hawkes_mlp_train_step need for batch B. */
+int64_t hawkes_mlp_workspace_floats(int64_t B);
+/* y[s] = network(X[s]) for s < B. */
+hawkes_status hawkes_mlp_forward(const float *d_params, const float *d_x, int64_t B, float *d_y, hipStream_t stream);
+/* Loss L = mean_s (network(X[rows[s]]) - target[rows[s]])^2 over a batch of B rows
+ * of the n_rows-row arrays d_x [n_rows][12] and d_target [n_rows] (d_rows: device
+ * int [B], or NULL for rows 0..B-1, which needs B <= n_rows) and its gradient by
+ * back-propagation, summed over the batch in fixed order in FP64:
+ * d_grad [5057] FP64, d_loss [1] FP64 (may be NULL).  A row index outside
+ * [0, n_rows) is never read: that sample is dropped and *d_err |= 1 (d_err: device
+ * int, may be NULL). */
+hawkes_status hawkes_mlp_grad(const float *d_params, const float *d_x, int64_t n_rows, const int *d_rows,
+                              const float *d_target, int64_t B, float *d_work, double *d_grad, double *d_loss,
+                              int *d_err, hipStream_t stream);
+/* hawkes_mlp_grad followed by one Adam update (Kingma & Ba 2015; beta1 0.9,
+ * beta2 0.999, epsilon 1e-8, bias-corrected, step >= 1) of d_params in place;
+ * d_adam_m, d_adam_v [5057] FP32 moment buffers (zero before step 1). */
+hawkes_status hawkes_mlp_train_step(float *d_params, float *d_adam_m, float *d_adam_v, int step, float lr,
+                                    const float *d_x, int64_t n_rows, const int *d_rows, const float *d_target,
+                                    int64_t B, float *d_work, double *d_grad, double *d_loss, int *d_err,
+                                    hipStream_t stream);
+
+/* Per-event network inputs for the subset (slot order), d_feat [m][12] FP32.
+ * With cell(e; s) = floor((x_e - gx0)/s), floor((y_e - gy0)/s) and time bin
+ * floor((t_e - T0) omega):
+ *   0..2  log1p(#other events in the event's cell), s = h, 3h, tau_x
+ *   3..5  s = h: log1p(#events in the cell in the previous bin, the next bin,
+ *         the next three bins)
+ *   6..8  the same for s = 3h
+ *   9     z_k;  10  #{e : t_e < t_k} / N;  11  (T1 - t_k) / (T1 - T0)
+ * d_t, d_xy are the arrays the plan was built from; (gx0, gy0) <= the minimum
+ * coordinates.  Counting uses grids sized from the plan's bounding box;
+ * HAWKES_E_UNSUPPORTED if a grid would exceed 2^26 (space) or 2^28 (space-time) cells. */
+hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hyper, const double *d_t, const double *d_xy,
+                              const double *d_z, double gx0, double gy0, float *d_feat, hipStream_t stream);
+
+/* Running average of the diagonal mass: d_mass[k] <- (count d_mass[k] + c_k)/(count + 1)
+ * with c_k the z-space curvature estimate at the rates d_theta:
+ *   d_pred == NULL: exact, max(theta^2 H - theta g, 0) + 1/sigma_z^2 (Eq. 3, Eq. 4, subset path);
+ *   d_pred != NULL: learned, theta^2 exp(d_pred[k]) + 1/sigma_z^2 (d_pred [m] FP32, slot order). */
+hawkes_status hawkes_mass_update(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
+                                 const float *d_pred, double sigma_z, int64_t count, double *d_mass,
+                                 hipStream_t stream);
+
 /* Timing of the pair passes with HIP events recorded on the launch stream.
  * hawkes_profile_enable(p, 1) starts recording around every row pass, column
  * pass and whole evaluation of plan p; 0 stops and discards.

@@ -74,6 +74,14 @@ SIGNATURES = {
     "hawkes_plan_set_subset": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
     "hawkes_subset_grad": (ctypes.c_int, [_vp, _HyP, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "hmc_step": (ctypes.c_int, [_vp, _HyP, ctypes.POINTER(HmcArgs), _vp]),
+    "hawkes_mlp_num_params": (_i64, []),
+    "hawkes_mlp_workspace_floats": (_i64, [_i64]),
+    "hawkes_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    "hawkes_mlp_grad": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "hawkes_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _i64, _vp, _vp,
+                                             _i64, _vp, _vp, _vp, _vp, _vp]),
+    "hawkes_features": (ctypes.c_int, [_vp, _HyP, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
+    "hawkes_mass_update": (ctypes.c_int, [_vp, _HyP, _vp, _vp, ctypes.c_double, _i64, _vp, _vp]),
     "hawkes_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hawkes_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "hawkes_exp2_bias": (ctypes.c_int, [_i64, ctypes.c_double, ctypes.c_double, _vp, _vp]),

@@ -75,6 +75,12 @@ __device__ __forceinline__ float rot_next(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xf, 0xf, true));
 }
 
+__device__ __forceinline__ double rot_next_d(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x134, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x134, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Knuth's TwoSum: (hi, lo) += v with the rounding error of the high add kept.
@@ -103,10 +109,17 @@ __global__ void k_gather(const double *__restrict__ theta, const int *__restrict
 // ------------------------------------------------------------------------------------
 // One sweep of a 64-column chunk by one wavefront: 64 steps, each lane pairing
 // its row with column (lane + s) mod 64 of the chunk.
+//
+// The three sums lambda_i is built from (background row sum B0, background
+// column sum, excitation X0) accumulate every term in FP64: a plain FP32 sum of
+// positive terms rounds away every term below half an ulp of the running sum,
+// which biases lambda low (by ~2e-8 relative on clustered data).  The moments
+// used only by derivatives stay in FP32 blocks.
 template <int MODE, bool MASK_BG, bool MASK_EX>
 __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, int lane, float ti, int xr, int yr,
                                           int irow, int gr, int cbase, const PairConst kc,
-                                          float (&blk)[HK_NROW], float (&C)[HK_NCOL]) {
+                                          float (&blk)[HK_NROW], float (&C)[HK_NCOL], double &B0d, double &X0d,
+                                          double &C0d) {
     // explicit FMAs only: a contracted (rotated + product) cannot take the DPP
     // operand, while a plain add of the shared product can
 #pragma clang fp contract(off)
@@ -118,26 +131,18 @@ __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, int la
         const float dy = (float)(yr - __float_as_int(r.z));
         const float r2 = fmaf(dx, dx, dy * dy);
         const float dt2 = dt * dt;
-        float ar, ae, b, E;
-        if (MODE == HK_MODE_LOGLIK) {
-            ar = fmaf(r2, kc.kbx_lo, r2 * kc.kbx);
-            b = fexp2(fmaf(dt2, kc.kbt, fmaf(dt2, kc.kbt_lo, ar)));
-            ae = fmaf(r2, kc.kex_lo, r2 * kc.kex);
-            E = fexp2(fmaf(dt, kc.kw, fmaf(dt, kc.kw_lo, ae)));
-        } else {
-            ar = r2 * kc.kbx;
-            b = fexp2(fmaf(dt2, kc.kbt, ar));
-            ae = r2 * kc.kex;
-            E = fexp2(fmaf(dt, kc.kw, ae));
-        }
+        const float ar = r2 * kc.kbx;
+        float b = fexp2(fmaf(dt2, kc.kbt, ar));
+        const float ae = r2 * kc.kex;
+        float E = fexp2(fmaf(dt, kc.kw, ae));
         if (MASK_BG || MASK_EX) {
             const int j = cbase + ((lane + s) & (HK_WAVE - 1));
             if (MASK_BG && !(j < irow)) b = 0.0f;
             if (!(j < gr)) E = 0.0f;
         }
         const float te = E * r.w;
-        blk[0] += b;
-        C[0] = rot_next(C[0]) + b;
+        B0d += (double)b;
+        C0d = rot_next_d(C0d) + (double)b;
         if (MODE >= HK_MODE_GRAD) {
             const float p1 = b * ar, p2 = b * dt2;
             blk[1] += p1;
@@ -152,7 +157,7 @@ __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, int la
                 C[4] = rot_next(C[4]) + p22;
             }
         }
-        blk[5] += te;
+        X0d += (double)te;
         if (MODE >= HK_MODE_GRAD) {
             blk[6] = fmaf(te, dt, blk[6]);
             const float q = te * ae;
@@ -171,9 +176,10 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
                                                   const int *__restrict__ g, const hk_item *__restrict__ items,
                                                   const int64_t *__restrict__ colpart_off,
                                                   double *__restrict__ rowpart, float *__restrict__ colpart,
-                                                  const PairConst kc) {
+                                                  double *__restrict__ colpart0, const PairConst kc) {
     __shared__ float4 rec[2 * HK_WAVE];
     __shared__ float colbuf[HK_WAVES][HK_NCOL][HK_WAVE];
+    __shared__ double colbuf0[HK_WAVES][HK_WAVE];
     constexpr int NC = MODE == HK_MODE_LOGLIK ? 1 : (MODE == HK_MODE_GRAD ? 3 : 5);
 
     const hk_item it = items[blockIdx.x];
@@ -181,23 +187,28 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
     const int tid = threadIdx.x, lane = tid & (HK_WAVE - 1), wv = tid / HK_WAVE;
     const int64_t row0 = (int64_t)I * HK_TILE;
     const int irow = (int)(row0 + tid);
-    const double TI = ts[row0];
-    const float ti = (float)(ts[irow] - TI);
+    const double tsi = ts[irow];
     const int xr = xi[irow], yr = yi[irow], gr = g[irow];
     const int wave_chunk = I * HK_CHUNKS_PER_TILE + wv;
     const int wave_gmin = g[(int64_t)wave_chunk * HK_WAVE];  // g is non-decreasing
     const int64_t stride = (int64_t)(I + 1) * HK_TILE;
     float *__restrict__ cp = colpart + colpart_off[I];
+    double *__restrict__ cp0 = colpart0 + colpart_off[I] / HK_NCOL;
 
     float hi[HK_NROW], lo[HK_NROW];
 #pragma unroll
     for (int a = 0; a < HK_NROW; ++a) hi[a] = lo[a] = 0.0f;
+    double B0d = 0.0, X0d = 0.0;
 
     for (int c = it.c_begin; c < it.c_end; ++c) {
+        // times relative to the chunk's first event: for the pairs that carry the
+        // sums (close in time) both operands of dt are then small and exact to FP32
+        const double Tc = ts[(int64_t)c * HK_WAVE];
+        const float ti = (float)(tsi - Tc);
         if (tid < HK_WAVE) {
             const int64_t j = (int64_t)c * HK_WAVE + tid;
             float4 r;
-            r.x = (float)(ts[j] - TI);
+            r.x = (float)(ts[j] - Tc);
             r.y = __int_as_float(xi[j]);
             r.z = __int_as_float(yi[j]);
             r.w = theta_s[j];
@@ -206,6 +217,7 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         }
         __syncthreads();
         float blk[HK_NROW], C[HK_NCOL];
+        double C0d = 0.0;
 #pragma unroll
         for (int a = 0; a < HK_NROW; ++a) blk[a] = 0.0f;
 #pragma unroll
@@ -213,34 +225,41 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         if (c <= wave_chunk) {
             const int cbase = c * HK_WAVE;
             if (c == wave_chunk)
-                row_sweep<MODE, true, true>(rec, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C);
+                row_sweep<MODE, true, true>(rec, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0d, C0d);
             else if (cbase + HK_WAVE - 1 >= wave_gmin)
-                row_sweep<MODE, false, true>(rec, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C);
+                row_sweep<MODE, false, true>(rec, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0d, C0d);
             else
-                row_sweep<MODE, false, false>(rec, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C);
+                row_sweep<MODE, false, false>(rec, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0d, C0d);
         }
         // after 64 rotation steps lane l holds the accumulators of column (l - 1) mod 64
         const int col = (lane + HK_WAVE - 1) & (HK_WAVE - 1);
+        colbuf0[wv][col] = C0d;
 #pragma unroll
-        for (int a = 0; a < NC; ++a) colbuf[wv][a][col] = C[a];
+        for (int a = 1; a < NC; ++a) colbuf[wv][a][col] = C[a];
         __syncthreads();
         for (int q = tid; q < NC * HK_WAVE; q += HK_TILE) {
             const int a = q / HK_WAVE, cc = q % HK_WAVE;
-            const float v = ((colbuf[0][a][cc] + colbuf[1][a][cc]) + colbuf[2][a][cc]) + colbuf[3][a][cc];
-            cp[a * stride + (int64_t)c * HK_WAVE + cc] = v;
+            if (a == 0) {
+                cp0[(int64_t)c * HK_WAVE + cc] = ((colbuf0[0][cc] + colbuf0[1][cc]) + colbuf0[2][cc]) + colbuf0[3][cc];
+            } else {
+                const float v = ((colbuf[0][a][cc] + colbuf[1][a][cc]) + colbuf[2][a][cc]) + colbuf[3][a][cc];
+                cp[a * stride + (int64_t)c * HK_WAVE + cc] = v;
+            }
         }
 #pragma unroll
         for (int a = 0; a < HK_NROW; ++a) {
-            const bool used = (a == 0 || a == 5) || (MODE >= HK_MODE_GRAD && (a == 1 || a == 2 || a == 6 || a == 7)) ||
-                              MODE >= HK_MODE_HESS;
+            const bool used = (MODE >= HK_MODE_GRAD && (a == 1 || a == 2 || a == 6 || a == 7)) ||
+                              (MODE >= HK_MODE_HESS && a != 0 && a != 5);
             if (used) two_sum_acc(hi[a], lo[a], blk[a]);
         }
     }
     double *__restrict__ rp = rowpart + (int64_t)blockIdx.x * HK_NROW * HK_TILE;
+    rp[tid] = B0d;
+    rp[5 * HK_TILE + tid] = X0d;
 #pragma unroll
     for (int a = 0; a < HK_NROW; ++a) {
-        const bool used = (a == 0 || a == 5) || (MODE >= HK_MODE_GRAD && (a == 1 || a == 2 || a == 6 || a == 7)) ||
-                          MODE >= HK_MODE_HESS;
+        const bool used = (MODE >= HK_MODE_GRAD && (a == 1 || a == 2 || a == 6 || a == 7)) ||
+                          (MODE >= HK_MODE_HESS && a != 0 && a != 5);
         if (used) rp[a * HK_TILE + tid] = (double)hi[a] + (double)lo[a];
     }
 }
@@ -289,8 +308,10 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
                                              const int *__restrict__ perm, int64_t n, int ntiles,
                                              const int *__restrict__ row_item0, const int *__restrict__ row_nseg,
                                              const double *__restrict__ rowpart, const float *__restrict__ colpart,
+                                             const double *__restrict__ colpart0,
                                              const int64_t *__restrict__ colpart_off, const FinConst fc,
-                                             double *__restrict__ lam, float *__restrict__ w, double *__restrict__ a_out,
+                                             double *__restrict__ lam, float *__restrict__ w, float *__restrict__ wlo,
+                                             double *__restrict__ a_out,
                                              double *__restrict__ blockpart, int *__restrict__ status) {
     __shared__ double sh[HK_WAVES][HK_NSUM];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -324,7 +345,7 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
         for (int J = I; J < ntiles; ++J) {
             const int64_t stride = (int64_t)(J + 1) * HK_TILE;
             const float *cp = colpart + colpart_off[J] + i;
-            acc[0] += (double)cp[0];
+            acc[0] += colpart0[colpart_off[J] / HK_NCOL + i];
             if (MODE >= HK_MODE_GRAD) {
                 acc[1] += (double)cp[stride];
                 acc[2] += (double)cp[2 * stride];
@@ -348,7 +369,12 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
         if (!(lamv > 0.0)) {
             atomicOr(status, isnan(lamv) ? HK_ST_NONFINITE : HK_ST_ZERO);
         }
-        w[i] = lamv > 0.0 ? (float)(fc.c_e / lamv) : 0.0f;
+        {
+            const double wd = lamv > 0.0 ? fc.c_e / lamv : 0.0;
+            const float whi = (float)wd;
+            w[i] = whi;
+            wlo[i] = (float)(wd - (double)whi);
+        }
         s[0] = log(lamv);
         const double inv = 1.0 / lamv;
         if (MODE >= HK_MODE_GRAD) {
@@ -400,6 +426,7 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
     } else if (i < (int64_t)ntiles * HK_TILE) {
         lam[i] = 1.0;
         w[i] = 0.0f;
+        wlo[i] = 0.0f;
         a_out[i] = 0.0;
     }
     const int lane = threadIdx.x & (HK_WAVE - 1), wv = threadIdx.x / HK_WAVE;
@@ -448,9 +475,15 @@ __global__ void k_fin2(const double *__restrict__ blockpart, int nblocks, double
 }
 
 // ------------------------------------------------------------------------------------
+// Column pass.  Each term E_ij w_i is formed to about FP32 rounding: w_i is a
+// (hi, lo) pair, times are rebased per 64-row chunk, and Eq. 4 (squared terms)
+// carries two extra moments, sum (E w)^2 dt and sum (E w)^2 a_e, from which the
+// FP64 finalisation removes the bias of the rounded exponent constants.
 template <bool WITH_H, bool MASKED>
-__device__ __forceinline__ void col_sweep(const float4 *__restrict__ rrec, const int *__restrict__ rg, int jcol,
-                                          float tj, int xj, int yj, const PairConst kc, float &G, float &H) {
+__device__ __forceinline__ void col_sweep(const float4 *__restrict__ rrec, const float *__restrict__ rwlo,
+                                          const int *__restrict__ rg, int jcol, float tj, int xj, int yj,
+                                          const PairConst kc, float &G, float &H, float &Hdt, float &Hae) {
+#pragma clang fp contract(off)
 #pragma unroll 16
     for (int s = 0; s < HK_WAVE; ++s) {
         const float4 r = rrec[s];
@@ -458,80 +491,102 @@ __device__ __forceinline__ void col_sweep(const float4 *__restrict__ rrec, const
         const float dx = (float)(__float_as_int(r.y) - xj);
         const float dy = (float)(__float_as_int(r.z) - yj);
         const float r2 = fmaf(dx, dx, dy * dy);
-        float E = fexp2(fmaf(dt, kc.kw, r2 * kc.kex));
+        const float ae = r2 * kc.kex;
+        float E = fexp2(fmaf(dt, kc.kw, ae));
         if (MASKED) {
             if (!(jcol < rg[s])) E = 0.0f;
         }
-        const float ew = E * r.w;
+        const float ew = fmaf(E, rwlo[s], E * r.w);
         G += ew;
-        if (WITH_H) H = fmaf(ew, ew, H);
+        if (WITH_H) {
+            const float e2 = ew * ew;
+            H += e2;
+            Hdt = fmaf(e2, dt, Hdt);
+            Hae = fmaf(e2, ae, Hae);
+        }
     }
 }
 
 template <bool WITH_H>
 __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, const int *__restrict__ xi,
                                                   const int *__restrict__ yi, const float *__restrict__ w,
-                                                  const int *__restrict__ g, const hk_item *__restrict__ items,
-                                                  double *__restrict__ colG, const PairConst kc) {
+                                                  const float *__restrict__ wlo, const int *__restrict__ g,
+                                                  const hk_item *__restrict__ items, double *__restrict__ colG,
+                                                  const PairConst kc) {
     __shared__ float4 rrec[HK_WAVE];
+    __shared__ float rwlo[HK_WAVE];
     __shared__ int rg[HK_WAVE];
     const hk_item it = items[blockIdx.x];
     const int J = it.tile;
     const int tid = threadIdx.x, wv = tid / HK_WAVE;
     const int64_t col0 = (int64_t)J * HK_TILE;
     const int jcol = (int)(col0 + tid);
-    const double TJ = ts[col0];
-    const float tj = (float)(ts[jcol] - TJ);
+    const double tsj = ts[jcol];
     const int xj = xi[jcol], yj = yi[jcol];
     const int wave_first = (int)(col0 + wv * HK_WAVE);
 
-    float Gh = 0.0f, Gl = 0.0f, Hh = 0.0f, Hl = 0.0f;
+    float Gh = 0.0f, Gl = 0.0f, Hh = 0.0f, Hl = 0.0f, Hdt = 0.0f, Hae = 0.0f;
     for (int c = it.c_begin; c < it.c_end; ++c) {
+        const double Tc = ts[(int64_t)c * HK_WAVE];
         if (tid < HK_WAVE) {
             const int64_t i = (int64_t)c * HK_WAVE + tid;
             float4 r;
-            r.x = (float)(ts[i] - TJ);
+            r.x = (float)(ts[i] - Tc);
             r.y = __int_as_float(xi[i]);
             r.z = __int_as_float(yi[i]);
             r.w = w[i];
             rrec[tid] = r;
+            rwlo[tid] = wlo[i];
             rg[tid] = g[i];
         }
         __syncthreads();
         const int gmax = rg[HK_WAVE - 1], gmin = rg[0];
         if (gmax > wave_first) {
+            const float tj = (float)(tsj - Tc);
             float G = 0.0f, H = 0.0f;
             if (gmin <= wave_first + HK_WAVE - 1)
-                col_sweep<WITH_H, true>(rrec, rg, jcol, tj, xj, yj, kc, G, H);
+                col_sweep<WITH_H, true>(rrec, rwlo, rg, jcol, tj, xj, yj, kc, G, H, Hdt, Hae);
             else
-                col_sweep<WITH_H, false>(rrec, rg, jcol, tj, xj, yj, kc, G, H);
+                col_sweep<WITH_H, false>(rrec, rwlo, rg, jcol, tj, xj, yj, kc, G, H, Hdt, Hae);
             two_sum_acc(Gh, Gl, G);
             if (WITH_H) two_sum_acc(Hh, Hl, H);
         }
         __syncthreads();
     }
-    double *cg = colG + (int64_t)blockIdx.x * 2 * HK_TILE;
+    double *cg = colG + (int64_t)blockIdx.x * 4 * HK_TILE;
     cg[tid] = (double)Gh + (double)Gl;
-    if (WITH_H) cg[HK_TILE + tid] = (double)Hh + (double)Hl;
+    if (WITH_H) {
+        cg[HK_TILE + tid] = (double)Hh + (double)Hl;
+        cg[2 * HK_TILE + tid] = (double)Hdt;
+        cg[3 * HK_TILE + tid] = (double)Hae;
+    }
 }
 
 __global__ void k_colfin(const int *__restrict__ perm, int64_t n, const int *__restrict__ col_item0,
                          const int *__restrict__ col_nseg, const double *__restrict__ colG,
-                         const double *__restrict__ a, double corr, double *__restrict__ grad_theta,
+                         const double *__restrict__ a, const FinConst fc, double *__restrict__ grad_theta,
                          double *__restrict__ negH_theta) {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int J = (int)(j / HK_TILE), r = (int)(j % HK_TILE);
     const int it0 = col_item0[J], ns = col_nseg[J];
-    double G = 0.0, H = 0.0;
+    double G = 0.0, H = 0.0, Hdt = 0.0, Hae = 0.0;
     for (int sg = 0; sg < ns; ++sg) {
-        const double *cg = colG + (int64_t)(it0 + sg) * 2 * HK_TILE + r;
+        const double *cg = colG + (int64_t)(it0 + sg) * 4 * HK_TILE + r;
         G += cg[0];
-        if (negH_theta) H += cg[HK_TILE];
+        if (negH_theta) {
+            H += cg[HK_TILE];
+            Hdt += cg[2 * HK_TILE];
+            Hae += cg[3 * HK_TILE];
+        }
     }
     const int dst = perm[j];
-    if (grad_theta) grad_theta[dst] = G * corr - a[j];
-    if (negH_theta) negH_theta[dst] = H * corr * corr;
+    if (grad_theta) grad_theta[dst] = G * fc.corr - a[j];
+    if (negH_theta) {
+        const double ln2 = 0.6931471805599453;
+        H -= 2.0 * ln2 * (fc.dkw * Hdt + fc.rho_ex * Hae);
+        negH_theta[dst] = H * fc.corr * fc.corr;
+    }
 }
 
 __global__ void k_scatter_lambda(const double *__restrict__ lam, const int *__restrict__ perm, int64_t n,
@@ -562,10 +617,6 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     kc->kbt = (float)kbt;
     kc->kex = (float)kex;
     kc->kw = (float)kw;
-    kc->kbx_lo = (float)(kbx - (double)kc->kbx);
-    kc->kbt_lo = (float)(kbt - (double)kc->kbt);
-    kc->kex_lo = (float)(kex - (double)kc->kex);
-    kc->kw_lo = (float)(kw - (double)kc->kw);
     fc->rho_bx = ((double)kc->kbx - kbx) / (double)kc->kbx;
     fc->dkbt = (double)kc->kbt - kbt;
     fc->dkw = (double)kc->kw - kw;
@@ -595,7 +646,9 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
     PairConst kc;
     FinConst fc;
     hk_make_consts(p, hyper, &kc, &fc);
-    const int mode = d_negH_hyper ? HK_MODE_HESS : (d_grad_hyper ? HK_MODE_GRAD : HK_MODE_LOGLIK);
+    // the log-likelihood alone still needs the first moments: they carry the
+    // correction for the rounded FP32 exponent constants
+    const int mode = d_negH_hyper ? HK_MODE_HESS : HK_MODE_GRAD;
     const int64_t npad = p->npad;
 
     hk_prof_mark(p, HK_PROF_EVAL, true, stream);
@@ -604,17 +657,15 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
     hk_prof_mark(p, HK_PROF_ROW, true, stream);
 #define HK_ROW(M)                                                                                              \
     hipLaunchKernelGGL(k_row<M>, dim3(p->n_row_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->theta_s, \
-                       p->g, p->row_items, p->colpart_off, p->rowpart, p->colpart, kc)
+                       p->g, p->row_items, p->colpart_off, p->rowpart, p->colpart, p->colpart0, kc)
 #define HK_FIN(M)                                                                                              \
     hipLaunchKernelGGL(k_fin<M>, dim3(p->nfin_blocks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->n,      \
-                       p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart_off, fc, p->lam, \
-                       p->w, p->a, p->blockpart, p->status)
-    if (mode == HK_MODE_LOGLIK) HK_ROW(HK_MODE_LOGLIK);
-    else if (mode == HK_MODE_GRAD) HK_ROW(HK_MODE_GRAD);
+                       p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart0, p->colpart_off, fc, \
+                       p->lam, p->w, p->wlo, p->a, p->blockpart, p->status)
+    if (mode == HK_MODE_GRAD) HK_ROW(HK_MODE_GRAD);
     else HK_ROW(HK_MODE_HESS);
     hk_prof_mark(p, HK_PROF_ROW, false, stream);
-    if (mode == HK_MODE_LOGLIK) HK_FIN(HK_MODE_LOGLIK);
-    else if (mode == HK_MODE_GRAD) HK_FIN(HK_MODE_GRAD);
+    if (mode == HK_MODE_GRAD) HK_FIN(HK_MODE_GRAD);
     else HK_FIN(HK_MODE_HESS);
 #undef HK_ROW
 #undef HK_FIN
@@ -624,13 +675,13 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
         hk_prof_mark(p, HK_PROF_COL, true, stream);
         if (d_negH_theta)
             hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                               p->w, p->g, p->col_items, p->colG, kc);
+                               p->w, p->wlo, p->g, p->col_items, p->colG, kc);
         else
             hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                               p->w, p->g, p->col_items, p->colG, kc);
+                               p->w, p->wlo, p->g, p->col_items, p->colG, kc);
         hk_prof_mark(p, HK_PROF_COL, false, stream);
         hipLaunchKernelGGL(k_colfin, dim3((unsigned)((p->n + 255) / 256)), dim3(256), 0, stream, p->perm, p->n,
-                           p->col_item0, p->col_nseg, p->colG, p->a, fc.corr, d_grad_theta, d_negH_theta);
+                           p->col_item0, p->col_nseg, p->colG, p->a, fc, d_grad_theta, d_negH_theta);
     }
     hk_prof_mark(p, HK_PROF_EVAL, false, stream);
     HK_CHECK(hipGetLastError());
@@ -638,8 +689,8 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 }
 
 void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream) {
-    hipLaunchKernelGGL(k_row<HK_MODE_LOGLIK>, dim3(p->n_row_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                       p->theta_s, p->g, p->row_items, p->colpart_off, p->rowpart, p->colpart, kc);
+    hipLaunchKernelGGL(k_row<HK_MODE_GRAD>, dim3(p->n_row_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
+                       p->theta_s, p->g, p->row_items, p->colpart_off, p->rowpart, p->colpart, p->colpart0, kc);
 }
 
 extern "C" hawkes_status hawkes_loglik(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,

@@ -49,6 +49,7 @@ struct hk_subset {
     // per-evaluation buffers
     float *theta32;      // [mpad] subset rates, time order
     double *xs;          // [npad] subset excitation sums per event
+    float *xmom;         // [npad][2] sum theta E dt, sum theta E a_e per event
     double *colG;        // [n_items][2][HK_TILE]
     double *gsub;        // [mpad] Eq. 3 on the subset, time order
     double *hsub;        // [mpad] Eq. 4 on the subset, time order
@@ -56,6 +57,9 @@ struct hk_subset {
     // HMC state
     double *z0, *p, *gz; // [m] slot order
     double *scal;        // [16] energies and flags
+    // feature grids of the learned preconditioner
+    int *grid;
+    int64_t grid_cap;
 };
 
 namespace {
@@ -153,6 +157,7 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
                                                     const int *__restrict__ row_nseg,
                                                     const double *__restrict__ rowpart,
                                                     const float *__restrict__ colpart,
+                                                    const double *__restrict__ colpart0,
                                                     const int64_t *__restrict__ colpart_off, const FinConst fc,
                                                     double *__restrict__ lam_static, double *__restrict__ blockpart) {
     __shared__ double sh[HK_WAVES];
@@ -160,13 +165,26 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
     double lam_part = 0.0;
     if (i < n) {
         const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
-        double b0 = 0.0, x0 = 0.0;
+        double b0 = 0.0, x0 = 0.0, b1 = 0.0, b2 = 0.0, x1 = 0.0, x2 = 0.0;
         for (int sg = 0; sg < row_nseg[I]; ++sg) {
             const double *rp = rowpart + (int64_t)(row_item0[I] + sg) * HK_NROW * HK_TILE + r;
             b0 += rp[0];
+            b1 += rp[1 * HK_TILE];
+            b2 += rp[2 * HK_TILE];
             x0 += rp[5 * HK_TILE];
+            x1 += rp[6 * HK_TILE];
+            x2 += rp[7 * HK_TILE];
         }
-        for (int J = I; J < ntiles; ++J) b0 += (double)colpart[colpart_off[J] + i];
+        for (int J = I; J < ntiles; ++J) {
+            const int64_t stride = (int64_t)(J + 1) * HK_TILE;
+            b0 += colpart0[colpart_off[J] / HK_NCOL + i];
+            b1 += (double)colpart[colpart_off[J] + stride + i];
+            b2 += (double)colpart[colpart_off[J] + 2 * stride + i];
+        }
+        // first-order correction for the rounded FP32 exponent constants
+        const double ln2 = 0.6931471805599453;
+        b0 -= ln2 * (fc.rho_bx * b1 + fc.dkbt * b2);
+        x0 -= ln2 * (fc.dkw * x1 + fc.rho_ex * x2);
         lam_static[i] = fc.c_b * b0 * fc.corr + fc.c_e * x0 * fc.corr;
         // integral term: background (all events) + excitation of the fixed-rate events
         const double ti = ts[i];
@@ -227,7 +245,7 @@ __global__ void k_sub_theta(const double *__restrict__ z, const int *__restrict_
 __global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
     const double *__restrict__ ts, const int *__restrict__ xi, const int *__restrict__ yi, const int *__restrict__ g,
     const int *__restrict__ pos, const float *__restrict__ theta32, const int *__restrict__ cnt,
-    const PairConst kc, double *__restrict__ xs) {
+    const PairConst kc, double *__restrict__ xs, float *__restrict__ xmom) {
     __shared__ float4 rec[HK_WAVE];
     __shared__ int rpos[HK_WAVE];
     const int b = blockIdx.x;
@@ -237,7 +255,8 @@ __global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
     const float ti = (float)(ts[i] - Tb);
     const int xr = xi[i], yr = yi[i], gr = g[i];
     const int nsub = cnt[b];
-    float hi = 0.0f, lo = 0.0f;
+    double acc = 0.0;  // every term in FP64 (see the row pass: FP32 sums drop small terms)
+    float mdt = 0.0f, mae = 0.0f;  // sum theta E dt, sum theta E a_e (constant-rounding correction)
     for (int c0 = 0; c0 < nsub; c0 += HK_WAVE) {
         {
             const int r = c0 + lane;
@@ -255,7 +274,6 @@ __global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
             rpos[lane] = r < nsub ? pj : 0x7fffffff;
         }
         __syncthreads();
-        float blk = 0.0f;
 #pragma unroll 8
         for (int s = 0; s < HK_WAVE; ++s) {
             const float4 v = rec[s];
@@ -263,33 +281,43 @@ __global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
             const float dx = (float)(xr - __float_as_int(v.y));
             const float dy = (float)(yr - __float_as_int(v.z));
             const float r2 = fmaf(dx, dx, dy * dy);
-            const float ae = fmaf(r2, kc.kex_lo, r2 * kc.kex);
-            float E = fexp2(fmaf(dt, kc.kw, fmaf(dt, kc.kw_lo, ae)));
+            const float ae = r2 * kc.kex;
+            float E = fexp2(fmaf(dt, kc.kw, ae));
             if (!(rpos[s] < gr)) E = 0.0f;
-            blk = fmaf(E, v.w, blk);
+            const float te = E * v.w;
+            acc += (double)te;
+            mdt = fmaf(te, dt, mdt);
+            mae = fmaf(te, ae, mae);
         }
-        two_sum_acc(hi, lo, blk);
         __syncthreads();
     }
-    xs[i] = (double)hi + (double)lo;
+    xs[i] = acc;
+    xmom[2 * i] = mdt;
+    xmom[2 * i + 1] = mae;
 }
 
 __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_static, const double *__restrict__ xs,
-                                                 int64_t n, int64_t npad, const FinConst fc,
-                                                 double *__restrict__ lam, float *__restrict__ w,
+                                                 const float *__restrict__ xmom, int64_t n, int64_t npad,
+                                                 const FinConst fc,
+                                                 double *__restrict__ lam, float *__restrict__ w, float *__restrict__ wlo,
                                                  double *__restrict__ blockpart, int *__restrict__ status) {
     __shared__ double sh[HK_WAVES];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double v = 0.0;
     if (i < n) {
-        const double l = lam_static[i] + fc.c_e * fc.corr * xs[i];
+        const double ln2 = 0.6931471805599453;
+        const double x = xs[i] - ln2 * (fc.dkw * (double)xmom[2 * i] + fc.rho_ex * (double)xmom[2 * i + 1]);
+        const double l = lam_static[i] + fc.c_e * fc.corr * x;
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
-        w[i] = l > 0.0 ? (float)(fc.c_e / l) : 0.0f;
+        const double wd = l > 0.0 ? fc.c_e / l : 0.0;
+        w[i] = (float)wd;
+        wlo[i] = (float)(wd - (double)(float)wd);
         v = log(l);
     } else if (i < npad) {
         lam[i] = 1.0;
         w[i] = 0.0f;
+        wlo[i] = 0.0f;
     }
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -302,21 +330,24 @@ __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_
 template <bool WITH_H>
 __global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ ts, const int *__restrict__ xi,
                                                       const int *__restrict__ yi, const float *__restrict__ w,
-                                                      const int *__restrict__ g, const int *__restrict__ pos,
-                                                      int64_t m, const hk_item *__restrict__ items,
-                                                      const PairConst kc, double *__restrict__ colG) {
+                                                      const float *__restrict__ wlo, const int *__restrict__ g,
+                                                      const int *__restrict__ pos, int64_t m,
+                                                      const hk_item *__restrict__ items, const PairConst kc,
+                                                      double *__restrict__ colG) {
     __shared__ float4 rrec[HK_WAVE];
+    __shared__ float rwlo[HK_WAVE];
     __shared__ int rg[HK_WAVE];
     const hk_item it = items[blockIdx.x];
     const int tid = threadIdx.x;
     const int64_t r = (int64_t)it.tile * HK_TILE + tid;
     const bool live = r < m;
     const int pj = live ? pos[r] : 0;
-    const double Tc = ts[(int64_t)it.c_begin * HK_WAVE];
-    const float tj = (float)(ts[pj] - Tc);
+    const double tsj = ts[pj];
     const int xj = xi[pj], yj = yi[pj];
-    float Gh = 0.0f, Gl = 0.0f, Hh = 0.0f, Hl = 0.0f;
+    float Gh = 0.0f, Gl = 0.0f, Hh = 0.0f, Hl = 0.0f, Hdt = 0.0f, Hae = 0.0f;
     for (int c = it.c_begin; c < it.c_end; ++c) {
+        const double Tc = ts[(int64_t)c * HK_WAVE];
+        const float tj = (float)(tsj - Tc);
         if (tid < HK_WAVE) {
             const int64_t i = (int64_t)c * HK_WAVE + tid;
             float4 v;
@@ -325,6 +356,7 @@ __global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ 
             v.z = __int_as_float(yi[i]);
             v.w = w[i];
             rrec[tid] = v;
+            rwlo[tid] = wlo[i];
             rg[tid] = g[i];
         }
         __syncthreads();
@@ -336,35 +368,52 @@ __global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ 
             const float dx = (float)(__float_as_int(v.y) - xj);
             const float dy = (float)(__float_as_int(v.z) - yj);
             const float r2 = fmaf(dx, dx, dy * dy);
-            float E = fexp2(fmaf(dt, kc.kw, r2 * kc.kex));
+            const float ae = r2 * kc.kex;
+            float E = fexp2(fmaf(dt, kc.kw, ae));
             if (!(pj < rg[s])) E = 0.0f;
-            const float ew = E * v.w;
+            const float ew = fmaf(E, rwlo[s], E * v.w);
             G += ew;
-            if (WITH_H) H = fmaf(ew, ew, H);
+            if (WITH_H) {
+                const float e2 = ew * ew;
+                H += e2;
+                Hdt = fmaf(e2, dt, Hdt);
+                Hae = fmaf(e2, ae, Hae);
+            }
         }
         two_sum_acc(Gh, Gl, G);
         if (WITH_H) two_sum_acc(Hh, Hl, H);
         __syncthreads();
     }
-    double *cg = colG + (int64_t)blockIdx.x * 2 * HK_TILE;
+    double *cg = colG + (int64_t)blockIdx.x * 4 * HK_TILE;
     cg[tid] = live ? (double)Gh + (double)Gl : 0.0;
-    if (WITH_H) cg[HK_TILE + tid] = live ? (double)Hh + (double)Hl : 0.0;
+    if (WITH_H) {
+        cg[HK_TILE + tid] = live ? (double)Hh + (double)Hl : 0.0;
+        cg[2 * HK_TILE + tid] = live ? (double)Hdt : 0.0;
+        cg[3 * HK_TILE + tid] = live ? (double)Hae : 0.0;
+    }
 }
 
 __global__ void k_sub_colfin(const int *__restrict__ item0, const int *__restrict__ nseg,
-                             const double *__restrict__ colG, const double *__restrict__ a, int64_t m, double corr,
-                             bool with_h, double *__restrict__ gsub, double *__restrict__ hsub) {
+                             const double *__restrict__ colG, const double *__restrict__ a, int64_t m,
+                             const FinConst fc, bool with_h, double *__restrict__ gsub, double *__restrict__ hsub) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= m) return;
     const int T = (int)(r / HK_TILE), lr = (int)(r % HK_TILE);
-    double G = 0.0, H = 0.0;
+    double G = 0.0, H = 0.0, Hdt = 0.0, Hae = 0.0;
     for (int sg = 0; sg < nseg[T]; ++sg) {
-        const double *cg = colG + (int64_t)(item0[T] + sg) * 2 * HK_TILE + lr;
+        const double *cg = colG + (int64_t)(item0[T] + sg) * 4 * HK_TILE + lr;
         G += cg[0];
-        if (with_h) H += cg[HK_TILE];
+        if (with_h) {
+            H += cg[HK_TILE];
+            Hdt += cg[2 * HK_TILE];
+            Hae += cg[3 * HK_TILE];
+        }
     }
-    gsub[r] = G * corr - a[r];
-    if (with_h) hsub[r] = H * corr * corr;
+    gsub[r] = G * fc.corr - a[r];
+    if (with_h) {
+        const double ln2 = 0.6931471805599453;
+        hsub[r] = (H - 2.0 * ln2 * (fc.dkw * Hdt + fc.rho_ex * Hae)) * fc.corr * fc.corr;
+    }
 }
 
 // Scatter the subset results to the caller's slot order.
@@ -516,7 +565,8 @@ void hk_subset_free(hawkes_plan p) {
     hk_subset *s = p->sub;
     if (!s) return;
     void *ptrs[] = {s->pos, s->slot, s->cidx, s->cnt, s->items, s->item0, s->nseg, s->lam_static, s->Lam_static,
-                    s->a, s->theta32, s->xs, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->scal};
+                    s->a, s->theta32, s->xs, s->xmom, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->scal,
+                    s->grid};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete s;
@@ -602,7 +652,8 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     SC(dalloc(&s->a, s->mpad));
     SC(dalloc(&s->theta32, s->mpad));
     SC(dalloc(&s->xs, p->npad));
-    SC(dalloc(&s->colG, (size_t)s->n_items * 2 * HK_TILE));
+    SC(dalloc(&s->xmom, 2 * p->npad));
+    SC(dalloc(&s->colG, (size_t)s->n_items * 4 * HK_TILE));
     SC(dalloc(&s->gsub, s->mpad));
     SC(dalloc(&s->hsub, s->mpad));
     SC(dalloc(&s->sums, 8));
@@ -633,7 +684,8 @@ hawkes_status ensure_static(hawkes_plan p, const hawkes_hyper *hy, const double 
     hipLaunchKernelGGL(k_sub_zero_subset, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->pos, s->m, p->theta_s);
     hk_launch_row_loglik(p, kc, stream);
     hipLaunchKernelGGL(k_sub_static, dim3(p->nfin_blocks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->theta_s,
-                       p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart_off, fc,
+                       p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart0,
+                       p->colpart_off, fc,
                        s->lam_static, p->blockpart);
     hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(64), 0, stream, p->blockpart, p->nfin_blocks, s->Lam_static);
     hipLaunchKernelGGL(k_sub_a, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, p->ts, s->pos, s->m, s->mpad, fc,
@@ -652,17 +704,18 @@ void sub_eval(hawkes_plan p, const double *z, double *theta_full, bool with_h, c
     hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, s->slot, s->cidx, s->m,
                        s->mpad, s->theta32, theta_full);
     hipLaunchKernelGGL(k_sub_row, dim3(p->nchunks), dim3(SUB_ROW_THREADS), 0, stream, p->ts, p->xi, p->yi, p->g,
-                       s->pos, s->theta32, s->cnt, kc, s->xs);
-    hipLaunchKernelGGL(k_sub_fin, dim3(p->nfin_blocks), dim3(256), 0, stream, s->lam_static, s->xs, p->n, p->npad, fc,
-                       p->lam, p->w, p->blockpart, p->status);
+                       s->pos, s->theta32, s->cnt, kc, s->xs, s->xmom);
+    hipLaunchKernelGGL(k_sub_fin, dim3(p->nfin_blocks), dim3(256), 0, stream, s->lam_static, s->xs, s->xmom, p->n,
+                       p->npad, fc,
+                       p->lam, p->w, p->wlo, p->blockpart, p->status);
     if (with_h)
         hipLaunchKernelGGL(k_sub_col<true>, dim3(s->n_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->w,
-                           p->g, s->pos, s->m, s->items, kc, s->colG);
+                           p->wlo, p->g, s->pos, s->m, s->items, kc, s->colG);
     else
         hipLaunchKernelGGL(k_sub_col<false>, dim3(s->n_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->w,
-                           p->g, s->pos, s->m, s->items, kc, s->colG);
+                           p->wlo, p->g, s->pos, s->m, s->items, kc, s->colG);
     hipLaunchKernelGGL(k_sub_colfin, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->item0, s->nseg, s->colG, s->a,
-                       s->m, fc.corr, with_h, s->gsub, s->hsub);
+                       s->m, fc, with_h, s->gsub, s->hsub);
 }
 
 __global__ void k_z_from_theta(const double *__restrict__ theta, const int64_t *__restrict__ cidx, int64_t m,
@@ -742,5 +795,45 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
                        a->counter, m, s->z0, a->d_z, a->d_out, (int *)(s->scal + 8));
     hipLaunchKernelGGL(k_sub_theta_full, dim3(gb), dim3(256), 0, stream, a->d_z, s->cidx, m, a->d_theta);
     HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
+void hk_subset_view(hawkes_plan p, int64_t *m, const int64_t **cidx, const int **pos, const int **slot) {
+    *m = p->sub->m;
+    *cidx = p->sub->cidx;
+    *pos = p->sub->pos;
+    *slot = p->sub->slot;
+}
+
+hawkes_status hk_subset_grid(hawkes_plan p, int64_t cells, hipStream_t stream) {
+    hk_subset *s = p->sub;
+    if (s->grid_cap >= cells) return HAWKES_OK;
+    if (s->grid) {
+        HK_CHECK(hipStreamSynchronize(stream));
+        (void)hipFree(s->grid);
+        s->grid = nullptr;
+        s->grid_cap = 0;
+    }
+    if (hipMalloc((void **)&s->grid, sizeof(int) * cells + 16) != hipSuccess) return HAWKES_E_NOMEM;
+    s->grid_cap = cells;
+    return HAWKES_OK;
+}
+
+int *hk_subset_grid_ptr(hawkes_plan p) { return p->sub->grid; }
+
+hawkes_status hk_subset_exact(hawkes_plan p, const hawkes_hyper *hy, const double *d_theta, hipStream_t stream,
+                              const double **gsub, const double **hsub) {
+    hk_subset *s = p->sub;
+    p->last_stream = stream;
+    PairConst kc;
+    FinConst fc;
+    hk_make_consts(p, hy, &kc, &fc);
+    hawkes_status st = ensure_static(p, hy, d_theta, false, kc, fc, stream);
+    if (st != HAWKES_OK) return st;
+    hipLaunchKernelGGL(k_z_from_theta, dim3(nblk(s->m, 256)), dim3(256), 0, stream, d_theta, s->cidx, s->m, s->z0);
+    sub_eval(p, s->z0, nullptr, true, kc, fc, stream);
+    HK_CHECK(hipGetLastError());
+    *gsub = s->gsub;
+    *hsub = s->hsub;
     return HAWKES_OK;
 }

@@ -48,6 +48,7 @@ struct hawkes_plan_s {
     double t0;       // window start
     double t1;       // max t
     double cx, cy;   // fixed-point centre
+    double xmin, xmax, ymin, ymax;  // bounding box of the locations
     int fxk;         // x_fixed = rint((x - cx) * 2^fxk)
     int device;
 
@@ -73,11 +74,13 @@ struct hawkes_plan_s {
     // per-evaluation scratch (device)
     float *theta_s;           // [npad] rates in sorted order (FP32), 0 on padding
     double *rowpart;          // [n_row_items][HK_NROW][HK_TILE]
-    float *colpart;           // triangular [tile][HK_NCOL][(tile+1)*HK_TILE]
+    float *colpart;           // triangular [tile][HK_NCOL][(tile+1)*HK_TILE] (slots 1..4)
+    double *colpart0;         // triangular [tile][(tile+1)*HK_TILE]: background column sums
     double *lam;              // [npad] lambda_i, sorted
-    float *w;                 // [npad] c_e / lambda_i (FP32), 0 on padding
+    float *w;                 // [npad] c_e / lambda_i (FP32 high part), 0 on padding
+    float *wlo;               // [npad] FP32 remainder of c_e / lambda_i
     double *a;                // [npad] theta0 (1 - exp(-omega (T1 - t_i)))
-    double *colG;             // [n_col_items][2][HK_TILE]
+    double *colG;             // [n_col_items][4][HK_TILE]: G, H and the two H moments
     int nfin_blocks;
     double *blockpart;        // [nfin_blocks][HK_NSUM]
     int *status;              // sticky device status bits
@@ -88,6 +91,10 @@ struct hawkes_plan_s {
 
 hipError_t hk_sort_pairs(double *key, int *idx, int64_t n2, hipStream_t stream);
 void hk_subset_free(hawkes_plan p);
+// views of the free-rate subset for the preconditioner code
+void hk_subset_view(hawkes_plan p, int64_t *m, const int64_t **cidx, const int **pos, const int **slot);
+hawkes_status hk_subset_grid(hawkes_plan p, int64_t cells, hipStream_t stream);
+int *hk_subset_grid_ptr(hawkes_plan p);
 
 // Exponent constants of the pair kernels (log2 units) and the FP64 constants of
 // the finalisation; built per call from the hyperparameters.
@@ -96,9 +103,6 @@ struct PairConst {
     float kbt;  // -1 / (2 tau_t^2 ln 2)
     float kex;  // -2^{-2k} / (2 h^2 ln 2): fixed-point r^2 -> log2 units, excitation
     float kw;   // -omega / ln 2
-    // FP32 remainders of the four constants (k = kf + klo to ~2^-48), used by the
-    // sweeps that accumulate no moments to correct with
-    float kbx_lo, kbt_lo, kex_lo, kw_lo;
 };
 
 struct FinConst {
@@ -117,8 +121,12 @@ struct FinConst {
 };
 
 bool hk_hyper_ok(const hawkes_hyper *h);
+// Eq. 3 and Eq. 4 on the subset at the rates d_theta (O(N M) path); device
+// pointers to the results in time order
+hawkes_status hk_subset_exact(hawkes_plan p, const hawkes_hyper *hy, const double *d_theta, hipStream_t stream,
+                              const double **gsub, const double **hsub);
 void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, FinConst *fc);
-// Row pass in log-likelihood mode over all pairs with the sorted FP32 rates
+// Row pass over all pairs (first moments included) with the sorted FP32 rates
 // already in p->theta_s; leaves the partial sums in p->rowpart / p->colpart.
 void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream);
 

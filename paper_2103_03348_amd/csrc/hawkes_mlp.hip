@@ -1,0 +1,401 @@
+// Learned preconditioner: per-event grid-count features, a 12 -> 64 -> 64 -> 1
+// tanh network (forward, back-propagation, Adam) and the running-average mass
+// update that consumes either its prediction or the exact Hessian diagonal.
+//
+// The network predicts log H_m, the rate Hessian diagonal of Eq. 4, from cheap
+// features of event m; the diagonal mass of the HMC step is then
+// theta_m^2 exp(y_m) + 1/sigma_z^2.  The exact Eq. 4 (column pass) remains the
+// training target, the periodic fallback and the judge, so the sampler stays
+// exact: any positive mass leaves the target distribution invariant.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "hawkes_internal.h"
+
+#define MLP_IN 12
+#define MLP_H 64
+#define MLP_OFF_W1 0
+#define MLP_OFF_B1 (MLP_OFF_W1 + MLP_H * MLP_IN)
+#define MLP_OFF_W2 (MLP_OFF_B1 + MLP_H)
+#define MLP_OFF_B2 (MLP_OFF_W2 + MLP_H * MLP_H)
+#define MLP_OFF_W3 (MLP_OFF_B2 + MLP_H)
+#define MLP_OFF_B3 (MLP_OFF_W3 + MLP_H)
+#define MLP_NP (MLP_OFF_B3 + 1)
+
+static_assert(MLP_NP == 5057, "parameter count");
+
+namespace {
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// ---- network -----------------------------------------------------------------------------
+// One thread per sample; parameters staged in LDS.  Activations h1, h2 are kept
+// for back-propagation when the pointers are non-NULL.
+// A batch row index outside [0, n_rows) is not read: the sample is dropped
+// (zero input, zero target weight) and bit 1 of *err is set.
+__device__ __forceinline__ int64_t checked_row(const int *rows, int64_t s, int64_t n_rows, int *err, bool &ok) {
+    const int64_t row = rows ? (int64_t)rows[s] : s;
+    ok = row >= 0 && row < n_rows;
+    if (!ok && err) atomicOr(err, 1);
+    return ok ? row : 0;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ params, const float *__restrict__ X,
+                                                 int64_t n_rows, const int *__restrict__ rows, int64_t B,
+                                                 float *__restrict__ y, float *__restrict__ h1o,
+                                                 float *__restrict__ h2o, int *__restrict__ err) {
+    __shared__ float P[MLP_NP];
+    for (int q = threadIdx.x; q < MLP_NP; q += blockDim.x) P[q] = params[q];
+    __syncthreads();
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= B) return;
+    bool ok;
+    const int64_t row = checked_row(rows, s, n_rows, err, ok);
+    float x[MLP_IN];
+#pragma unroll
+    for (int j = 0; j < MLP_IN; ++j) x[j] = ok ? X[row * MLP_IN + j] : 0.0f;
+    float h1[MLP_H];
+#pragma unroll 4
+    for (int k = 0; k < MLP_H; ++k) {
+        float a = P[MLP_OFF_B1 + k];
+#pragma unroll
+        for (int j = 0; j < MLP_IN; ++j) a = fmaf(P[MLP_OFF_W1 + k * MLP_IN + j], x[j], a);
+        h1[k] = tanhf(a);
+    }
+    float out = P[MLP_OFF_B3];
+    for (int k = 0; k < MLP_H; ++k) {
+        float a = P[MLP_OFF_B2 + k];
+#pragma unroll
+        for (int j = 0; j < MLP_H; ++j) a = fmaf(P[MLP_OFF_W2 + k * MLP_H + j], h1[j], a);
+        const float h2 = tanhf(a);
+        if (h2o) h2o[s * MLP_H + k] = h2;
+        out = fmaf(P[MLP_OFF_W3 + k], h2, out);
+    }
+    if (h1o)
+#pragma unroll
+        for (int k = 0; k < MLP_H; ++k) h1o[s * MLP_H + k] = h1[k];
+    y[s] = out;
+}
+
+// Per-sample back-propagation: dy = 2 (y - t) / B, d2 = dy w3 (1 - h2^2),
+// d1 = (W2^T d2) (1 - h1^2); block partial sums of the squared residuals.
+__global__ __launch_bounds__(256) void k_mlp_bwd(const float *__restrict__ params, const float *__restrict__ y,
+                                                 const float *__restrict__ target, int64_t n_rows,
+                                                 const int *__restrict__ rows, int64_t B,
+                                                 const float *__restrict__ h1, const float *__restrict__ h2,
+                                                 float *__restrict__ d1o, float *__restrict__ d2o,
+                                                 float *__restrict__ dyo, double *__restrict__ loss_part) {
+    __shared__ float P[MLP_H * MLP_H + MLP_H];
+    __shared__ double red[256];
+    for (int q = threadIdx.x; q < MLP_H * MLP_H; q += blockDim.x) P[q] = params[MLP_OFF_W2 + q];
+    for (int q = threadIdx.x; q < MLP_H; q += blockDim.x) P[MLP_H * MLP_H + q] = params[MLP_OFF_W3 + q];
+    __syncthreads();
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double r2 = 0.0;
+    if (s < B) {
+        bool ok;
+        const int64_t row = checked_row(rows, s, n_rows, nullptr, ok);
+        const float r = ok ? y[s] - target[row] : 0.0f;
+        r2 = (double)r * (double)r;
+        const float dy = 2.0f * r / (float)B;
+        dyo[s] = dy;
+        float d2[MLP_H];
+#pragma unroll
+        for (int k = 0; k < MLP_H; ++k) {
+            const float hk = h2[s * MLP_H + k];
+            d2[k] = dy * P[MLP_H * MLP_H + k] * (1.0f - hk * hk);
+            d2o[s * MLP_H + k] = d2[k];
+        }
+        for (int j = 0; j < MLP_H; ++j) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < MLP_H; ++k) a = fmaf(P[k * MLP_H + j], d2[k], a);
+            const float hj = h1[s * MLP_H + j];
+            d1o[s * MLP_H + j] = a * (1.0f - hj * hj);
+        }
+    }
+    red[threadIdx.x] = r2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// One thread per parameter: the batch sum of its gradient terms in fixed order (FP64).
+__global__ __launch_bounds__(256) void k_mlp_wgrad(const float *__restrict__ X, int64_t n_rows,
+                                                   const int *__restrict__ rows, int64_t B,
+                                                   const float *__restrict__ h1,
+                                                   const float *__restrict__ h2, const float *__restrict__ d1,
+                                                   const float *__restrict__ d2, const float *__restrict__ dy,
+                                                   double *__restrict__ grad) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= MLP_NP) return;
+    double acc = 0.0;
+    if (q < MLP_OFF_B1) {
+        const int k = q / MLP_IN, j = q % MLP_IN;
+        for (int64_t s = 0; s < B; ++s) {
+            bool ok;
+            const int64_t row = checked_row(rows, s, n_rows, nullptr, ok);
+            if (ok) acc += (double)d1[s * MLP_H + k] * (double)X[row * MLP_IN + j];
+        }
+    } else if (q < MLP_OFF_W2) {
+        const int k = q - MLP_OFF_B1;
+        for (int64_t s = 0; s < B; ++s) acc += (double)d1[s * MLP_H + k];
+    } else if (q < MLP_OFF_B2) {
+        const int k = (q - MLP_OFF_W2) / MLP_H, j = (q - MLP_OFF_W2) % MLP_H;
+        for (int64_t s = 0; s < B; ++s) acc += (double)d2[s * MLP_H + k] * (double)h1[s * MLP_H + j];
+    } else if (q < MLP_OFF_W3) {
+        const int k = q - MLP_OFF_B2;
+        for (int64_t s = 0; s < B; ++s) acc += (double)d2[s * MLP_H + k];
+    } else if (q < MLP_OFF_B3) {
+        const int k = q - MLP_OFF_W3;
+        for (int64_t s = 0; s < B; ++s) acc += (double)dy[s] * (double)h2[s * MLP_H + k];
+    } else {
+        for (int64_t s = 0; s < B; ++s) acc += (double)dy[s];
+    }
+    grad[q] = acc;
+}
+
+__global__ void k_mlp_loss(const double *__restrict__ part, int nb, int64_t B, double *__restrict__ loss) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[b];
+        loss[0] = s / (double)B;
+    }
+}
+
+// Adam (Kingma & Ba 2015) with bias correction; step t >= 1.
+__global__ void k_adam(float *__restrict__ params, const double *__restrict__ grad, float *__restrict__ m,
+                       float *__restrict__ v, int t, float lr, float b1, float b2, float eps) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= MLP_NP) return;
+    const float g = (float)grad[q];
+    const float mq = b1 * m[q] + (1.0f - b1) * g;
+    const float vq = b2 * v[q] + (1.0f - b2) * g * g;
+    m[q] = mq;
+    v[q] = vq;
+    const float mh = mq / (1.0f - powf(b1, (float)t));
+    const float vh = vq / (1.0f - powf(b2, (float)t));
+    params[q] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// ---- features -------------------------------------------------------------------------------
+struct GridSpec {
+    double gx0, gy0, t0, omega;
+    double s[3];     // cell sizes h, 3h, tau_x
+    int nx[3], ny[3];
+    int nbins;       // time bins of width 1/omega
+    int64_t off_sp[3], off_st[2];  // offsets of the spatial grids and the space-time grids (h, 3h)
+    int64_t total;
+};
+
+__device__ __forceinline__ void cell_of(double x, double y, const GridSpec &G, int c, int &cx, int &cy) {
+    cx = (int)floor((x - G.gx0) / G.s[c]);
+    cy = (int)floor((y - G.gy0) / G.s[c]);
+    cx = min(max(cx, 0), G.nx[c] - 1);
+    cy = min(max(cy, 0), G.ny[c] - 1);
+}
+
+__global__ void k_fill_zero(int *__restrict__ a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
+}
+
+__global__ void k_grid_count(const double *__restrict__ t, const double *__restrict__ xy, int64_t n,
+                             const GridSpec G, int *__restrict__ grid) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double x = xy[2 * e], y = xy[2 * e + 1];
+    const int b = min(max((int)floor((t[e] - G.t0) * G.omega), 0), G.nbins - 1);
+    for (int c = 0; c < 3; ++c) {
+        int cx, cy;
+        cell_of(x, y, G, c, cx, cy);
+        atomicAdd(&grid[G.off_sp[c] + (int64_t)cy * G.nx[c] + cx], 1);
+        if (c < 2) atomicAdd(&grid[G.off_st[c] + ((int64_t)cy * G.nx[c] + cx) * G.nbins + b], 1);
+    }
+}
+
+__global__ void k_features(const double *__restrict__ t, const double *__restrict__ xy,
+                           const int64_t *__restrict__ cidx, const int *__restrict__ pos, const int *__restrict__ slot,
+                           const int *__restrict__ g, const double *__restrict__ z, int64_t m, int64_t n, double t1,
+                           const GridSpec G, const int *__restrict__ grid, float *__restrict__ feat) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int k = slot[r];
+    const int64_t e = cidx[k];
+    const double x = xy[2 * e], y = xy[2 * e + 1];
+    const int b = min(max((int)floor((t[e] - G.t0) * G.omega), 0), G.nbins - 1);
+    float f[MLP_IN];
+    for (int c = 0; c < 3; ++c) {
+        int cx, cy;
+        cell_of(x, y, G, c, cx, cy);
+        f[c] = (float)log1p((double)(grid[G.off_sp[c] + (int64_t)cy * G.nx[c] + cx] - 1));
+        if (c < 2) {
+            const int *st = grid + G.off_st[c] + ((int64_t)cy * G.nx[c] + cx) * G.nbins;
+            const int prev = b > 0 ? st[b - 1] : 0;
+            const int next = b + 1 < G.nbins ? st[b + 1] : 0;
+            int next3 = 0;
+            for (int q = b + 1; q <= b + 3 && q < G.nbins; ++q) next3 += st[q];
+            f[3 + 3 * c] = (float)log1p((double)prev);
+            f[4 + 3 * c] = (float)log1p((double)next);
+            f[5 + 3 * c] = (float)log1p((double)next3);
+        }
+    }
+    f[9] = (float)z[k];
+    f[10] = (float)((double)g[pos[r]] / (double)n);
+    const double span = t1 - G.t0;
+    f[11] = (float)(span > 0.0 ? (t1 - t[e]) / span : 0.0);
+    for (int j = 0; j < MLP_IN; ++j) feat[(int64_t)k * MLP_IN + j] = f[j];
+}
+
+// ---- mass update ---------------------------------------------------------------------------
+// curvature_k = max(theta^2 H - theta g, 0) + 1/s^2 (exact) or theta^2 exp(pred) + 1/s^2
+// (learned); mass <- (count mass + curvature) / (count + 1)
+__global__ void k_mass_update(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
+                              const double *__restrict__ hsub, const float *__restrict__ pred,
+                              const double *__restrict__ theta, const int64_t *__restrict__ cidx, double inv_s2,
+                              double count, double *__restrict__ mass) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int k = slot[r];
+    const double th = theta[cidx[k]];
+    double curv;
+    if (pred) curv = th * th * exp((double)pred[k]) + inv_s2;
+    else curv = fmax(th * th * hsub[r] - th * gsub[r], 0.0) + inv_s2;
+    mass[k] = (count * mass[k] + curv) / (count + 1.0);
+}
+
+}  // namespace
+
+extern "C" int64_t hawkes_mlp_num_params(void) { return MLP_NP; }
+
+extern "C" int64_t hawkes_mlp_workspace_floats(int64_t B) {
+    // h1, h2, d1, d2 [B][64], y, dy [B], gradient (FP64, 2 floats each), loss partials (FP64)
+    return 4 * B * MLP_H + 2 * B + 2 * (int64_t)MLP_NP + 2 * (int64_t)nblk(B, 256) + 2 + 64;
+}
+
+extern "C" hawkes_status hawkes_mlp_forward(const float *d_params, const float *d_x, int64_t B, float *d_y,
+                                            hipStream_t stream) {
+    if (!d_params || !d_x || !d_y || B < 1) return HAWKES_E_INVALID;
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(nblk(B, 256)), dim3(256), 0, stream, d_params, d_x, B, (const int *)nullptr,
+                       B, d_y, (float *)nullptr, (float *)nullptr, (int *)nullptr);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
+static void mlp_grad_launch(const float *d_params, const float *d_x, int64_t n_rows, const int *d_rows,
+                            const float *d_target, int64_t B, float *d_work, double *d_grad, double *d_loss,
+                            int *d_err, hipStream_t stream) {
+    float *h1 = d_work, *h2 = h1 + B * MLP_H, *d1 = h2 + B * MLP_H, *d2 = d1 + B * MLP_H;
+    float *y = d2 + B * MLP_H, *dy = y + B;
+    // FP64 scratch after the FP32 arrays, 8-byte aligned
+    uintptr_t up = (uintptr_t)(dy + B);
+    up = (up + 7) & ~(uintptr_t)7;
+    double *lpart = (double *)up;
+    const unsigned nb = nblk(B, 256);
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(nb), dim3(256), 0, stream, d_params, d_x, n_rows, d_rows, B, y, h1, h2,
+                       d_err);
+    hipLaunchKernelGGL(k_mlp_bwd, dim3(nb), dim3(256), 0, stream, d_params, y, d_target, n_rows, d_rows, B, h1, h2,
+                       d1, d2, dy, lpart);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk(MLP_NP, 256)), dim3(256), 0, stream, d_x, n_rows, d_rows, B, h1, h2,
+                       d1, d2, dy, d_grad);
+    if (d_loss) hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(64), 0, stream, lpart, (int)nb, B, d_loss);
+}
+
+extern "C" hawkes_status hawkes_mlp_grad(const float *d_params, const float *d_x, int64_t n_rows,
+                                         const int *d_rows, const float *d_target, int64_t B, float *d_work,
+                                         double *d_grad, double *d_loss, int *d_err, hipStream_t stream) {
+    if (!d_params || !d_x || !d_target || !d_work || !d_grad || B < 1 || n_rows < 1) return HAWKES_E_INVALID;
+    if (!d_rows && B > n_rows) return HAWKES_E_INVALID;
+    mlp_grad_launch(d_params, d_x, n_rows, d_rows, d_target, B, d_work, d_grad, d_loss, d_err, stream);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
+extern "C" hawkes_status hawkes_mlp_train_step(float *d_params, float *d_adam_m, float *d_adam_v, int step,
+                                               float lr, const float *d_x, int64_t n_rows, const int *d_rows,
+                                               const float *d_target, int64_t B, float *d_work, double *d_grad,
+                                               double *d_loss, int *d_err, hipStream_t stream) {
+    if (!d_params || !d_adam_m || !d_adam_v || step < 1 || !d_x || !d_target || !d_work || !d_grad || B < 1 ||
+        n_rows < 1)
+        return HAWKES_E_INVALID;
+    if (!d_rows && B > n_rows) return HAWKES_E_INVALID;
+    mlp_grad_launch(d_params, d_x, n_rows, d_rows, d_target, B, d_work, d_grad, d_loss, d_err, stream);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(MLP_NP, 256)), dim3(256), 0, stream, d_params, d_grad, d_adam_m, d_adam_v,
+                       step, lr, 0.9f, 0.999f, 1e-8f);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
+extern "C" hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hy, const double *d_t,
+                                         const double *d_xy, const double *d_z, double gx0, double gy0,
+                                         float *d_feat, hipStream_t stream) {
+    if (!p || !hk_hyper_ok(hy) || !d_t || !d_xy || !d_z || !d_feat) return HAWKES_E_INVALID;
+    if (!p->sub) return HAWKES_E_UNSUPPORTED;
+    if (!(gx0 <= p->xmin) || !(gy0 <= p->ymin)) return HAWKES_E_INVALID;
+    GridSpec G;
+    G.gx0 = gx0;
+    G.gy0 = gy0;
+    G.t0 = p->t0;
+    G.omega = hy->omega;
+    G.s[0] = hy->h;
+    G.s[1] = 3.0 * hy->h;
+    G.s[2] = hy->tau_x;
+    int64_t off = 0;
+    const double nbd = floor((p->t1 - p->t0) * hy->omega) + 1.0;
+    if (!(nbd < 1e7)) return HAWKES_E_UNSUPPORTED;
+    G.nbins = (int)nbd;
+    for (int c = 0; c < 3; ++c) {
+        const double nx = floor((p->xmax - gx0) / G.s[c]) + 1.0, ny = floor((p->ymax - gy0) / G.s[c]) + 1.0;
+        if (!(nx * ny < (double)(1 << 26))) return HAWKES_E_UNSUPPORTED;
+        G.nx[c] = (int)nx;
+        G.ny[c] = (int)ny;
+        G.off_sp[c] = off;
+        off += (int64_t)G.nx[c] * G.ny[c];
+    }
+    for (int c = 0; c < 2; ++c) {
+        const double cells = (double)G.nx[c] * G.ny[c] * G.nbins;
+        if (!(cells < (double)(1 << 28))) return HAWKES_E_UNSUPPORTED;
+        G.off_st[c] = off;
+        off += (int64_t)G.nx[c] * G.ny[c] * G.nbins;
+    }
+    G.total = off;
+    hawkes_status st = hk_subset_grid(p, G.total, stream);
+    if (st != HAWKES_OK) return st;
+    int *grid = hk_subset_grid_ptr(p);
+    hipLaunchKernelGGL(k_fill_zero, dim3(std::min<int64_t>(nblk(G.total, 256), 4096)), dim3(256), 0, stream, grid,
+                       G.total);
+    hipLaunchKernelGGL(k_grid_count, dim3(nblk(p->n, 256)), dim3(256), 0, stream, d_t, d_xy, p->n, G, grid);
+    int64_t m;
+    const int64_t *cidx;
+    const int *pos, *slot;
+    hk_subset_view(p, &m, &cidx, &pos, &slot);
+    hipLaunchKernelGGL(k_features, dim3(nblk(m, 256)), dim3(256), 0, stream, d_t, d_xy, cidx, pos, slot, p->g, d_z,
+                       m, p->n, p->t1, G, grid, d_feat);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
+extern "C" hawkes_status hawkes_mass_update(hawkes_plan p, const hawkes_hyper *hy, const double *d_theta,
+                                            const float *d_pred, double sigma_z, int64_t count, double *d_mass,
+                                            hipStream_t stream) {
+    if (!p || !hk_hyper_ok(hy) || !d_theta || !d_mass || !(sigma_z > 0.0) || count < 0) return HAWKES_E_INVALID;
+    if (!p->sub) return HAWKES_E_UNSUPPORTED;
+    int64_t m;
+    const int64_t *cidx;
+    const int *pos, *slot;
+    hk_subset_view(p, &m, &cidx, &pos, &slot);
+    const double *gsub = nullptr, *hsub = nullptr;
+    if (!d_pred) {
+        hawkes_status st = hk_subset_exact(p, hy, d_theta, stream, &gsub, &hsub);
+        if (st != HAWKES_OK) return st;
+    }
+    hipLaunchKernelGGL(k_mass_update, dim3(nblk(m, 256)), dim3(256), 0, stream, slot, m, gsub, hsub, d_pred, d_theta,
+                       cidx, 1.0 / (sigma_z * sigma_z), (double)count, d_mass);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}

@@ -151,7 +151,7 @@ void free_plan(hawkes_plan p) {
     hk_subset_free(p);
     void *ptrs[] = {p->ts, p->xi, p->yi, p->perm, p->g, p->row_items, p->row_item0, p->row_nseg,
                     p->colpart_off, p->col_items, p->col_item0, p->col_nseg, p->theta_s, p->rowpart,
-                    p->colpart, p->lam, p->w, p->a, p->colG, p->blockpart, p->status};
+                    p->colpart, p->colpart0, p->lam, p->w, p->wlo, p->a, p->colG, p->blockpart, p->status};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -217,6 +217,10 @@ extern "C" hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const d
         return HAWKES_E_INVALID;
     }
     p->t1 = tmax;
+    p->xmin = xmin;
+    p->xmax = xmax;
+    p->ymin = ymin;
+    p->ymax = ymax;
     p->cx = 0.5 * (xmin + xmax);
     p->cy = 0.5 * (ymin + ymax);
     double half = fmax(fmax(xmax - p->cx, ymax - p->cy), 0.0);
@@ -318,10 +322,12 @@ extern "C" hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const d
     PC(dalloc(&p->theta_s, npad));
     PC(dalloc(&p->rowpart, (size_t)p->n_row_items * HK_NROW * HK_TILE));
     PC(dalloc(&p->colpart, (size_t)cpl));
+    PC(dalloc(&p->colpart0, (size_t)(cpl / HK_NCOL)));
     PC(dalloc(&p->lam, npad));
     PC(dalloc(&p->w, npad));
+    PC(dalloc(&p->wlo, npad));
     PC(dalloc(&p->a, npad));
-    PC(dalloc(&p->colG, (size_t)p->n_col_items * 2 * HK_TILE));
+    PC(dalloc(&p->colG, (size_t)p->n_col_items * 4 * HK_TILE));
     p->nfin_blocks = (int)(npad / 256);
     PC(dalloc(&p->blockpart, (size_t)p->nfin_blocks * HK_NSUM));
     PC(dalloc(&p->status, 1));

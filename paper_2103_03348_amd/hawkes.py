@@ -77,7 +77,8 @@ class Plan:
         if negH_hyper and "negH_hyper" not in o:
             o["negH_hyper"] = self._vec(6)
         hy = Hyper.of(hyper)
-        check(_lib.lib().hawkes_eval(self._h, ctypes.byref(hy), ptr(theta.contiguous()),
+        th = theta.contiguous()  # referenced until the call returns and stream-ordered after it
+        check(_lib.lib().hawkes_eval(self._h, ctypes.byref(hy), ptr(th),
                                      ptr(o.get("loglik") if loglik else None),
                                      ptr(o.get("grad_theta") if grad_theta else None),
                                      ptr(o.get("grad_hyper") if grad_hyper else None),

@@ -91,10 +91,12 @@ class HmcSampler:
                    "hawkes_subset_grad")
         return self._h.clone()
 
-    def fold_mass(self, estimate: torch.Tensor):
-        """Running average of the preconditioner estimates."""
+    def fold_exact(self):
+        """Fold the exact curvature at the current state into the running-average mass."""
+        _lib.check(_lib.lib().hawkes_mass_update(self.plan.handle, ctypes.byref(self.hyper), _lib.ptr(self.theta),
+                                                 None, self.sigma_z, self.mass_count, _lib.ptr(self.mass),
+                                                 _lib.stream_handle()), "hawkes_mass_update")
         self.mass_count += 1
-        self.mass.mul_((self.mass_count - 1) / self.mass_count).add_(estimate / self.mass_count)
 
     # ---- one iteration ------------------------------------------------------------------------
     def step(self, eps):
@@ -107,9 +109,9 @@ class HmcSampler:
     def run(self, n_iter, warmup, eps0=0.02, mass="exact", refresh=50, learned=None, exact_every=None,
             record=True, target_accept=0.8):
         """Run warmup + n_iter iterations.  mass in {"identity", "exact", "learned"}.
-        With "learned", `learned` maps the sampler to a mass estimate and the exact
-        estimate is still folded in every `exact_every` iterations (the exact kernel
-        stays the judge).  Returns dict(draws [n_iter, m] host array, eps, accept,
+        With "learned", `learned` (a LearnedPreconditioner) supplies the estimate and
+        the exact estimate is still folded in every `exact_every` iterations (the
+        exact kernel stays the judge).  Returns dict(draws [n_iter, m] host array, eps, accept,
         seconds of the sampling phase, seconds of the warm-up)."""
         da = DualAveraging(eps0, target=target_accept)
         eps = eps0
@@ -122,9 +124,9 @@ class HmcSampler:
             if it % refresh != 0:
                 return
             if mass == "exact" or (exact_every and it % exact_every == 0):
-                self.fold_mass(self.exact_curvature())
+                self.fold_exact()
             else:
-                self.fold_mass(learned(self))
+                learned.fold_into_mass(self)
 
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -1,0 +1,149 @@
+"""Learned-preconditioner kernels vs the FP64 oracle: network forward,
+back-propagation, Adam; grid-count features; the exact mass update."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import features as ofeat
+from oracle import hmc as ohmc
+from oracle import mlp as omlp
+from paper_2103_03348_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda:0") if dtype is None else \
+        torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda:0")
+
+
+def test_mlp_forward_grad_adam_match_oracle(gpu):
+    import torch
+
+    from paper_2103_03348_amd import _lib
+
+    L = _lib.lib()
+    rng = np.random.default_rng(5)
+    p = (omlp.init(seed=3) + 0.1 * rng.standard_normal(omlp.N_PARAMS)).astype(np.float32)
+    B = 777
+    X = rng.standard_normal((B, 12)).astype(np.float32)
+    T = rng.standard_normal(B).astype(np.float32)
+    dp, dX, dT = _t(p), _t(X), _t(T)
+    y = torch.empty(B, dtype=torch.float32, device="cuda:0")
+    _lib.check(L.hawkes_mlp_forward(_lib.ptr(dp), _lib.ptr(dX), B, _lib.ptr(y), _lib.stream_handle()), "fwd")
+    yref, _ = omlp.forward(p.astype(np.float64), X.astype(np.float64))
+    np.testing.assert_allclose(y.cpu().numpy(), yref, rtol=1e-5, atol=1e-5)
+    work = torch.empty(int(L.hawkes_mlp_workspace_floats(B)), dtype=torch.float32, device="cuda:0")
+    grad = torch.empty(omlp.N_PARAMS, dtype=torch.float64, device="cuda:0")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    _lib.check(L.hawkes_mlp_grad(_lib.ptr(dp), _lib.ptr(dX), B, None, _lib.ptr(dT), B, _lib.ptr(work),
+                                 _lib.ptr(grad), _lib.ptr(loss), None, _lib.stream_handle()), "grad")
+    lref, gref = omlp.loss_and_grad(p.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(lref, rel=1e-5)
+    g = grad.cpu().numpy()
+    scale = np.abs(gref) + 1e-3 * np.abs(gref).max()
+    assert np.max(np.abs(g - gref) / scale) < 1e-4
+    # one Adam step from zero moments (bias-corrected first step)
+    m = torch.zeros(omlp.N_PARAMS, dtype=torch.float32, device="cuda:0")
+    v = torch.zeros_like(m)
+    _lib.check(L.hawkes_mlp_train_step(_lib.ptr(dp), _lib.ptr(m), _lib.ptr(v), 1, ctypes.c_float(1e-3),
+                                       _lib.ptr(dX), B, None, _lib.ptr(dT), B, _lib.ptr(work), _lib.ptr(grad),
+                                       _lib.ptr(loss), None, _lib.stream_handle()), "train")
+    pnew, _, _ = omlp.adam_step(p.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, lr=1e-3)
+    np.testing.assert_allclose(dp.cpu().numpy(), pnew, rtol=1e-6, atol=2e-7)
+
+
+def test_mlp_batch_rows(gpu):
+    """A batch given by row indices equals the same rows passed contiguously; an
+    out-of-range row index is reported, not read."""
+    import torch
+
+    from paper_2103_03348_amd import _lib
+
+    L = _lib.lib()
+    rng = np.random.default_rng(6)
+    p = omlp.init(seed=4).astype(np.float32)
+    X = rng.standard_normal((1000, 12)).astype(np.float32)
+    T = rng.standard_normal(1000).astype(np.float32)
+    rows = rng.integers(0, 1000, size=300).astype(np.int32)
+    B = rows.shape[0]
+    # every argument tensor stays referenced until the GPU work is done
+    dp, dX, dT, drows = _t(p), _t(X), _t(T), _t(rows)
+    dXr, dTr = _t(X[rows]), _t(T[rows])
+    work = torch.empty(int(L.hawkes_mlp_workspace_floats(B)), dtype=torch.float32, device="cuda:0")
+    g1 = torch.empty(omlp.N_PARAMS, dtype=torch.float64, device="cuda:0")
+    g2 = torch.empty_like(g1)
+    err = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    _lib.check(L.hawkes_mlp_grad(_lib.ptr(dp), _lib.ptr(dX), 1000, _lib.ptr(drows), _lib.ptr(dT), B,
+                                 _lib.ptr(work), _lib.ptr(g1), None, _lib.ptr(err), _lib.stream_handle()), "g1")
+    _lib.check(L.hawkes_mlp_grad(_lib.ptr(dp), _lib.ptr(dXr), B, None, _lib.ptr(dTr), B,
+                                 _lib.ptr(work), _lib.ptr(g2), None, _lib.ptr(err), _lib.stream_handle()), "g2")
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    assert int(err.item()) == 0
+    bad = rows.copy()
+    bad[7] = 1000
+    bad[9] = -1
+    dbad = _t(bad)
+    _lib.check(L.hawkes_mlp_grad(_lib.ptr(dp), _lib.ptr(dX), 1000, _lib.ptr(dbad), _lib.ptr(dT), B,
+                                 _lib.ptr(work), _lib.ptr(g1), None, _lib.ptr(err), _lib.stream_handle()), "g3")
+    torch.cuda.synchronize()
+    assert int(err.item()) == 1
+
+
+def _plan_with_subset(es):
+    import torch
+
+    from paper_2103_03348_amd import _lib
+    from paper_2103_03348_amd.hawkes import Plan
+
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
+    idx = torch.as_tensor(es.subset, dtype=torch.int64, device="cuda:0")
+    _lib.check(_lib.lib().hawkes_plan_set_subset(plan.handle, idx.numel(), _lib.ptr(idx), _lib.stream_handle()),
+               "subset")
+    return plan
+
+
+@pytest.mark.parametrize("cfg", ["small", "n23422"])
+def test_features_match_oracle(gpu, cfg):
+    import torch
+
+    from paper_2103_03348_amd import _lib
+
+    es = synth.small(3000, seed=31, all_free=False) if cfg == "small" else synth.config(1)
+    plan = _plan_with_subset(es)
+    z = np.log(es.theta[es.subset])
+    gx0, gy0 = float(es.x.min()) - 1e-9, float(es.y.min()) - 1e-9
+    feat = torch.empty((es.subset.shape[0], 12), dtype=torch.float32, device="cuda:0")
+    hy = _lib.Hyper.of(es.hyper)
+    dt, dxy, dz = _t(es.t), _t(np.stack([es.x, es.y], 1)), _t(z)
+    _lib.check(_lib.lib().hawkes_features(plan.handle, ctypes.byref(hy), _lib.ptr(dt), _lib.ptr(dxy), _lib.ptr(dz),
+                                          gx0, gy0, _lib.ptr(feat), _lib.stream_handle()), "features")
+    torch.cuda.synchronize()
+    F = feat.cpu().numpy()
+    sub = slice(None) if cfg == "small" else slice(0, 300)
+    ref = ofeat.features(es.t, es.x, es.y, es.subset[sub], z[sub], es.hyper, es.t0, gx0, gy0)
+    np.testing.assert_allclose(F[sub], ref, rtol=1e-6, atol=1e-6)
+
+
+def test_exact_mass_update_matches_oracle(gpu):
+    """mass <- curvature (count 0): max(theta^2 H - theta g, 0) + 1/sigma^2 on the subset."""
+    import torch
+
+    from paper_2103_03348_amd import _lib
+
+    es = synth.small(1200, seed=32, all_free=False)
+    plan = _plan_with_subset(es)
+    sig = 0.5
+    mass = torch.zeros(es.subset.shape[0], dtype=torch.float64, device="cuda:0")
+    hy = _lib.Hyper.of(es.hyper)
+    dth = _t(es.theta)
+    _lib.check(_lib.lib().hawkes_mass_update(plan.handle, ctypes.byref(hy), _lib.ptr(dth), None, sig, 0,
+                                             _lib.ptr(mass), _lib.stream_handle()), "mass")
+    torch.cuda.synchronize()
+    ref = ohmc.z_hessian_diag(es.t, es.x, es.y, es.theta, es.subset, np.log(es.theta[es.subset]), es.hyper, 0.0, sig)
+    ref = np.maximum(ref - 1.0 / sig ** 2, 0.0) + 1.0 / sig ** 2
+    np.testing.assert_allclose(mass.cpu().numpy(), ref, rtol=1e-6)
