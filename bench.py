@@ -62,6 +62,66 @@ def cpu_baseline(es, budget_s=12.0):
                       f"derivatives) of the N={n} workload, {el:.1f} s"}
 
 
+def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_states=200, seed=7):
+    """HMC ESS/s on the free log-rates with the exact and the learned diagonal
+    preconditioner (and, for reference, none), each chain adapting its step size
+    by dual averaging during its own warm-up, then `n_iter` timed iterations.
+    The network is trained first on exact Hessian diagonals at `n_states` states
+    of a pilot chain (the one-off training cost is reported separately)."""
+    import numpy as np
+    import torch
+
+    from paper_2103_03348_amd import ess as ess_mod
+    from paper_2103_03348_amd.hawkes import Plan
+    from paper_2103_03348_amd.preconditioner import LearnedPreconditioner
+    from paper_2103_03348_amd.sampler import HmcSampler
+
+    dev = torch.device("cuda:0")
+    t = torch.as_tensor(es.t, device=dev)
+    xy = torch.as_tensor(np.stack([es.x, es.y], 1), device=dev).contiguous()
+    theta0 = torch.as_tensor(es.theta, device=dev)
+    idx = torch.as_tensor(es.subset, device=dev)
+    out = {}
+
+    # pilot chain with the exact preconditioner -> training states -> network
+    tt0 = time.perf_counter()
+    plan = Plan(t, xy, es.t0)
+    pilot = HmcSampler(plan, theta0, idx, es.hyper, sigma_z=0.5, L=L, seed=seed)
+    r = pilot.run(0, warmup, eps0=0.05, mass="exact", refresh=refresh, record=False)
+    pre = LearnedPreconditioner(pilot, t, xy, seed=seed)
+    X, T = pre.collect(n_states, r["eps"], thin=2)
+    ntr = int(0.9 * X.shape[0])
+    perm = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(seed)).to(dev)
+    Xtr, Ttr, Xva, Tva = X[perm[:ntr]], T[perm[:ntr]], X[perm[ntr:]], T[perm[ntr:]]
+    loss0 = pre.evaluate(Xva, Tva)
+    pre.train(Xtr, Ttr, steps=1500, batch=4096, lr=2e-3, seed=seed)
+    loss1 = pre.evaluate(Xva, Tva)
+    torch.cuda.synchronize()
+    out["training"] = {"states": n_states, "samples": int(X.shape[0]), "val_mse_untrained": loss0,
+                       "val_mse_trained": loss1, "target_var": float(Tva.double().var().item()),
+                       "seconds": time.perf_counter() - tt0}
+    plan.close()
+
+    for mode in ("exact", "learned", "identity"):
+        plan = Plan(t, xy, es.t0)
+        smp = HmcSampler(plan, theta0, idx, es.hyper, sigma_z=0.5, L=L, seed=seed + 1)
+        learned = None
+        if mode == "learned":
+            pre.s = smp
+            learned = pre
+        r = smp.run(n_iter, warmup, eps0=0.05, mass=mode, refresh=refresh, learned=learned,
+                    exact_every=exact_every if mode == "learned" else None)
+        e = ess_mod.ess(r["draws"])
+        out[mode] = {"ess_min": float(e.min()), "ess_median": float(np.median(e)),
+                     "ess_per_s_min": float(e.min() / r["seconds"]),
+                     "ess_per_s_median": float(np.median(e) / r["seconds"]),
+                     "seconds": r["seconds"], "accept": r["accept"], "eps": r["eps"]}
+        plan.close()
+    out["config"] = {"n_events": es.n, "free_rates": int(es.subset.shape[0]), "leapfrog": L, "iterations": n_iter,
+                     "warmup": warmup, "mass_refresh": refresh, "exact_refresh_in_learned": exact_every}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +130,10 @@ def main():
     ap.add_argument("--config", type=int, default=1, choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-hmc", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device-to-device copy 5 times (HBM counter calibration)")
+    ap.add_argument("--hmc-iters", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path is built and measured on a single MI355X; "
@@ -78,6 +142,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": {"read": src.numel() * 4, "write": dst.numel() * 4}}))
+        return
 
     from paper_2103_03348_amd import _lib, synth
     from paper_2103_03348_amd.hawkes import Plan
@@ -118,7 +191,7 @@ def main():
 
     achieved = FLOPS_ROW_PER_PAIR * pairs / (row_ms * 1e-3) / 1e12
     rec = {
-        "metric": "pair-evals/s for loglik+grad+Hess-diag at N=23,422" if args.config == 1
+        "metric": "pair-evals/s for loglik+grad+Hess-diag at N=23,422; HMC ESS/s learned vs exact" if args.config == 1
         else f"pair-evals/s for loglik+grad+Hess-diag at N={n:,}",
         "value": pairs / (ms_step * 1e-3),
         "unit": "pair-evals/s",
@@ -155,6 +228,8 @@ def main():
         "eval_tflops": FLOPS_PER_PAIR * pairs / (eval_ms * 1e-3) / 1e12,
         "loglik": ll,
     }
+    if not args.no_hmc and args.config == 1:
+        rec["hmc"] = bench_hmc(synth.config(3), n_iter=args.hmc_iters)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(es, args.cpu_budget)
     print(json.dumps(rec), flush=True)

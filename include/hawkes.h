@@ -175,7 +175,7 @@ typedef struct {
 
 hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawkes_hmc_args *args, hipStream_t stream);
 
-/* ---- Learned preconditioner (a small network predicting Eq. 4) ----
+/* ---- Learned preconditioner (a small network predicting the diagonal mass) ----
  *
  * Network 12 -> 64 -> 64 -> 1, tanh hidden layers, FP32.  Parameter vector
  * (hawkes_mlp_num_params() = 5057 floats, device): W1 [64][12], b1 [64],
@@ -221,7 +221,8 @@ hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hyper, const do
 /* Running average of the diagonal mass: d_mass[k] <- (count d_mass[k] + c_k)/(count + 1)
  * with c_k the z-space curvature estimate at the rates d_theta:
  *   d_pred == NULL: exact, max(theta^2 H - theta g, 0) + 1/sigma_z^2 (Eq. 3, Eq. 4, subset path);
- *   d_pred != NULL: learned, theta^2 exp(d_pred[k]) + 1/sigma_z^2 (d_pred [m] FP32, slot order). */
+ *   d_pred != NULL: learned, max(exp(d_pred[k]), 1/sigma_z^2) (d_pred [m] FP32, slot order: a
+ *                   prediction of the log of the exact estimate). */
 hawkes_status hawkes_mass_update(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
                                  const float *d_pred, double sigma_z, int64_t count, double *d_mass,
                                  hipStream_t stream);

@@ -2,11 +2,12 @@
 // tanh network (forward, back-propagation, Adam) and the running-average mass
 // update that consumes either its prediction or the exact Hessian diagonal.
 //
-// The network predicts log H_m, the rate Hessian diagonal of Eq. 4, from cheap
-// features of event m; the diagonal mass of the HMC step is then
-// theta_m^2 exp(y_m) + 1/sigma_z^2.  The exact Eq. 4 (column pass) remains the
-// training target, the periodic fallback and the judge, so the sampler stays
-// exact: any positive mass leaves the target distribution invariant.
+// The network predicts, from cheap features of free event m, the log of the
+// exact diagonal mass estimate max(theta_m^2 H_m - theta_m g_m, 0) + 1/sigma_z^2
+// built from Eq. 3 and Eq. 4 (the z-space curvature of the log posterior).  The
+// exact column pass remains the training target, the periodic fallback and the
+// judge, so the sampler stays exact: any positive mass leaves the target
+// distribution invariant.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -253,8 +254,9 @@ __global__ void k_features(const double *__restrict__ t, const double *__restric
 }
 
 // ---- mass update ---------------------------------------------------------------------------
-// curvature_k = max(theta^2 H - theta g, 0) + 1/s^2 (exact) or theta^2 exp(pred) + 1/s^2
-// (learned); mass <- (count mass + curvature) / (count + 1)
+// curvature_k = max(theta^2 H - theta g, 0) + 1/s^2 (exact) or max(exp(pred), 1/s^2)
+// (learned: the network predicts the log of the exact estimate); mass <- (count mass
+// + curvature) / (count + 1)
 __global__ void k_mass_update(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
                               const double *__restrict__ hsub, const float *__restrict__ pred,
                               const double *__restrict__ theta, const int64_t *__restrict__ cidx, double inv_s2,
@@ -264,7 +266,7 @@ __global__ void k_mass_update(const int *__restrict__ slot, int64_t m, const dou
     const int k = slot[r];
     const double th = theta[cidx[k]];
     double curv;
-    if (pred) curv = th * th * exp((double)pred[k]) + inv_s2;
+    if (pred) curv = fmax(exp((double)pred[k]), inv_s2);
     else curv = fmax(th * th * hsub[r] - th * gsub[r], 0.0) + inv_s2;
     mass[k] = (count * mass[k] + curv) / (count + 1.0);
 }

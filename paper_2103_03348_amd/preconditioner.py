@@ -1,13 +1,15 @@
 """Learned diagonal preconditioner for the HMC step.
 
-A 12 -> 64 -> 64 -> 1 tanh network predicts log H_k, the Eq. 4 Hessian
-diagonal of free event k, from cheap per-event features (grid-cell counts,
-recent-window counts, log theta, time rank, time to the window end).  It is
-trained on the GPU by the library's own forward, back-propagation and Adam
-kernels on exact Hessian diagonals collected at saved HMC states.  The sampler
-uses theta^2 exp(prediction) + 1/sigma_z^2 as its mass estimate and still folds
-in the exact estimate at a coarser interval; because any positive mass leaves
-the target invariant, the sampler stays exact whatever the network predicts.
+A 12 -> 64 -> 64 -> 1 tanh network predicts, for free event k, the log of the
+exact diagonal mass estimate max(theta_k^2 H_k - theta_k g_k, 0) + 1/sigma_z^2
+(the z-space curvature from Eq. 3 and the Eq. 4 Hessian diagonal) from cheap
+per-event features (grid-cell counts, recent-window counts, log theta, time
+rank, time to the window end).  It is trained on the GPU by the library's own
+forward, back-propagation and Adam kernels on exact estimates collected at
+saved HMC states.  The sampler folds max(exp(prediction), 1/sigma_z^2) into
+its running-average mass and still folds in the exact estimate at a coarser
+interval; because any positive mass leaves the target invariant, the sampler
+stays exact whatever the network predicts.
 """
 from __future__ import annotations
 
@@ -20,7 +22,6 @@ from . import _lib
 from .sampler import HmcSampler
 
 N_FEATURES = 12
-H_FLOOR = 1e-6  # added to H before the log: below it the prior precision dominates the mass
 
 
 def glorot_init(seed: int) -> np.ndarray:
@@ -61,8 +62,9 @@ class LearnedPreconditioner:
         return self.feat
 
     def collect(self, n_states: int, eps: float, thin: int = 1):
-        """Advance the sampler (current mass) and record features and exact
-        log(H + floor) at n_states states.  Returns (X [n_states*m, 12], T [n_states*m])."""
+        """Advance the sampler (current mass) and record features and the log of
+        the exact mass estimate at n_states states.  Returns (X [n_states*m, 12],
+        T [n_states*m])."""
         m = self.s.m
         X = torch.empty((n_states * m, N_FEATURES), dtype=torch.float32, device=self.dev)
         T = torch.empty(n_states * m, dtype=torch.float32, device=self.dev)
@@ -70,7 +72,7 @@ class LearnedPreconditioner:
             for _ in range(thin):
                 self.s.step(eps)
             X[k * m:(k + 1) * m].copy_(self.features())
-            T[k * m:(k + 1) * m].copy_(torch.log(self.s.exact_theta_hessian() + H_FLOOR).float())
+            T[k * m:(k + 1) * m].copy_(torch.log(self.s.exact_curvature()).float())
         return X, T
 
     # ---- training ------------------------------------------------------------------------------

@@ -3,7 +3,11 @@
 The driver keeps all state on the device and calls the library's hmc_step once
 per iteration.  Between iterations it adapts:
   * the step size, by dual averaging towards a target acceptance rate during
-    warm-up (Hoffman & Gelman 2014, Algorithm 5's schedule), then frozen;
+    warm-up (Hoffman & Gelman 2014, Algorithm 5's schedule), then frozen; each
+    iteration uses the step size times a uniform jitter in [1 - j, 1 + j] (Neal
+    2011, Sec. 5.4.2.2), so that a well-preconditioned target, whose coordinates
+    all oscillate at one frequency, is not sampled at a fixed fraction of its
+    period;
   * the diagonal mass matrix, as the running average of preconditioner
     estimates computed at a fixed interval (the paper's adaptation, which keeps
     Monte Carlo estimates asymptotically unbiased).  The estimate is either the
@@ -54,7 +58,8 @@ class DualAveraging:
 class HmcSampler:
     """HMC over z = log theta on the subset `idx` of a plan's events."""
 
-    def __init__(self, plan: Plan, theta: torch.Tensor, idx: torch.Tensor, hyper, sigma_z=0.5, L=20, seed=1):
+    def __init__(self, plan: Plan, theta: torch.Tensor, idx: torch.Tensor, hyper, sigma_z=0.5, L=20, seed=1,
+                 jitter=0.5):
         self.plan = plan
         self.dev = theta.device
         self.theta = theta.clone().contiguous()
@@ -67,6 +72,8 @@ class HmcSampler:
         self.L = int(L)
         self.seed = int(seed)
         self.counter = 0
+        self.jitter = float(jitter)
+        self._jrng = np.random.default_rng(seed)
         self.z = torch.log(self.theta[self.idx]).contiguous()
         self.mass = torch.full((self.m,), 1.0 / self.sigma_z ** 2, dtype=torch.float64, device=self.dev)
         self.mass_count = 0
@@ -100,6 +107,8 @@ class HmcSampler:
 
     # ---- one iteration ------------------------------------------------------------------------
     def step(self, eps):
+        if self.jitter > 0:
+            eps = eps * self._jrng.uniform(1.0 - self.jitter, 1.0 + self.jitter)
         args = _lib.HmcArgs(self.z.data_ptr(), self.theta.data_ptr(), self.mass.data_ptr(), float(eps), self.L,
                             self.sigma_z, self.seed, self.counter, 0, self.out.data_ptr())
         _lib.check(_lib.lib().hmc_step(self.plan.handle, ctypes.byref(self.hyper), ctypes.byref(args),

@@ -53,8 +53,11 @@ def errors(es, gpu, ref):
         # the squared terms of Eq. 4 underflow FP32 below ~1e-38; 1e-30 is the floor
         hrel = np.abs(gpu["negH_theta"] - H) / (H + 1e-30)
         out["h_rel_all"] = float(np.max(hrel))
-        sig = H >= 1e-6 * H.max() if H.size and H.max() > 0 else np.zeros_like(H, dtype=bool)
-        out["h_rel"] = float(np.max(hrel[sig])) if sig.any() else 0.0
+        hmax = H.max() if H.size else 0.0
+        for tag, thr in (("h_rel_1e6", 1e-6), ("h_rel", 1e-4), ("h_rel_1e2", 1e-2)):
+            sig = H >= thr * hmax if hmax > 0 else np.zeros_like(H, dtype=bool)
+            out[tag] = float(np.max(hrel[sig])) if sig.any() else 0.0
+        out["h_rel_norm"] = float(np.linalg.norm(gpu["negH_theta"] - H) / max(np.linalg.norm(H), 1e-300))
         out["h_zero_abs"] = float(np.max(np.abs(gpu["negH_theta"][~pos]))) if (~pos).any() else 0.0
         out["gh_abs"] = np.abs(gpu["grad_hyper"] - ref["grad_hyper"])
         out["Hh_abs"] = np.abs(gpu["negH_hyper"] - ref["negH_hyper"])

@@ -54,7 +54,7 @@ def test_subset_grad_matches_oracle(gpu, cfg):
     a = es.hyper[3] * (1.0 - np.exp(-es.hyper[4] * (es.t.max() - es.t[es.subset])))
     rel_l = abs(ll - ref["loglik"]) / abs(ref["loglik"])
     rel_g = np.max(np.abs(g - gi) / np.maximum(gi + 2 * a, 1e-300))
-    sig = hi >= 1e-6 * hi.max()
+    sig = hi >= 1e-4 * hi.max()
     rel_h = np.max(np.abs(h - hi)[sig] / hi[sig])
     print(f"\nsubset {cfg}: n={es.n} m={es.subset.shape[0]} loglik rel {rel_l:.2e} g {rel_g:.2e} H {rel_h:.2e}")
     assert rel_l < (1e-9 if cfg == "n23422" else 2e-6 * es.n / abs(ref["loglik"]))

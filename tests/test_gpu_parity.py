@@ -9,12 +9,15 @@ Tolerances (FP32 pair arithmetic, compensated sums, FP64 finals):
     with margin for sets where one term dominates).
   * rate gradient: 1e-6 relative to the magnitude of Eq. 3's two terms.
   * Hessian diagonal: 1e-6 relative (all terms positive) on every entry of
-    at least 1e-6 of the largest; on the remaining entries, which consist of
-    terms with exponent arguments |a| up to ~90, each term carries the FP32
-    rounding of its argument (|a| 2^-24 ln 2, doubled by the square): 3e-5,
-    with an absolute floor of 1e-30 where the squared terms underflow FP32.
+    at least 1e-4 of the largest, and 1e-6 norm-wise.  A term with FP32
+    exponent argument a carries a relative error up to ~2 ln2 2^-24 |a| from the
+    argument's rounding (doubled by the square); entries of at least 1e-4 of the
+    largest are made of terms with |a| below ~7.  On all entries (|a| up to the
+    FP32 underflow at ~126): 3e-5, with an absolute floor of 1e-30 where the
+    squared terms underflow.
   * hyperparameter derivatives on sets below 256 events, where a handful of
-    FP32 terms carry each sum without any averaging: 1e-5 instead of 1e-6.
+    FP32 terms carry each sum without averaging and the second derivatives in
+    tau_x and h cancel three such sums: 5e-5 instead of 1e-6.
   * hyperparameter gradient / Hessian: 1e-6 relative to max(|value|, N/p) --
     their per-event terms are O(1/p), so N/p is the size of the sums that cancel.
 """
@@ -46,12 +49,13 @@ def _check(es, gpu, ref, l_tol=1e-9, tiny=False):
     assert e["lam_rel"] < 2e-6
     assert e["g_rel"] < 1e-6
     assert e["h_rel"] < 1e-6
+    assert e["h_rel_norm"] < 1e-6
     assert e["h_rel_all"] < 3e-5
     n = es.n
     hy = np.asarray(es.hyper)
     gscale = np.maximum(np.abs(ref["grad_hyper"]), n / hy)
     hscale = np.maximum(np.abs(ref["negH_hyper"]), n / hy ** 2)
-    htol = 1e-6 if n >= 256 else 1e-5
+    htol = 1e-6 if n >= 256 else 5e-5
     assert np.all(e["gh_abs"] / gscale < htol), e["gh_abs"] / gscale
     assert np.all(e["Hh_abs"] / hscale < htol), e["Hh_abs"] / hscale
 
