@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "hawkes_internal.h"
@@ -107,6 +108,17 @@ __global__ void k_gather(const double *__restrict__ theta, const int *__restrict
 }
 
 // ------------------------------------------------------------------------------------
+// Time factorisation of the excitation.  exp(-omega (t_i - t_j)) splits into
+// exp(-omega (t_i - T_c)) exp(omega (t_j - T_c)) for a chunk reference time T_c;
+// both factors are formed in FP64 once per event and chunk, so that only the
+// spatial part exp(-r^2 / 2h^2) goes through the FP32 exp2 of the pair loop
+// (and the pair loop saves the time term of the exponent).  The split is used
+// when omega times the chunk's time span is at most HK_FACT_SPAN, which keeps
+// both factors far inside the FP32 range; a chunk that spans more time (sparse
+// data) takes the direct exponent instead, with the rounding of the FP32 rate
+// constant corrected to first order inside the loop.
+#define HK_FACT_SPAN 40.0
+
 // One sweep of a 64-column chunk by one wavefront: 64 steps, each lane pairing
 // its row with column (lane + s) mod 64 of the chunk.
 //
@@ -115,10 +127,11 @@ __global__ void k_gather(const double *__restrict__ theta, const int *__restrict
 // positive terms rounds away every term below half an ulp of the running sum,
 // which biases lambda low (by ~2e-8 relative on clustered data).  The moments
 // used only by derivatives stay in FP32 blocks.
-template <int MODE, bool MASK_BG, bool MASK_EX>
-__device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, int lane, float ti, int xr, int yr,
+template <int MODE, bool MASK_BG, bool MASK_EX, bool FACT>
+__device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, const double *__restrict__ rtd,
+                                          double tsi, int lane, float ti, int xr, int yr,
                                           int irow, int gr, int cbase, const PairConst kc,
-                                          float (&blk)[HK_NROW], float (&C)[HK_NCOL], double &B0d, double &X0d,
+                                          float (&blk)[HK_NROW], float (&C)[HK_NCOL], double &B0d, double &X0c,
                                           double &C0d) {
     // explicit FMAs only: a contracted (rotated + product) cannot take the DPP
     // operand, while a plain add of the shared product can
@@ -126,7 +139,9 @@ __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, int la
 #pragma unroll 16
     for (int s = 0; s < HK_WAVE; ++s) {
         const float4 r = rec[lane + s];
-        const float dt = ti - r.x;
+        // a chunk that spans a long time takes dt from the FP64 times: relative to
+        // the chunk start, both operands could then be large
+        const float dt = FACT ? ti - r.x : (float)(tsi - rtd[lane + s]);
         const float dx = (float)(xr - __float_as_int(r.y));
         const float dy = (float)(yr - __float_as_int(r.z));
         const float r2 = fmaf(dx, dx, dy * dy);
@@ -134,7 +149,13 @@ __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, int la
         const float ar = r2 * kc.kbx;
         float b = fexp2(fmaf(dt2, kc.kbt, ar));
         const float ae = r2 * kc.kex;
-        float E = fexp2(fmaf(dt, kc.kw, ae));
+        float E;
+        if (FACT) {
+            E = fexp2(ae);
+        } else {
+            E = fexp2(fmaf(dt, kc.kw, ae));
+            E *= fmaf(dt, kc.cw, 1.0f);
+        }
         if (MASK_BG || MASK_EX) {
             const int j = cbase + ((lane + s) & (HK_WAVE - 1));
             if (MASK_BG && !(j < irow)) b = 0.0f;
@@ -157,7 +178,7 @@ __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, int la
                 C[4] = rot_next(C[4]) + p22;
             }
         }
-        X0d += (double)te;
+        X0c += (double)te;
         if (MODE >= HK_MODE_GRAD) {
             blk[6] = fmaf(te, dt, blk[6]);
             const float q = te * ae;
@@ -170,97 +191,133 @@ __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, int la
     }
 }
 
+template <int MODE, bool FACT>
+__device__ __forceinline__ void row_sweep_masked(const float4 *__restrict__ rec, const double *__restrict__ rtd,
+                                                 double tsi, int lane, float ti, int xr, int yr,
+                                                 int irow, int gr, int c, int wave_chunk, int wave_gmin,
+                                                 const PairConst kc, float (&blk)[HK_NROW],
+                                                 float (&C)[HK_NCOL], double &B0d, double &X0c, double &C0d) {
+    const int cbase = c * HK_WAVE;
+    if (c == wave_chunk)
+        row_sweep<MODE, true, true, FACT>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+    else if (cbase + HK_WAVE - 1 >= wave_gmin)
+        row_sweep<MODE, false, true, FACT>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+    else
+        row_sweep<MODE, false, false, FACT>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+}
+
 template <int MODE>
 __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, const int *__restrict__ xi,
                                                   const int *__restrict__ yi, const float *__restrict__ theta_s,
                                                   const int *__restrict__ g, const hk_item *__restrict__ items,
+                                                  const int *__restrict__ block0,
                                                   const int64_t *__restrict__ colpart_off,
-                                                  double *__restrict__ rowpart, float *__restrict__ colpart,
-                                                  double *__restrict__ colpart0, const PairConst kc) {
+                                                  float *__restrict__ rowpart, float *__restrict__ colpart,
+                                                  const PairConst kc) {
     __shared__ float4 rec[2 * HK_WAVE];
+    __shared__ double rtd[2 * HK_WAVE];
     __shared__ float colbuf[HK_WAVES][HK_NCOL][HK_WAVE];
     __shared__ double colbuf0[HK_WAVES][HK_WAVE];
+    __shared__ int fact_sh;
     constexpr int NC = MODE == HK_MODE_LOGLIK ? 1 : (MODE == HK_MODE_GRAD ? 3 : 5);
-
-    const hk_item it = items[blockIdx.x];
-    const int I = it.tile;
     const int tid = threadIdx.x, lane = tid & (HK_WAVE - 1), wv = tid / HK_WAVE;
-    const int64_t row0 = (int64_t)I * HK_TILE;
-    const int irow = (int)(row0 + tid);
-    const double tsi = ts[irow];
-    const int xr = xi[irow], yr = yi[irow], gr = g[irow];
-    const int wave_chunk = I * HK_CHUNKS_PER_TILE + wv;
-    const int wave_gmin = g[(int64_t)wave_chunk * HK_WAVE];  // g is non-decreasing
-    const int64_t stride = (int64_t)(I + 1) * HK_TILE;
-    float *__restrict__ cp = colpart + colpart_off[I];
-    double *__restrict__ cp0 = colpart0 + colpart_off[I] / HK_NCOL;
+    const int q_end = block0[blockIdx.x + 1];
 
-    float hi[HK_NROW], lo[HK_NROW];
-#pragma unroll
-    for (int a = 0; a < HK_NROW; ++a) hi[a] = lo[a] = 0.0f;
-    double B0d = 0.0, X0d = 0.0;
+    for (int q = block0[blockIdx.x]; q < q_end; ++q) {
+        const hk_item it = items[q];
+        const int I = it.tile;
+        const int64_t row0 = (int64_t)I * HK_TILE;
+        const int irow = (int)(row0 + tid);
+        const double tsi = ts[irow];
+        const int xr = xi[irow], yr = yi[irow], gr = g[irow];
+        const int wave_chunk = I * HK_CHUNKS_PER_TILE + wv;
+        const int wave_gmin = g[(int64_t)wave_chunk * HK_WAVE];  // g is non-decreasing
+        const int64_t stride = (int64_t)(I + 1) * HK_TILE;
+        float *__restrict__ cp = colpart + colpart_off[I];
 
-    for (int c = it.c_begin; c < it.c_end; ++c) {
-        // times relative to the chunk's first event: for the pairs that carry the
-        // sums (close in time) both operands of dt are then small and exact to FP32
-        const double Tc = ts[(int64_t)c * HK_WAVE];
-        const float ti = (float)(tsi - Tc);
-        if (tid < HK_WAVE) {
-            const int64_t j = (int64_t)c * HK_WAVE + tid;
-            float4 r;
-            r.x = (float)(ts[j] - Tc);
-            r.y = __int_as_float(xi[j]);
-            r.z = __int_as_float(yi[j]);
-            r.w = theta_s[j];
-            rec[tid] = r;
-            rec[tid + HK_WAVE] = r;
-        }
-        __syncthreads();
-        float blk[HK_NROW], C[HK_NCOL];
-        double C0d = 0.0;
+        float hi[HK_NROW], lo[HK_NROW];
 #pragma unroll
-        for (int a = 0; a < HK_NROW; ++a) blk[a] = 0.0f;
+        for (int a = 0; a < HK_NROW; ++a) hi[a] = lo[a] = 0.0f;
+        double B0d = 0.0, X0d = 0.0;
+
+        for (int c = it.c_begin; c < it.c_end; ++c) {
+            // times relative to the chunk's first event: for the pairs that carry
+            // the sums (close in time) both operands of dt are then small and
+            // exact to FP32
+            const double Tc = ts[(int64_t)c * HK_WAVE];
+            const float ti = (float)(tsi - Tc);
+            if (tid < HK_WAVE) {
+                // the staging threads are wavefront 0: one vote decides the split
+                const int64_t j = (int64_t)c * HK_WAVE + tid;
+                const double dtj = ts[j] - Tc;
+                const float th = theta_s[j];
+                const bool wide = th > 0.0f && kc.omega * dtj > HK_FACT_SPAN;
+                const bool fact = !__any(wide);
+                float4 r;
+                r.x = (float)dtj;
+                r.y = __int_as_float(xi[j]);
+                r.z = __int_as_float(yi[j]);
+                r.w = (fact && th > 0.0f) ? (float)((double)th * exp(kc.omega * dtj)) : th;
+                rec[tid] = r;
+                rec[tid + HK_WAVE] = r;
+                rtd[tid] = rtd[tid + HK_WAVE] = ts[j];
+                if (tid == 0) fact_sh = fact;
+            }
+            __syncthreads();
+            const bool fact = fact_sh != 0;
+            float blk[HK_NROW], C[HK_NCOL];
+            double C0d = 0.0, X0c = 0.0;
 #pragma unroll
-        for (int a = 0; a < HK_NCOL; ++a) C[a] = 0.0f;
-        if (c <= wave_chunk) {
-            const int cbase = c * HK_WAVE;
-            if (c == wave_chunk)
-                row_sweep<MODE, true, true>(rec, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0d, C0d);
-            else if (cbase + HK_WAVE - 1 >= wave_gmin)
-                row_sweep<MODE, false, true>(rec, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0d, C0d);
-            else
-                row_sweep<MODE, false, false>(rec, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0d, C0d);
-        }
-        // after 64 rotation steps lane l holds the accumulators of column (l - 1) mod 64
-        const int col = (lane + HK_WAVE - 1) & (HK_WAVE - 1);
-        colbuf0[wv][col] = C0d;
+            for (int a = 0; a < HK_NROW; ++a) blk[a] = 0.0f;
 #pragma unroll
-        for (int a = 1; a < NC; ++a) colbuf[wv][a][col] = C[a];
-        __syncthreads();
-        for (int q = tid; q < NC * HK_WAVE; q += HK_TILE) {
-            const int a = q / HK_WAVE, cc = q % HK_WAVE;
-            if (a == 0) {
-                cp0[(int64_t)c * HK_WAVE + cc] = ((colbuf0[0][cc] + colbuf0[1][cc]) + colbuf0[2][cc]) + colbuf0[3][cc];
-            } else {
-                const float v = ((colbuf[0][a][cc] + colbuf[1][a][cc]) + colbuf[2][a][cc]) + colbuf[3][a][cc];
+            for (int a = 0; a < HK_NCOL; ++a) C[a] = 0.0f;
+            if (c <= wave_chunk) {
+                if (fact)
+                    row_sweep_masked<MODE, true>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
+                                                 blk, C, B0d, X0c, C0d);
+                else
+                    row_sweep_masked<MODE, false>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
+                                                  blk, C, B0d, X0c, C0d);
+                // the row's time factor (t_i >= T_c here, so it is at most 1)
+                const double ui = fact ? exp(-kc.omega * (tsi - Tc)) : 1.0;
+                X0d += ui * X0c;
+                const float uf = (float)ui;
+#pragma unroll
+                for (int a = 6; a < HK_NROW; ++a) blk[a] *= uf;
+            }
+            // after 64 rotation steps lane l holds the accumulators of column (l - 1) mod 64
+            const int col = (lane + HK_WAVE - 1) & (HK_WAVE - 1);
+            colbuf0[wv][col] = C0d;
+#pragma unroll
+            for (int a = 1; a < NC; ++a) colbuf[wv][a][col] = C[a];
+            __syncthreads();
+            // partial sums are stored rounded to FP32 once (unbiased, relative
+            // 2^-24 each) and summed in FP64 by the finalisation
+            for (int e = tid; e < NC * HK_WAVE; e += HK_TILE) {
+                const int a = e / HK_WAVE, cc = e % HK_WAVE;
+                float v;
+                if (a == 0)
+                    v = (float)(((colbuf0[0][cc] + colbuf0[1][cc]) + colbuf0[2][cc]) + colbuf0[3][cc]);
+                else
+                    v = ((colbuf[0][a][cc] + colbuf[1][a][cc]) + colbuf[2][a][cc]) + colbuf[3][a][cc];
                 cp[a * stride + (int64_t)c * HK_WAVE + cc] = v;
             }
+#pragma unroll
+            for (int a = 0; a < HK_NROW; ++a) {
+                const bool used = (MODE >= HK_MODE_GRAD && (a == 1 || a == 2 || a == 6 || a == 7)) ||
+                                  (MODE >= HK_MODE_HESS && a != 0 && a != 5);
+                if (used) two_sum_acc(hi[a], lo[a], blk[a]);
+            }
         }
+        float *__restrict__ rp = rowpart + (int64_t)q * HK_NROW * HK_TILE;
+        rp[tid] = (float)B0d;
+        rp[5 * HK_TILE + tid] = (float)X0d;
 #pragma unroll
         for (int a = 0; a < HK_NROW; ++a) {
             const bool used = (MODE >= HK_MODE_GRAD && (a == 1 || a == 2 || a == 6 || a == 7)) ||
                               (MODE >= HK_MODE_HESS && a != 0 && a != 5);
-            if (used) two_sum_acc(hi[a], lo[a], blk[a]);
+            if (used) rp[a * HK_TILE + tid] = (float)((double)hi[a] + (double)lo[a]);
         }
-    }
-    double *__restrict__ rp = rowpart + (int64_t)blockIdx.x * HK_NROW * HK_TILE;
-    rp[tid] = B0d;
-    rp[5 * HK_TILE + tid] = X0d;
-#pragma unroll
-    for (int a = 0; a < HK_NROW; ++a) {
-        const bool used = (MODE >= HK_MODE_GRAD && (a == 1 || a == 2 || a == 6 || a == 7)) ||
-                          (MODE >= HK_MODE_HESS && a != 0 && a != 5);
-        if (used) rp[a * HK_TILE + tid] = (double)hi[a] + (double)lo[a];
     }
 }
 
@@ -303,29 +360,30 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 __device__ __forceinline__ double std_pdf(double u) { return 0.3989422804014327 * exp(-0.5 * u * u); }
 __device__ __forceinline__ double std_cdf(double u) { return 0.5 * erfc(-u * 0.7071067811865476); }
 
+// Finalisation, one block per 64-event chunk.  The four wavefronts first split
+// the partial sums of the chunk's events between them (row pieces and column
+// partials of the later row tiles, round robin), the partials are combined in a
+// fixed order through LDS, and the first wavefront finishes the events.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, const double *__restrict__ theta,
                                              const int *__restrict__ perm, int64_t n, int ntiles,
                                              const int *__restrict__ row_item0, const int *__restrict__ row_nseg,
-                                             const double *__restrict__ rowpart, const float *__restrict__ colpart,
-                                             const double *__restrict__ colpart0,
+                                             const float *__restrict__ rowpart, const float *__restrict__ colpart,
                                              const int64_t *__restrict__ colpart_off, const FinConst fc,
                                              double *__restrict__ lam, float *__restrict__ w, float *__restrict__ wlo,
                                              double *__restrict__ a_out,
                                              double *__restrict__ blockpart, int *__restrict__ status) {
-    __shared__ double sh[HK_WAVES][HK_NSUM];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    double s[HK_NSUM];
-#pragma unroll
-    for (int k = 0; k < HK_NSUM; ++k) s[k] = 0.0;
-    if (i < n) {
-        const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
+    __shared__ double part[HK_WAVES][HK_NROW][HK_WAVE];
+    const int lane = threadIdx.x & (HK_WAVE - 1), wv = threadIdx.x / HK_WAVE;
+    const int64_t i = (int64_t)blockIdx.x * HK_WAVE + lane;
+    const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
+    {
         double acc[HK_NROW];
 #pragma unroll
         for (int k = 0; k < HK_NROW; ++k) acc[k] = 0.0;
         const int it0 = row_item0[I], ns = row_nseg[I];
-        for (int sg = 0; sg < ns; ++sg) {
-            const double *rp = rowpart + (int64_t)(it0 + sg) * HK_NROW * HK_TILE + r;
+        for (int sg = wv; sg < ns; sg += HK_WAVES) {
+            const float *rp = rowpart + (int64_t)(it0 + sg) * HK_NROW * HK_TILE + r;
             acc[0] += rp[0];
             acc[5] += rp[5 * HK_TILE];
             if (MODE >= HK_MODE_GRAD) {
@@ -341,11 +399,11 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
                 acc[9] += rp[9 * HK_TILE];
             }
         }
-        // background from later events: the column partials of tiles I' >= I
-        for (int J = I; J < ntiles; ++J) {
+        // background from later events: the column partials of row tiles J >= I
+        for (int J = I + wv; J < ntiles; J += HK_WAVES) {
             const int64_t stride = (int64_t)(J + 1) * HK_TILE;
             const float *cp = colpart + colpart_off[J] + i;
-            acc[0] += colpart0[colpart_off[J] / HK_NCOL + i];
+            acc[0] += (double)cp[0];
             if (MODE >= HK_MODE_GRAD) {
                 acc[1] += (double)cp[stride];
                 acc[2] += (double)cp[2 * stride];
@@ -355,13 +413,27 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
                 acc[4] += (double)cp[4 * stride];
             }
         }
+#pragma unroll
+        for (int k = 0; k < HK_NROW; ++k) part[wv][k][lane] = acc[k];
+    }
+    __syncthreads();
+    if (wv != 0) return;
+
+    double s[HK_NSUM];
+#pragma unroll
+    for (int k = 0; k < HK_NSUM; ++k) s[k] = 0.0;
+    if (i < n) {
+        double acc[HK_NROW];
+#pragma unroll
+        for (int k = 0; k < HK_NROW; ++k)
+            acc[k] = ((part[0][k][lane] + part[1][k][lane]) + part[2][k][lane]) + part[3][k][lane];
         // moments corrected for the mean exp2 bias and, when the first moments
         // are present, for the rounding of the FP32 exponent constants
         double b0 = acc[0], x0 = acc[5];
         if (MODE >= HK_MODE_GRAD) {
             const double ln2 = 0.6931471805599453;
             b0 -= ln2 * (fc.rho_bx * acc[1] + fc.dkbt * acc[2]);
-            x0 -= ln2 * (fc.dkw * acc[6] + fc.rho_ex * acc[7]);
+            x0 -= ln2 * fc.rho_ex * acc[7];
         }
         const double B0 = b0 * fc.corr, X0 = x0 * fc.corr;
         const double lamv = fc.c_b * B0 + fc.c_e * X0;
@@ -393,13 +465,14 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
             if (MODE >= HK_MODE_HESS) {
                 const double B11 = acc[3] * fc.corr * fc.Kx * fc.Kx, B22 = acc[4] * fc.corr;
                 const double X11 = acc[8] * fc.corr, X22 = acc[9] * fc.corr * fc.Kh * fc.Kh;
+                const double tx2 = tx * tx, tt2 = tt * tt, hh2 = hh * hh;
                 double d2[6];
                 d2[0] = 0.0;
-                d2[1] = fc.c_b * (6.0 * B0 / (tx * tx) - 7.0 * B1 / (tx * tx * tx * tx) + B11 / pow(tx, 6));
-                d2[2] = fc.c_b * (2.0 * B0 / (tt * tt) - 5.0 * B2 / (tt * tt * tt * tt) + B22 / pow(tt, 6));
+                d2[1] = fc.c_b * (6.0 * B0 / tx2 - 7.0 * B1 / (tx2 * tx2) + B11 / (tx2 * tx2 * tx2));
+                d2[2] = fc.c_b * (2.0 * B0 / tt2 - 5.0 * B2 / (tt2 * tt2) + B22 / (tt2 * tt2 * tt2));
                 d2[3] = 0.0;
                 d2[4] = fc.c_e * (X11 - 2.0 * X1 / om);
-                d2[5] = fc.c_e * (6.0 * X0 / (hh * hh) - 7.0 * X2 / (hh * hh * hh * hh) + X22 / pow(hh, 6));
+                d2[5] = fc.c_e * (6.0 * X0 / hh2 - 7.0 * X2 / (hh2 * hh2) + X22 / (hh2 * hh2 * hh2));
 #pragma unroll
                 for (int p = 0; p < 6; ++p) s[7 + p] = d2[p] * inv - s[1 + p] * s[1 + p];
             }
@@ -423,43 +496,61 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
             s[18] = fc.mu0 * (p1 * (2.0 * u1 - u1 * u1 * u1) - p0 * (2.0 * u0 - u0 * u0 * u0)) / (fc.tau_t * fc.tau_t);
             s[19] = -fc.theta0 * th * sv * sv * e;
         }
-    } else if (i < (int64_t)ntiles * HK_TILE) {
+    } else {
         lam[i] = 1.0;
         w[i] = 0.0f;
         wlo[i] = 0.0f;
         a_out[i] = 0.0;
     }
-    const int lane = threadIdx.x & (HK_WAVE - 1), wv = threadIdx.x / HK_WAVE;
 #pragma unroll
     for (int k = 0; k < HK_NSUM; ++k) {
         const double v = wave_sum_f64(s[k]);
-        if (lane == 0) sh[wv][k] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < HK_NSUM) {
-        const int k = threadIdx.x;
-        blockpart[(int64_t)blockIdx.x * HK_NSUM + k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
+        if (lane == k) blockpart[(int64_t)k * gridDim.x + blockIdx.x] = v;
     }
 }
 
-__global__ void k_fin2(const double *__restrict__ blockpart, int nblocks, double *__restrict__ loglik,
-                       double *__restrict__ grad_hyper, double *__restrict__ negH_hyper,
-                       int *__restrict__ status) {
+// Knuth's TwoSum in FP64: the exact rounding error of a + b (independent of
+// the order of the operands).
+__device__ __forceinline__ double two_sum_err(double a, double b, double s) {
+    const double bp = s - a;
+    return (a - (s - bp)) + (b - bp);
+}
+
+// The per-block partials ([HK_NSUM][nblocks]) -> loglik and the
+// hyperparameter derivatives, in one block of HK_NSUM half-wavefronts: lane l of
+// sum k keeps a Neumaier sum over blocks l, l + 32, ... (coalesced loads, all in
+// flight together), then the 32 lanes of the sum combine by a butterfly of
+// exact TwoSum steps, so that the result is fixed whatever the timing.
+constexpr int HK_FIN2_LANES = 32;
+
+__global__ __launch_bounds__(HK_NSUM * HK_FIN2_LANES) void k_fin2(const double *__restrict__ blockpart,
+                                                                  int nblocks, double *__restrict__ loglik,
+                                                                  double *__restrict__ grad_hyper,
+                                                                  double *__restrict__ negH_hyper,
+                                                                  int *__restrict__ status) {
     __shared__ double tot[HK_NSUM];
-    const int k = threadIdx.x;
-    if (k < HK_NSUM) {
-        double sum = 0.0, c = 0.0, plain = 0.0;  // Neumaier, fixed order
-        for (int b = 0; b < nblocks; ++b) {
-            const double v = blockpart[(int64_t)b * HK_NSUM + k];
-            const double t = sum + v;
-            plain += v;
-            c += fabs(sum) >= fabs(v) ? (sum - t) + v : (v - t) + sum;
-            sum = t;
-        }
-        tot[k] = isfinite(plain) ? sum + c : plain;
+    const int k = threadIdx.x / HK_FIN2_LANES, l = threadIdx.x % HK_FIN2_LANES;
+    const double *part = blockpart + (int64_t)k * nblocks;
+    double sum = 0.0, c = 0.0, plain = 0.0;
+#pragma unroll 4
+    for (int b = l; b < nblocks; b += HK_FIN2_LANES) {
+        const double v = part[b];
+        const double t = sum + v;
+        c += two_sum_err(sum, v, t);
+        sum = t;
+        plain += v;
     }
+#pragma unroll
+    for (int off = 1; off < HK_FIN2_LANES; off <<= 1) {
+        const double s2 = __shfl_xor(sum, off), c2 = __shfl_xor(c, off), p2 = __shfl_xor(plain, off);
+        const double t = sum + s2;
+        c = (c + c2) + two_sum_err(sum, s2, t);
+        sum = t;
+        plain += p2;
+    }
+    if (l == 0) tot[k] = isfinite(plain) ? sum + c : plain;
     __syncthreads();
-    if (k == 0) {
+    if (threadIdx.x == 0) {
         const double ll = tot[0] - tot[13];
         if (loglik) loglik[0] = ll;
         if (isnan(ll)) atomicOr(status, HK_ST_NONFINITE);
@@ -475,35 +566,36 @@ __global__ void k_fin2(const double *__restrict__ blockpart, int nblocks, double
 }
 
 // ------------------------------------------------------------------------------------
-// Column pass.  Each term E_ij w_i is formed to about FP32 rounding: w_i is a
-// (hi, lo) pair, times are rebased per 64-row chunk, and Eq. 4 (squared terms)
-// carries two extra moments, sum (E w)^2 dt and sum (E w)^2 a_e, from which the
-// FP64 finalisation removes the bias of the rounded exponent constants.
-template <bool WITH_H, bool MASKED>
-__device__ __forceinline__ void col_sweep(const float4 *__restrict__ rrec, const float *__restrict__ rwlo,
-                                          const int *__restrict__ rg, int jcol, float tj, int xj, int yj,
-                                          const PairConst kc, float &G, float &H, float &Hdt, float &Hae) {
+// Column pass.  G_j = sum_{t_i > t_j} E_ij w_i and H_j = sum (E_ij w_i)^2 for the
+// lanes' columns j against a staged chunk of 64 later rows i.  With the time
+// factorisation the staged row carries v_i = w_i exp(-omega (t_i - T_c)) as an
+// FP32 (hi, lo) pair and the lane applies u_j = exp(omega (t_j - T_c)) to its
+// chunk sums; the spatial exponent is formed in FP64 and rounded once, so that
+// each term E_ij w_i is good to a few FP32 roundings (H squares it, which
+// doubles its relative error, and an absolute rounding of the exponent becomes
+// a relative error of the term, so the exponent must not carry more).
+template <bool WITH_H, bool MASKED, bool FACT>
+__device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const float2 *__restrict__ rv,
+                                          const double *__restrict__ rtd, const int *__restrict__ rg, int jcol,
+                                          double tsj, double xj, double yj, const PairConst kc, float &G, float &H) {
 #pragma clang fp contract(off)
 #pragma unroll 16
     for (int s = 0; s < HK_WAVE; ++s) {
-        const float4 r = rrec[s];
-        const float dt = r.x - tj;
-        const float dx = (float)(__float_as_int(r.y) - xj);
-        const float dy = (float)(__float_as_int(r.z) - yj);
-        const float r2 = fmaf(dx, dx, dy * dy);
-        const float ae = r2 * kc.kex;
-        float E = fexp2(fmaf(dt, kc.kw, ae));
+        // coordinates pre-scaled in FP64, so that the spatial exponent is minus a
+        // squared distance, formed in FP64 and rounded once
+        const double2 p = rxy[s];
+        const double dx = p.x - xj, dy = p.y - yj;
+        const double aed = -fma(dx, dx, dy * dy);
+        // with the time term when the chunk is too wide for the split
+        const float E = fexp2(FACT ? (float)aed : (float)fma(rtd[s] - tsj, kc.kw_d, aed));
+        float Em = E;
         if (MASKED) {
-            if (!(jcol < rg[s])) E = 0.0f;
+            if (!(jcol < rg[s])) Em = 0.0f;
         }
-        const float ew = fmaf(E, rwlo[s], E * r.w);
+        const float2 v = rv[s];
+        const float ew = fmaf(Em, v.y, Em * v.x);
         G += ew;
-        if (WITH_H) {
-            const float e2 = ew * ew;
-            H += e2;
-            Hdt = fmaf(e2, dt, Hdt);
-            Hae = fmaf(e2, ae, Hae);
-        }
+        if (WITH_H) H = fmaf(ew, ew, H);
     }
 }
 
@@ -511,82 +603,100 @@ template <bool WITH_H>
 __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, const int *__restrict__ xi,
                                                   const int *__restrict__ yi, const float *__restrict__ w,
                                                   const float *__restrict__ wlo, const int *__restrict__ g,
-                                                  const hk_item *__restrict__ items, double *__restrict__ colG,
-                                                  const PairConst kc) {
-    __shared__ float4 rrec[HK_WAVE];
-    __shared__ float rwlo[HK_WAVE];
+                                                  const hk_item *__restrict__ items, const int *__restrict__ block0,
+                                                  double *__restrict__ colG, const PairConst kc) {
+    __shared__ double2 rxy[HK_WAVE];
+    __shared__ float2 rv[HK_WAVE];
+    __shared__ double rtd[HK_WAVE];
     __shared__ int rg[HK_WAVE];
-    const hk_item it = items[blockIdx.x];
-    const int J = it.tile;
+    __shared__ int fact_sh;
     const int tid = threadIdx.x, wv = tid / HK_WAVE;
-    const int64_t col0 = (int64_t)J * HK_TILE;
-    const int jcol = (int)(col0 + tid);
-    const double tsj = ts[jcol];
-    const int xj = xi[jcol], yj = yi[jcol];
-    const int wave_first = (int)(col0 + wv * HK_WAVE);
+    const int q_end = block0[blockIdx.x + 1];
 
-    float Gh = 0.0f, Gl = 0.0f, Hh = 0.0f, Hl = 0.0f, Hdt = 0.0f, Hae = 0.0f;
-    for (int c = it.c_begin; c < it.c_end; ++c) {
-        const double Tc = ts[(int64_t)c * HK_WAVE];
-        if (tid < HK_WAVE) {
-            const int64_t i = (int64_t)c * HK_WAVE + tid;
-            float4 r;
-            r.x = (float)(ts[i] - Tc);
-            r.y = __int_as_float(xi[i]);
-            r.z = __int_as_float(yi[i]);
-            r.w = w[i];
-            rrec[tid] = r;
-            rwlo[tid] = wlo[i];
-            rg[tid] = g[i];
+    for (int q = block0[blockIdx.x]; q < q_end; ++q) {
+        const hk_item it = items[q];
+        const int J = it.tile;
+        const int64_t col0 = (int64_t)J * HK_TILE;
+        const int jcol = (int)(col0 + tid);
+        const double tsj = ts[jcol];
+        const double xj = (double)xi[jcol] * kc.sx, yj = (double)yi[jcol] * kc.sx;
+        const int wave_first = (int)(col0 + wv * HK_WAVE);
+
+        double Gd = 0.0, Hd = 0.0;
+        for (int c = it.c_begin; c < it.c_end; ++c) {
+            const double Tc = ts[(int64_t)c * HK_WAVE];
+            if (tid < HK_WAVE) {
+                // the staging threads are wavefront 0: one vote decides the split
+                const int64_t i = (int64_t)c * HK_WAVE + tid;
+                const double ti = ts[i];
+                const double dti = ti - Tc;
+                const double wd = (double)w[i] + (double)wlo[i];
+                const bool wide = wd > 0.0 && kc.omega * dti > HK_FACT_SPAN;
+                const bool fact = !__any(wide);
+                const double v = fact ? wd * exp(-kc.omega * dti) : wd;
+                const float vhi = (float)v;
+                rxy[tid] = make_double2((double)xi[i] * kc.sx, (double)yi[i] * kc.sx);
+                rv[tid] = make_float2(vhi, (float)(v - (double)vhi));
+                rtd[tid] = ti;
+                rg[tid] = g[i];
+                if (tid == 0) fact_sh = fact;
+            }
+            __syncthreads();
+            const int gmax = rg[HK_WAVE - 1], gmin = rg[0];
+            if (gmax > wave_first) {
+                const bool fact = fact_sh != 0;
+                float G = 0.0f, H = 0.0f;
+                const bool masked = gmin <= wave_first + HK_WAVE - 1;
+                if (fact) {
+                    if (masked) col_sweep<WITH_H, true, true>(rxy, rv, rtd, rg, jcol, tsj, xj, yj, kc, G, H);
+                    else col_sweep<WITH_H, false, true>(rxy, rv, rtd, rg, jcol, tsj, xj, yj, kc, G, H);
+                } else {
+                    if (masked) col_sweep<WITH_H, true, false>(rxy, rv, rtd, rg, jcol, tsj, xj, yj, kc, G, H);
+                    else col_sweep<WITH_H, false, false>(rxy, rv, rtd, rg, jcol, tsj, xj, yj, kc, G, H);
+                }
+                // a column with a causal pair here has t_j < t_i <= T_c + span, so
+                // its factor is finite; the others have nothing to scale
+                if (G != 0.0f) {
+                    const double uj = fact ? exp(kc.omega * (tsj - Tc)) : 1.0;
+                    Gd += uj * (double)G;
+                    if (WITH_H) Hd += (uj * uj) * (double)H;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        const int gmax = rg[HK_WAVE - 1], gmin = rg[0];
-        if (gmax > wave_first) {
-            const float tj = (float)(tsj - Tc);
-            float G = 0.0f, H = 0.0f;
-            if (gmin <= wave_first + HK_WAVE - 1)
-                col_sweep<WITH_H, true>(rrec, rwlo, rg, jcol, tj, xj, yj, kc, G, H, Hdt, Hae);
-            else
-                col_sweep<WITH_H, false>(rrec, rwlo, rg, jcol, tj, xj, yj, kc, G, H, Hdt, Hae);
-            two_sum_acc(Gh, Gl, G);
-            if (WITH_H) two_sum_acc(Hh, Hl, H);
-        }
-        __syncthreads();
-    }
-    double *cg = colG + (int64_t)blockIdx.x * 4 * HK_TILE;
-    cg[tid] = (double)Gh + (double)Gl;
-    if (WITH_H) {
-        cg[HK_TILE + tid] = (double)Hh + (double)Hl;
-        cg[2 * HK_TILE + tid] = (double)Hdt;
-        cg[3 * HK_TILE + tid] = (double)Hae;
+        double *cg = colG + (int64_t)q * 2 * HK_TILE;
+        cg[tid] = Gd;
+        if (WITH_H) cg[HK_TILE + tid] = Hd;
     }
 }
 
-__global__ void k_colfin(const int *__restrict__ perm, int64_t n, const int *__restrict__ col_item0,
-                         const int *__restrict__ col_nseg, const double *__restrict__ colG,
-                         const double *__restrict__ a, const FinConst fc, double *__restrict__ grad_theta,
-                         double *__restrict__ negH_theta) {
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// Column finalisation, one block per 64-event chunk: the wavefronts split the
+// column pieces round robin, then the first combines them in a fixed order.
+__global__ __launch_bounds__(256) void k_colfin(const int *__restrict__ perm, int64_t n,
+                                                const int *__restrict__ col_item0, const int *__restrict__ col_nseg,
+                                                const double *__restrict__ colG, const double *__restrict__ a,
+                                                const FinConst fc, double *__restrict__ grad_theta,
+                                                double *__restrict__ negH_theta) {
+    __shared__ double part[HK_WAVES][2][HK_WAVE];
+    const int lane = threadIdx.x & (HK_WAVE - 1), wv = threadIdx.x / HK_WAVE;
+    const int64_t j = (int64_t)blockIdx.x * HK_WAVE + lane;
     const int J = (int)(j / HK_TILE), r = (int)(j % HK_TILE);
     const int it0 = col_item0[J], ns = col_nseg[J];
-    double G = 0.0, H = 0.0, Hdt = 0.0, Hae = 0.0;
-    for (int sg = 0; sg < ns; ++sg) {
-        const double *cg = colG + (int64_t)(it0 + sg) * 4 * HK_TILE + r;
+    double G = 0.0, H = 0.0;
+    for (int sg = wv; sg < ns; sg += HK_WAVES) {
+        const double *cg = colG + (int64_t)(it0 + sg) * 2 * HK_TILE + r;
         G += cg[0];
-        if (negH_theta) {
-            H += cg[HK_TILE];
-            Hdt += cg[2 * HK_TILE];
-            Hae += cg[3 * HK_TILE];
-        }
+        if (negH_theta) H += cg[HK_TILE];
     }
+    part[wv][0][lane] = G;
+    part[wv][1][lane] = H;
+    __syncthreads();
+    if (wv != 0 || j >= n) return;
+    const double Gs = ((part[0][0][lane] + part[1][0][lane]) + part[2][0][lane]) + part[3][0][lane];
+    const double Hs = ((part[0][1][lane] + part[1][1][lane]) + part[2][1][lane]) + part[3][1][lane];
     const int dst = perm[j];
-    if (grad_theta) grad_theta[dst] = G * fc.corr - a[j];
-    if (negH_theta) {
-        const double ln2 = 0.6931471805599453;
-        H -= 2.0 * ln2 * (fc.dkw * Hdt + fc.rho_ex * Hae);
-        negH_theta[dst] = H * fc.corr * fc.corr;
-    }
+    if (grad_theta) grad_theta[dst] = Gs * fc.corr - a[j];
+    if (negH_theta) negH_theta[dst] = Hs * fc.corr * fc.corr;
 }
 
 __global__ void k_scatter_lambda(const double *__restrict__ lam, const int *__restrict__ perm, int64_t n,
@@ -617,9 +727,13 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     kc->kbt = (float)kbt;
     kc->kex = (float)kex;
     kc->kw = (float)kw;
+    kc->cw = (float)(ln2 * (kw - (double)kc->kw));
+    kc->omega = hy->omega;
+    kc->kex_d = kex;
+    kc->kw_d = kw;
+    kc->sx = sqrt(-kex);
     fc->rho_bx = ((double)kc->kbx - kbx) / (double)kc->kbx;
     fc->dkbt = (double)kc->kbt - kbt;
-    fc->dkw = (double)kc->kw - kw;
     fc->rho_ex = ((double)kc->kex - kex) / (double)kc->kex;
     const double corr = 1.0 / (1.0 + HK_EXP2_BIAS);
     const double two_pi = 6.283185307179586;
@@ -656,11 +770,12 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
                        p->theta_s, p->status);
     hk_prof_mark(p, HK_PROF_ROW, true, stream);
 #define HK_ROW(M)                                                                                              \
-    hipLaunchKernelGGL(k_row<M>, dim3(p->n_row_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->theta_s, \
-                       p->g, p->row_items, p->colpart_off, p->rowpart, p->colpart, p->colpart0, kc)
+    hipLaunchKernelGGL(k_row<M>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,          \
+                       p->theta_s, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart, p->colpart,   \
+                       kc)
 #define HK_FIN(M)                                                                                              \
-    hipLaunchKernelGGL(k_fin<M>, dim3(p->nfin_blocks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->n,      \
-                       p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart0, p->colpart_off, fc, \
+    hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->n,          \
+                       p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart_off, fc,             \
                        p->lam, p->w, p->wlo, p->a, p->blockpart, p->status)
     if (mode == HK_MODE_GRAD) HK_ROW(HK_MODE_GRAD);
     else HK_ROW(HK_MODE_HESS);
@@ -669,19 +784,19 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
     else HK_FIN(HK_MODE_HESS);
 #undef HK_ROW
 #undef HK_FIN
-    hipLaunchKernelGGL(k_fin2, dim3(1), dim3(64), 0, stream, p->blockpart, p->nfin_blocks, d_loglik, d_grad_hyper,
-                       d_negH_hyper, p->status);
+    hipLaunchKernelGGL(k_fin2, dim3(1), dim3(HK_NSUM * HK_FIN2_LANES), 0, stream, p->blockpart, p->nchunks,
+                       d_loglik, d_grad_hyper, d_negH_hyper, p->status);
     if (d_grad_theta || d_negH_theta) {
         hk_prof_mark(p, HK_PROF_COL, true, stream);
         if (d_negH_theta)
-            hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                               p->w, p->wlo, p->g, p->col_items, p->colG, kc);
+            hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
+                               p->w, p->wlo, p->g, p->col_items, p->col_block0, p->colG, kc);
         else
-            hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                               p->w, p->wlo, p->g, p->col_items, p->colG, kc);
+            hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
+                               p->w, p->wlo, p->g, p->col_items, p->col_block0, p->colG, kc);
         hk_prof_mark(p, HK_PROF_COL, false, stream);
-        hipLaunchKernelGGL(k_colfin, dim3((unsigned)((p->n + 255) / 256)), dim3(256), 0, stream, p->perm, p->n,
-                           p->col_item0, p->col_nseg, p->colG, p->a, fc, d_grad_theta, d_negH_theta);
+        hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(256), 0, stream, p->perm, p->n, p->col_item0,
+                           p->col_nseg, p->colG, p->a, fc, d_grad_theta, d_negH_theta);
     }
     hk_prof_mark(p, HK_PROF_EVAL, false, stream);
     HK_CHECK(hipGetLastError());
@@ -689,8 +804,25 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 }
 
 void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream) {
-    hipLaunchKernelGGL(k_row<HK_MODE_GRAD>, dim3(p->n_row_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                       p->theta_s, p->g, p->row_items, p->colpart_off, p->rowpart, p->colpart, p->colpart0, kc);
+    hipLaunchKernelGGL(k_row<HK_MODE_GRAD>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
+                       p->theta_s, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart, p->colpart, kc);
+}
+
+// Blocks per compute unit in the pair-pass schedules.  Eight blocks of four
+// wavefronts fill a CU of gfx950 at the register footprints of k_row and k_col;
+// two rounds of equal-weight blocks measured faster than one (the hardware
+// dispatcher then evens out the blocks' run-time differences), while more
+// rounds cost more partial-sum traffic than they gain.
+#ifndef HK_BLOCKS_PER_CU
+#define HK_BLOCKS_PER_CU 16
+#endif
+
+int64_t hk_pass_slots(int device, int pass) {
+    (void)pass;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+        cus = 256;
+    return (int64_t)cus * HK_BLOCKS_PER_CU;
 }
 
 extern "C" hawkes_status hawkes_loglik(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,

@@ -49,7 +49,7 @@ struct hk_subset {
     // per-evaluation buffers
     float *theta32;      // [mpad] subset rates, time order
     double *xs;          // [npad] subset excitation sums per event
-    float *xmom;         // [npad][2] sum theta E dt, sum theta E a_e per event
+    float *xmom;         // [npad] sum theta E a_e per event (spatial-constant rounding)
     double *colG;        // [n_items][2][HK_TILE]
     double *gsub;        // [mpad] Eq. 3 on the subset, time order
     double *hsub;        // [mpad] Eq. 4 on the subset, time order
@@ -155,9 +155,8 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
                                                     const int *__restrict__ perm, const float *__restrict__ theta_s,
                                                     int64_t n, int ntiles, const int *__restrict__ row_item0,
                                                     const int *__restrict__ row_nseg,
-                                                    const double *__restrict__ rowpart,
+                                                    const float *__restrict__ rowpart,
                                                     const float *__restrict__ colpart,
-                                                    const double *__restrict__ colpart0,
                                                     const int64_t *__restrict__ colpart_off, const FinConst fc,
                                                     double *__restrict__ lam_static, double *__restrict__ blockpart) {
     __shared__ double sh[HK_WAVES];
@@ -165,26 +164,25 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
     double lam_part = 0.0;
     if (i < n) {
         const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
-        double b0 = 0.0, x0 = 0.0, b1 = 0.0, b2 = 0.0, x1 = 0.0, x2 = 0.0;
+        double b0 = 0.0, x0 = 0.0, b1 = 0.0, b2 = 0.0, x2 = 0.0;
         for (int sg = 0; sg < row_nseg[I]; ++sg) {
-            const double *rp = rowpart + (int64_t)(row_item0[I] + sg) * HK_NROW * HK_TILE + r;
+            const float *rp = rowpart + (int64_t)(row_item0[I] + sg) * HK_NROW * HK_TILE + r;
             b0 += rp[0];
             b1 += rp[1 * HK_TILE];
             b2 += rp[2 * HK_TILE];
             x0 += rp[5 * HK_TILE];
-            x1 += rp[6 * HK_TILE];
             x2 += rp[7 * HK_TILE];
         }
         for (int J = I; J < ntiles; ++J) {
             const int64_t stride = (int64_t)(J + 1) * HK_TILE;
-            b0 += colpart0[colpart_off[J] / HK_NCOL + i];
+            b0 += (double)colpart[colpart_off[J] + i];
             b1 += (double)colpart[colpart_off[J] + stride + i];
             b2 += (double)colpart[colpart_off[J] + 2 * stride + i];
         }
         // first-order correction for the rounded FP32 exponent constants
         const double ln2 = 0.6931471805599453;
         b0 -= ln2 * (fc.rho_bx * b1 + fc.dkbt * b2);
-        x0 -= ln2 * (fc.dkw * x1 + fc.rho_ex * x2);
+        x0 -= ln2 * fc.rho_ex * x2;
         lam_static[i] = fc.c_b * b0 * fc.corr + fc.c_e * x0 * fc.corr;
         // integral term: background (all events) + excitation of the fixed-rate events
         const double ti = ts[i];
@@ -241,59 +239,85 @@ __global__ void k_sub_theta(const double *__restrict__ z, const int *__restrict_
 }
 
 // Subset excitation per event: one wavefront owns 64 rows and sweeps the subset
-// entries that precede them (cnt[b]), staged 64 at a time through LDS.
+// entries that precede them (cnt[b]), staged 64 at a time through LDS.  The
+// time factor of E is split at the first staged entry's time as in the full row
+// pass (FP64 factors, spatial exponent in the loop) unless the staged entries
+// span more than HK_SUB_FACT_SPAN / omega in time.
+#define HK_SUB_FACT_SPAN 40.0
+
+template <bool FACT>
+__device__ __forceinline__ void sub_row_sweep(const float4 *__restrict__ rec, const double *__restrict__ rtd,
+                                              const int *__restrict__ rpos, double tsi, int xr, int yr, int gr,
+                                              const PairConst kc, double &acc, float &mae) {
+#pragma unroll 8
+    for (int s = 0; s < HK_WAVE; ++s) {
+        const float4 v = rec[s];
+        const float dx = (float)(xr - __float_as_int(v.y));
+        const float dy = (float)(yr - __float_as_int(v.z));
+        const float r2 = fmaf(dx, dx, dy * dy);
+        const float ae = r2 * kc.kex;
+        float E;
+        if (FACT) {
+            E = fexp2(ae);
+        } else {
+            const float dt = (float)(tsi - rtd[s]);
+            E = fexp2(fmaf(dt, kc.kw, ae)) * fmaf(dt, kc.cw, 1.0f);
+        }
+        if (!(rpos[s] < gr)) E = 0.0f;
+        const float te = E * v.w;
+        acc += (double)te;
+        mae = fmaf(te, ae, mae);
+    }
+}
+
 __global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
     const double *__restrict__ ts, const int *__restrict__ xi, const int *__restrict__ yi, const int *__restrict__ g,
     const int *__restrict__ pos, const float *__restrict__ theta32, const int *__restrict__ cnt,
     const PairConst kc, double *__restrict__ xs, float *__restrict__ xmom) {
     __shared__ float4 rec[HK_WAVE];
+    __shared__ double rtd[HK_WAVE];
     __shared__ int rpos[HK_WAVE];
     const int b = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t i = (int64_t)b * HK_WAVE + lane;
-    const double Tb = ts[(int64_t)b * HK_WAVE];
-    const float ti = (float)(ts[i] - Tb);
+    const double tsi = ts[i];
     const int xr = xi[i], yr = yi[i], gr = g[i];
     const int nsub = cnt[b];
     double acc = 0.0;  // every term in FP64 (see the row pass: FP32 sums drop small terms)
-    float mdt = 0.0f, mae = 0.0f;  // sum theta E dt, sum theta E a_e (constant-rounding correction)
+    float mae = 0.0f;  // sum theta E a_e (rounding of the FP32 spatial constant)
     for (int c0 = 0; c0 < nsub; c0 += HK_WAVE) {
+        const double Tr = ts[pos[c0]];
+        bool fact;
         {
             const int r = c0 + lane;
             const int pj = r < nsub ? pos[r] : 0;
+            const double dtk = r < nsub ? ts[pj] - Tr : 0.0;
+            const float th = r < nsub ? theta32[r] : 0.0f;
+            fact = !__any(th > 0.0f && kc.omega * dtk > HK_SUB_FACT_SPAN);
             float4 v;
-            if (r < nsub) {
-                v.x = (float)(ts[pj] - Tb);
-                v.y = __int_as_float(xi[pj]);
-                v.z = __int_as_float(yi[pj]);
-                v.w = theta32[r];
-            } else {
-                v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            }
+            v.x = (float)dtk;
+            v.y = __int_as_float(r < nsub ? xi[pj] : 0);
+            v.z = __int_as_float(r < nsub ? yi[pj] : 0);
+            v.w = (fact && th > 0.0f) ? (float)((double)th * exp(kc.omega * dtk)) : th;
             rec[lane] = v;
+            rtd[lane] = r < nsub ? ts[pj] : 0.0;
             rpos[lane] = r < nsub ? pj : 0x7fffffff;
         }
         __syncthreads();
-#pragma unroll 8
-        for (int s = 0; s < HK_WAVE; ++s) {
-            const float4 v = rec[s];
-            const float dt = ti - v.x;
-            const float dx = (float)(xr - __float_as_int(v.y));
-            const float dy = (float)(yr - __float_as_int(v.z));
-            const float r2 = fmaf(dx, dx, dy * dy);
-            const float ae = r2 * kc.kex;
-            float E = fexp2(fmaf(dt, kc.kw, ae));
-            if (!(rpos[s] < gr)) E = 0.0f;
-            const float te = E * v.w;
-            acc += (double)te;
-            mdt = fmaf(te, dt, mdt);
-            mae = fmaf(te, ae, mae);
+        double accb = 0.0;
+        float maeb = 0.0f;
+        if (fact) sub_row_sweep<true>(rec, rtd, rpos, tsi, xr, yr, gr, kc, accb, maeb);
+        else sub_row_sweep<false>(rec, rtd, rpos, tsi, xr, yr, gr, kc, accb, maeb);
+        // a row with a causal pair here has t_i > t_k >= T_r: its factor is at most 1
+        if (accb != 0.0) {
+            const double ui = fact ? exp(-kc.omega * (tsi - Tr)) : 1.0;
+            acc += ui * accb;
+            mae += (float)ui * maeb;
         }
         __syncthreads();
     }
     xs[i] = acc;
-    xmom[2 * i] = mdt;
-    xmom[2 * i + 1] = mae;
+    xmom[i] = mae;
 }
 
 __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_static, const double *__restrict__ xs,
@@ -306,7 +330,7 @@ __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_
     double v = 0.0;
     if (i < n) {
         const double ln2 = 0.6931471805599453;
-        const double x = xs[i] - ln2 * (fc.dkw * (double)xmom[2 * i] + fc.rho_ex * (double)xmom[2 * i + 1]);
+        const double x = xs[i] - ln2 * fc.rho_ex * (double)xmom[i];
         const double l = lam_static[i] + fc.c_e * fc.corr * x;
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
@@ -326,7 +350,28 @@ __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_
 }
 
 // Column pass on the subset: lanes own subset entries (time order), rows are
-// all events after them, broadcast from LDS.
+// all events after them, broadcast from LDS.  Same arithmetic as the full
+// column pass: time factors in FP64, spatial exponent from pre-scaled FP64
+// coordinates, rounded once.
+template <bool WITH_H, bool FACT>
+__device__ __forceinline__ void sub_col_sweep(const double2 *__restrict__ rxy, const float2 *__restrict__ rv,
+                                              const double *__restrict__ rtd, const int *__restrict__ rg, int pj,
+                                              double tsj, double xj, double yj, const PairConst kc, float &G,
+                                              float &H) {
+#pragma unroll 8
+    for (int s = 0; s < HK_WAVE; ++s) {
+        const double2 p = rxy[s];
+        const double dx = p.x - xj, dy = p.y - yj;
+        const double aed = -fma(dx, dx, dy * dy);
+        float E = fexp2(FACT ? (float)aed : (float)fma(rtd[s] - tsj, kc.kw_d, aed));
+        if (!(pj < rg[s])) E = 0.0f;
+        const float2 v = rv[s];
+        const float ew = fmaf(E, v.y, E * v.x);
+        G += ew;
+        if (WITH_H) H = fmaf(ew, ew, H);
+    }
+}
+
 template <bool WITH_H>
 __global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ ts, const int *__restrict__ xi,
                                                       const int *__restrict__ yi, const float *__restrict__ w,
@@ -334,63 +379,50 @@ __global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ 
                                                       const int *__restrict__ pos, int64_t m,
                                                       const hk_item *__restrict__ items, const PairConst kc,
                                                       double *__restrict__ colG) {
-    __shared__ float4 rrec[HK_WAVE];
-    __shared__ float rwlo[HK_WAVE];
+    __shared__ double2 rxy[HK_WAVE];
+    __shared__ float2 rv[HK_WAVE];
+    __shared__ double rtd[HK_WAVE];
     __shared__ int rg[HK_WAVE];
+    __shared__ int fact_sh;
     const hk_item it = items[blockIdx.x];
     const int tid = threadIdx.x;
     const int64_t r = (int64_t)it.tile * HK_TILE + tid;
     const bool live = r < m;
     const int pj = live ? pos[r] : 0;
     const double tsj = ts[pj];
-    const int xj = xi[pj], yj = yi[pj];
-    float Gh = 0.0f, Gl = 0.0f, Hh = 0.0f, Hl = 0.0f, Hdt = 0.0f, Hae = 0.0f;
+    const double xj = (double)xi[pj] * kc.sx, yj = (double)yi[pj] * kc.sx;
+    double Gd = 0.0, Hd = 0.0;
     for (int c = it.c_begin; c < it.c_end; ++c) {
         const double Tc = ts[(int64_t)c * HK_WAVE];
-        const float tj = (float)(tsj - Tc);
         if (tid < HK_WAVE) {
             const int64_t i = (int64_t)c * HK_WAVE + tid;
-            float4 v;
-            v.x = (float)(ts[i] - Tc);
-            v.y = __int_as_float(xi[i]);
-            v.z = __int_as_float(yi[i]);
-            v.w = w[i];
-            rrec[tid] = v;
-            rwlo[tid] = wlo[i];
+            const double ti = ts[i];
+            const double dti = ti - Tc;
+            const double wd = (double)w[i] + (double)wlo[i];
+            const bool fact = !__any(wd > 0.0 && kc.omega * dti > HK_SUB_FACT_SPAN);
+            const double vv = fact ? wd * exp(-kc.omega * dti) : wd;
+            const float vhi = (float)vv;
+            rxy[tid] = make_double2((double)xi[i] * kc.sx, (double)yi[i] * kc.sx);
+            rv[tid] = make_float2(vhi, (float)(vv - (double)vhi));
+            rtd[tid] = ti;
             rg[tid] = g[i];
+            if (tid == 0) fact_sh = fact;
         }
         __syncthreads();
+        const bool fact = fact_sh != 0;
         float G = 0.0f, H = 0.0f;
-#pragma unroll 8
-        for (int s = 0; s < HK_WAVE; ++s) {
-            const float4 v = rrec[s];
-            const float dt = v.x - tj;
-            const float dx = (float)(__float_as_int(v.y) - xj);
-            const float dy = (float)(__float_as_int(v.z) - yj);
-            const float r2 = fmaf(dx, dx, dy * dy);
-            const float ae = r2 * kc.kex;
-            float E = fexp2(fmaf(dt, kc.kw, ae));
-            if (!(pj < rg[s])) E = 0.0f;
-            const float ew = fmaf(E, rwlo[s], E * v.w);
-            G += ew;
-            if (WITH_H) {
-                const float e2 = ew * ew;
-                H += e2;
-                Hdt = fmaf(e2, dt, Hdt);
-                Hae = fmaf(e2, ae, Hae);
-            }
+        if (fact) sub_col_sweep<WITH_H, true>(rxy, rv, rtd, rg, pj, tsj, xj, yj, kc, G, H);
+        else sub_col_sweep<WITH_H, false>(rxy, rv, rtd, rg, pj, tsj, xj, yj, kc, G, H);
+        if (G != 0.0f) {
+            const double uj = fact ? exp(kc.omega * (tsj - Tc)) : 1.0;
+            Gd += uj * (double)G;
+            if (WITH_H) Hd += (uj * uj) * (double)H;
         }
-        two_sum_acc(Gh, Gl, G);
-        if (WITH_H) two_sum_acc(Hh, Hl, H);
         __syncthreads();
     }
-    double *cg = colG + (int64_t)blockIdx.x * 4 * HK_TILE;
-    cg[tid] = live ? (double)Gh + (double)Gl : 0.0;
-    if (WITH_H) {
-        cg[HK_TILE + tid] = live ? (double)Hh + (double)Hl : 0.0;
-        cg[2 * HK_TILE + tid] = live ? (double)Hdt : 0.0;
-        cg[3 * HK_TILE + tid] = live ? (double)Hae : 0.0;
-    }
+    double *cg = colG + (int64_t)blockIdx.x * 2 * HK_TILE;
+    cg[tid] = live ? Gd : 0.0;
+    if (WITH_H) cg[HK_TILE + tid] = live ? Hd : 0.0;
 }
 
 __global__ void k_sub_colfin(const int *__restrict__ item0, const int *__restrict__ nseg,
@@ -399,21 +431,14 @@ __global__ void k_sub_colfin(const int *__restrict__ item0, const int *__restric
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= m) return;
     const int T = (int)(r / HK_TILE), lr = (int)(r % HK_TILE);
-    double G = 0.0, H = 0.0, Hdt = 0.0, Hae = 0.0;
+    double G = 0.0, H = 0.0;
     for (int sg = 0; sg < nseg[T]; ++sg) {
-        const double *cg = colG + (int64_t)(item0[T] + sg) * 4 * HK_TILE + lr;
+        const double *cg = colG + (int64_t)(item0[T] + sg) * 2 * HK_TILE + lr;
         G += cg[0];
-        if (with_h) {
-            H += cg[HK_TILE];
-            Hdt += cg[2 * HK_TILE];
-            Hae += cg[3 * HK_TILE];
-        }
+        if (with_h) H += cg[HK_TILE];
     }
     gsub[r] = G * fc.corr - a[r];
-    if (with_h) {
-        const double ln2 = 0.6931471805599453;
-        hsub[r] = (H - 2.0 * ln2 * (fc.dkw * Hdt + fc.rho_ex * Hae)) * fc.corr * fc.corr;
-    }
+    if (with_h) hsub[r] = H * fc.corr * fc.corr;
 }
 
 // Scatter the subset results to the caller's slot order.
@@ -652,8 +677,8 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     SC(dalloc(&s->a, s->mpad));
     SC(dalloc(&s->theta32, s->mpad));
     SC(dalloc(&s->xs, p->npad));
-    SC(dalloc(&s->xmom, 2 * p->npad));
-    SC(dalloc(&s->colG, (size_t)s->n_items * 4 * HK_TILE));
+    SC(dalloc(&s->xmom, p->npad));
+    SC(dalloc(&s->colG, (size_t)s->n_items * 2 * HK_TILE));
     SC(dalloc(&s->gsub, s->mpad));
     SC(dalloc(&s->hsub, s->mpad));
     SC(dalloc(&s->sums, 8));
@@ -684,7 +709,7 @@ hawkes_status ensure_static(hawkes_plan p, const hawkes_hyper *hy, const double 
     hipLaunchKernelGGL(k_sub_zero_subset, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->pos, s->m, p->theta_s);
     hk_launch_row_loglik(p, kc, stream);
     hipLaunchKernelGGL(k_sub_static, dim3(p->nfin_blocks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->theta_s,
-                       p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart0,
+                       p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart,
                        p->colpart_off, fc,
                        s->lam_static, p->blockpart);
     hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(64), 0, stream, p->blockpart, p->nfin_blocks, s->Lam_static);

@@ -33,11 +33,11 @@
 
 enum { HK_MODE_LOGLIK = 0, HK_MODE_GRAD = 1, HK_MODE_HESS = 2 };
 
-struct hk_item {  // one block of a pair pass
+struct hk_item {  // one piece of a pair-pass block: a chunk range of one tile
     int tile;     // row tile (row pass) or column tile (column pass)
     int c_begin;  // first chunk of the swept index
     int c_end;    // one past the last chunk
-    int seg;      // segment number within the tile
+    int seg;      // piece number within the tile
 };
 
 struct hawkes_plan_s {
@@ -61,6 +61,8 @@ struct hawkes_plan_s {
     // row pass schedule
     int n_row_items;
     hk_item *row_items;       // [n_row_items] (device)
+    int n_row_blocks;         // blocks of the row pass
+    int *row_block0;          // [n_row_blocks + 1] first item of each block (device)
     int *row_item0;           // [ntiles] first item of each row tile (device)
     int *row_nseg;            // [ntiles] items per row tile (device)
     int64_t *colpart_off;     // [ntiles] offset of tile I's column partials (device)
@@ -68,21 +70,22 @@ struct hawkes_plan_s {
     // column pass schedule
     int n_col_items;
     hk_item *col_items;
+    int n_col_blocks;
+    int *col_block0;
     int *col_item0;
     int *col_nseg;
 
     // per-evaluation scratch (device)
     float *theta_s;           // [npad] rates in sorted order (FP32), 0 on padding
-    double *rowpart;          // [n_row_items][HK_NROW][HK_TILE]
-    float *colpart;           // triangular [tile][HK_NCOL][(tile+1)*HK_TILE] (slots 1..4)
-    double *colpart0;         // triangular [tile][(tile+1)*HK_TILE]: background column sums
+    float *rowpart;           // [n_row_items][HK_NROW][HK_TILE] row partial sums of each piece
+    float *colpart;           // triangular [tile][HK_NCOL][(tile+1)*HK_TILE]: background column partials
     double *lam;              // [npad] lambda_i, sorted
     float *w;                 // [npad] c_e / lambda_i (FP32 high part), 0 on padding
     float *wlo;               // [npad] FP32 remainder of c_e / lambda_i
     double *a;                // [npad] theta0 (1 - exp(-omega (T1 - t_i)))
-    double *colG;             // [n_col_items][4][HK_TILE]: G, H and the two H moments
-    int nfin_blocks;
-    double *blockpart;        // [nfin_blocks][HK_NSUM]
+    double *colG;             // [n_col_items][2][HK_TILE]: G and H of each column piece
+    int nfin_blocks;          // npad / 256 (subset-path reductions)
+    double *blockpart;        // [nchunks][HK_NSUM] per-block partial sums
     int *status;              // sticky device status bits
     hipStream_t last_stream;
     struct hk_profile *prof;  // HIP-event timing of the passes (NULL when off)
@@ -90,6 +93,9 @@ struct hawkes_plan_s {
 };
 
 hipError_t hk_sort_pairs(double *key, int *idx, int64_t n2, hipStream_t stream);
+// Blocks of a pair pass (0 = row, 1 = column) resident at once on `device`:
+// compute units times the pass kernels' occupancy.
+int64_t hk_pass_slots(int device, int pass);
 void hk_subset_free(hawkes_plan p);
 // views of the free-rate subset for the preconditioner code
 void hk_subset_view(hawkes_plan p, int64_t *m, const int64_t **cidx, const int **pos, const int **slot);
@@ -103,6 +109,11 @@ struct PairConst {
     float kbt;  // -1 / (2 tau_t^2 ln 2)
     float kex;  // -2^{-2k} / (2 h^2 ln 2): fixed-point r^2 -> log2 units, excitation
     float kw;   // -omega / ln 2
+    float cw;      // ln 2 (kw - kw_f): first-order correction of the rounded kw, per unit dt
+    double omega;  // excitation decay rate (time factors formed in FP64)
+    double kex_d;  // kex and kw in FP64 (the column pass forms its exponent in FP64)
+    double kw_d;
+    double sx;     // sqrt(-kex): fixed-point coordinate -> coordinate whose squared distance is -a_e
 };
 
 struct FinConst {
@@ -114,10 +125,11 @@ struct FinConst {
     double t0, t1;
     // First-order correction for the rounding of the FP32 exponent constants:
     // a term computed as exp2(a + d) equals exp2(a) (1 + d ln 2 + O(d^2)), and d
-    // is linear in r^2, dt^2 (background) and dt, r^2 (excitation), whose
-    // weighted sums are the first moments the row pass accumulates.
+    // is linear in r^2, dt^2 (background) and r^2 (excitation), whose weighted
+    // sums are the first moments the row pass accumulates.  (The excitation's
+    // time term is formed in FP64 or corrected inside the pair loop.)
     double rho_bx, dkbt;   // (kbx_f - kbx) / kbx_f, kbt_f - kbt
-    double dkw, rho_ex;    // kw_f - kw, (kex_f - kex) / kex_f
+    double rho_ex;         // (kex_f - kex) / kex_f
 };
 
 bool hk_hyper_ok(const hawkes_hyper *h);

@@ -149,23 +149,63 @@ void free_plan(hawkes_plan p) {
     if (!p) return;
     hk_prof_free(p);
     hk_subset_free(p);
-    void *ptrs[] = {p->ts, p->xi, p->yi, p->perm, p->g, p->row_items, p->row_item0, p->row_nseg,
-                    p->colpart_off, p->col_items, p->col_item0, p->col_nseg, p->theta_s, p->rowpart,
-                    p->colpart, p->colpart0, p->lam, p->w, p->wlo, p->a, p->colG, p->blockpart, p->status};
+    void *ptrs[] = {p->ts, p->xi, p->yi, p->perm, p->g, p->row_items, p->row_block0, p->row_item0, p->row_nseg,
+                    p->colpart_off, p->col_items, p->col_block0, p->col_item0, p->col_nseg, p->theta_s, p->rowpart,
+                    p->colpart, p->lam, p->w, p->wlo, p->a, p->colG, p->blockpart, p->status};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
 }
 
-// Chunks per item: keep the item count near a few thousand so that the
-// triangular work spreads over all 256 CUs while the partial buffers stay small.
-int segment_chunks(int ntiles) {
-    int64_t target = 4096;
-    int64_t tri_chunks = (int64_t)ntiles * (ntiles + 1) / 2 * HK_CHUNKS_PER_TILE;
-    int64_t s = (tri_chunks + target - 1) / target;
-    s = std::max<int64_t>(s, HK_CHUNKS_PER_TILE);
-    s = (s + HK_CHUNKS_PER_TILE - 1) / HK_CHUNKS_PER_TILE * HK_CHUNKS_PER_TILE;
-    return (int)s;
+// Pair-pass schedule.  The sweeps of a pass -- (tile, chunk) pairs -- are laid
+// out tile by tile and cut into `slots` runs of nearly equal weight, one run per
+// block, so that every block resident on the chip finishes at about the same
+// time (a second, partly filled round of blocks would run at low occupancy).
+// A run is split into pieces at tile boundaries; the pieces of one tile are
+// contiguous in the item table and in chunk order, and each piece owns one
+// slice of the partial-sum buffers.  Weights count wavefront-sweeps: a chunk on
+// the diagonal tile is swept by only some of the block's four wavefronts.
+struct Schedule {
+    std::vector<hk_item> items;
+    std::vector<int> block0;  // [blocks + 1] first item of each block
+    std::vector<int> item0;   // [tiles] first item of each tile
+    std::vector<int> nseg;    // [tiles] items of each tile
+};
+
+template <class Lo, class Hi, class Wt>
+Schedule make_schedule(int T, Lo lo, Hi hi, Wt weight, int64_t slots) {
+    int64_t total = 0, nch = 0;
+    for (int I = 0; I < T; ++I)
+        for (int c = lo(I); c < hi(I); ++c) {
+            total += weight(I, c);
+            ++nch;
+        }
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(slots, nch));
+    auto target = [&](int64_t b) { return (total * (b + 1) + nb - 1) / nb; };
+    Schedule s;
+    s.item0.assign(T, 0);
+    s.nseg.assign(T, 0);
+    s.block0.push_back(0);
+    int64_t cum = 0, b = 0;
+    for (int I = 0; I < T; ++I) {
+        s.item0[I] = (int)s.items.size();
+        bool open = false;
+        for (int c = lo(I); c < hi(I); ++c) {
+            if (!open) {
+                s.items.push_back({I, c, c, s.nseg[I]++});
+                open = true;
+            }
+            s.items.back().c_end = c + 1;
+            cum += weight(I, c);
+            if (b < nb - 1 && cum >= target(b)) {
+                open = false;
+                s.block0.push_back((int)s.items.size());
+                while (b < nb - 1 && cum >= target(b)) ++b;
+            }
+        }
+    }
+    if (s.block0.back() != (int)s.items.size()) s.block0.push_back((int)s.items.size());
+    return s;
 }
 
 }  // namespace
@@ -274,62 +314,59 @@ extern "C" hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const d
 
     // ---- schedules ----
     const int T = p->ntiles;
-    // row pass: row tile I sweeps column chunks [0, 4(I+1)) in segments
-    const int S = segment_chunks(T);
-    std::vector<hk_item> ritems;
-    std::vector<int> ritem0(T), rnseg(T);
+    const int C4 = HK_CHUNKS_PER_TILE;
+    // row pass: row tile I sweeps column chunks [0, 4(I+1)); wavefront w of the
+    // block stops at its own chunk 4I + w
+    Schedule rs = make_schedule(
+        T, [](int) { return 0; }, [&](int I) { return C4 * (I + 1); },
+        [&](int I, int c) { return c < C4 * I ? C4 : C4 - (c - C4 * I); }, hk_pass_slots(p->device, 0));
+    // column pass: column tile J sweeps row chunks [4J, nchunks); wavefront w
+    // starts at its own chunk 4J + w
+    Schedule cs = make_schedule(
+        T, [&](int J) { return C4 * J; }, [&](int) { return p->nchunks; },
+        [&](int J, int c) { return c >= C4 * (J + 1) ? C4 : 1 + (c - C4 * J); }, hk_pass_slots(p->device, 1));
     std::vector<int64_t> cpoff(T);
     int64_t cpl = 0;
     for (int I = 0; I < T; ++I) {
-        int nc = HK_CHUNKS_PER_TILE * (I + 1);
-        ritem0[I] = (int)ritems.size();
-        int seg = 0;
-        for (int c = 0; c < nc; c += S) ritems.push_back({I, c, std::min(c + S, nc), seg++});
-        rnseg[I] = seg;
         cpoff[I] = cpl;
         cpl += (int64_t)HK_NCOL * (I + 1) * HK_TILE;
     }
     p->colpart_len = cpl;
-    p->n_row_items = (int)ritems.size();
-    // column pass: column tile J sweeps row chunks [4J, nchunks) in segments
-    std::vector<hk_item> citems;
-    std::vector<int> citem0(T), cnseg(T);
-    for (int J = 0; J < T; ++J) {
-        int cb = HK_CHUNKS_PER_TILE * J;
-        citem0[J] = (int)citems.size();
-        int seg = 0;
-        for (int c = cb; c < p->nchunks; c += S) citems.push_back({J, c, std::min(c + S, p->nchunks), seg++});
-        cnseg[J] = seg;
-    }
-    p->n_col_items = (int)citems.size();
+    p->n_row_items = (int)rs.items.size();
+    p->n_row_blocks = (int)rs.block0.size() - 1;
+    p->n_col_items = (int)cs.items.size();
+    p->n_col_blocks = (int)cs.block0.size() - 1;
 
-    PC(dalloc(&p->row_items, ritems.size()));
+    PC(dalloc(&p->row_items, rs.items.size()));
+    PC(dalloc(&p->row_block0, rs.block0.size()));
     PC(dalloc(&p->row_item0, T));
     PC(dalloc(&p->row_nseg, T));
     PC(dalloc(&p->colpart_off, T));
-    PC(dalloc(&p->col_items, citems.size()));
+    PC(dalloc(&p->col_items, cs.items.size()));
+    PC(dalloc(&p->col_block0, cs.block0.size()));
     PC(dalloc(&p->col_item0, T));
     PC(dalloc(&p->col_nseg, T));
-    PC(hipMemcpy(p->row_items, ritems.data(), sizeof(hk_item) * ritems.size(), hipMemcpyHostToDevice));
-    PC(hipMemcpy(p->row_item0, ritem0.data(), sizeof(int) * T, hipMemcpyHostToDevice));
-    PC(hipMemcpy(p->row_nseg, rnseg.data(), sizeof(int) * T, hipMemcpyHostToDevice));
+    PC(hipMemcpy(p->row_items, rs.items.data(), sizeof(hk_item) * rs.items.size(), hipMemcpyHostToDevice));
+    PC(hipMemcpy(p->row_block0, rs.block0.data(), sizeof(int) * rs.block0.size(), hipMemcpyHostToDevice));
+    PC(hipMemcpy(p->row_item0, rs.item0.data(), sizeof(int) * T, hipMemcpyHostToDevice));
+    PC(hipMemcpy(p->row_nseg, rs.nseg.data(), sizeof(int) * T, hipMemcpyHostToDevice));
     PC(hipMemcpy(p->colpart_off, cpoff.data(), sizeof(int64_t) * T, hipMemcpyHostToDevice));
-    PC(hipMemcpy(p->col_items, citems.data(), sizeof(hk_item) * citems.size(), hipMemcpyHostToDevice));
-    PC(hipMemcpy(p->col_item0, citem0.data(), sizeof(int) * T, hipMemcpyHostToDevice));
-    PC(hipMemcpy(p->col_nseg, cnseg.data(), sizeof(int) * T, hipMemcpyHostToDevice));
+    PC(hipMemcpy(p->col_items, cs.items.data(), sizeof(hk_item) * cs.items.size(), hipMemcpyHostToDevice));
+    PC(hipMemcpy(p->col_block0, cs.block0.data(), sizeof(int) * cs.block0.size(), hipMemcpyHostToDevice));
+    PC(hipMemcpy(p->col_item0, cs.item0.data(), sizeof(int) * T, hipMemcpyHostToDevice));
+    PC(hipMemcpy(p->col_nseg, cs.nseg.data(), sizeof(int) * T, hipMemcpyHostToDevice));
 
     // ---- per-evaluation scratch ----
     PC(dalloc(&p->theta_s, npad));
     PC(dalloc(&p->rowpart, (size_t)p->n_row_items * HK_NROW * HK_TILE));
     PC(dalloc(&p->colpart, (size_t)cpl));
-    PC(dalloc(&p->colpart0, (size_t)(cpl / HK_NCOL)));
     PC(dalloc(&p->lam, npad));
     PC(dalloc(&p->w, npad));
     PC(dalloc(&p->wlo, npad));
     PC(dalloc(&p->a, npad));
-    PC(dalloc(&p->colG, (size_t)p->n_col_items * 4 * HK_TILE));
+    PC(dalloc(&p->colG, (size_t)p->n_col_items * 2 * HK_TILE));
     p->nfin_blocks = (int)(npad / 256);
-    PC(dalloc(&p->blockpart, (size_t)p->nfin_blocks * HK_NSUM));
+    PC(dalloc(&p->blockpart, (size_t)p->nchunks * HK_NSUM));
     PC(dalloc(&p->status, 1));
     PC(hipMemsetAsync(p->status, 0, sizeof(int), stream));
     PC(hipStreamSynchronize(stream));
