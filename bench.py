@@ -4,8 +4,8 @@
 A step is one full evaluation (hawkes_eval with every output): the row pass
 over all N(N-1)/2 event pairs (intensities, background moments, excitation
 moments), the per-event finalisation with the integral term and the
-hyperparameter sums, and the column pass over the causal pairs (Eq. 3 and
-Eq. 4) -- log-likelihood, rate gradient, Hessian diagonal and hyperparameter
+hyperparameter sums, and the column pass over the causal pairs (Eq. 4 and
+Eq. 5) -- log-likelihood, rate gradient, Hessian diagonal and hyperparameter
 gradient and Hessian.  Workload: N = 23,422 events simulated from the Hawkes
 branching process, rates lognormal(0, 0.5) on 1,610 of them (the paper's
 application size).  Inputs are resident in HBM before timing starts.

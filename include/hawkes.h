@@ -12,8 +12,8 @@
  *   Lambda   = mu0 sum_n [Phi((T1-t_n)/tau_t) - Phi((T0-t_n)/tau_t)]
  *            + theta0 sum_n theta_n (1 - exp(-omega (T1 - t_n)))          (App. A)
  *   loglik   = sum_i log lambda_i - Lambda                                  (Eq. 1)
- *   d loglik/d theta_j = sum_{t_i > t_j} c_e E_ij / lambda_i - theta0 (1 - exp(-omega (T1 - t_j)))  (Eq. 3)
- *   -d2 loglik/d theta_j^2 = sum_{t_i > t_j} (c_e E_ij / lambda_i)^2                              (Eq. 4)
+ *   d loglik/d theta_j = sum_{t_i > t_j} c_e E_ij / lambda_i - theta0 (1 - exp(-omega (T1 - t_j)))  (Eq. 4)
+ *   -d2 loglik/d theta_j^2 = sum_{t_i > t_j} (c_e E_ij / lambda_i)^2                              (Eq. 5)
  * The paper's background is spatial only; the Gaussian-in-time factor is this
  * library's extension.  Its integral is the exact integral of the stated
  * background.  The self-exclusion indicator is j != i; the excitation is
@@ -88,12 +88,12 @@ hawkes_status hawkes_plan_destroy(hawkes_plan p);
 /* Number of events of the plan, or -1 for NULL. */
 int64_t hawkes_plan_size(hawkes_plan p);
 
-/* Core evaluation (Eq. 1, Eq. 3, Eq. 4 and the hyperparameter derivatives).
+/* Core evaluation (Eq. 1, Eq. 4, Eq. 5 and the hyperparameter derivatives).
  *   d_theta       [n] rates theta_n >= 0, caller order (device, FP64)
  *   d_loglik      [1] loglik (Eq. 1)                           -- may be NULL
- *   d_grad_theta  [n] d loglik / d theta_j (Eq. 3)            -- may be NULL
+ *   d_grad_theta  [n] d loglik / d theta_j (Eq. 4)            -- may be NULL
  *   d_grad_hyper  [6] d loglik / d (mu0,tau_x,tau_t,theta0,omega,h) -- may be NULL
- *   d_negH_theta  [n] -d2 loglik / d theta_j^2 (Eq. 4)        -- may be NULL
+ *   d_negH_theta  [n] -d2 loglik / d theta_j^2 (Eq. 5)        -- may be NULL
  *   d_negH_hyper  [6] -d2 loglik / d p^2 for the six hyperparameters -- may be NULL
  * One row pass over the causal pairs always runs (it gives lambda); a column
  * pass runs iff d_grad_theta or d_negH_theta is non-NULL.  When some lambda_i
@@ -136,14 +136,14 @@ hawkes_status hawkes_copy_lambda(hawkes_plan p, double *d_lambda, hipStream_t st
  * HAWKES_E_INVALID for an index out of range or repeated. */
 hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const int64_t *d_idx, hipStream_t stream);
 
-/* Eq. 1, Eq. 3 and Eq. 4 restricted to the subset, by the O(N M) path.
+/* Eq. 1, Eq. 4 and Eq. 5 restricted to the subset, by the O(N M) path.
  *   d_theta        [n] full rate vector, caller order (device, read only)
  *   refresh_static non-zero: recompute the cached static part (needed when the
  *                  rates OFF the subset changed; a change of hyperparameters is
  *                  detected by the library)
  *   d_loglik       [1] loglik (Eq. 1) -- may be NULL
- *   d_grad_sub     [m] d loglik / d theta_{idx[k]} (Eq. 3) -- may be NULL
- *   d_negH_sub     [m] -d2 loglik / d theta_{idx[k]}^2 (Eq. 4) -- may be NULL
+ *   d_grad_sub     [m] d loglik / d theta_{idx[k]} (Eq. 4) -- may be NULL
+ *   d_negH_sub     [m] -d2 loglik / d theta_{idx[k]}^2 (Eq. 5) -- may be NULL
  * Needs hawkes_plan_set_subset first (else HAWKES_E_UNSUPPORTED). */
 hawkes_status hawkes_subset_grad(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
                                  int refresh_static, double *d_loglik, double *d_grad_sub, double *d_negH_sub,
@@ -220,7 +220,7 @@ hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hyper, const do
 
 /* Running average of the diagonal mass: d_mass[k] <- (count d_mass[k] + c_k)/(count + 1)
  * with c_k the z-space curvature estimate at the rates d_theta:
- *   d_pred == NULL: exact, max(theta^2 H - theta g, 0) + 1/sigma_z^2 (Eq. 3, Eq. 4, subset path);
+ *   d_pred == NULL: exact, max(theta^2 H - theta g, 0) + 1/sigma_z^2 (Eq. 4, Eq. 5, subset path);
  *   d_pred != NULL: learned, max(exp(d_pred[k]), 1/sigma_z^2) (d_pred [m] FP32, slot order: a
  *                   prediction of the log of the exact estimate). */
 hawkes_status hawkes_mass_update(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,

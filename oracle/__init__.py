@@ -7,7 +7,7 @@ input generator, which holds none of the method's arithmetic.
 
 Contents:
   * ``hawkes_oracle.c`` (compiled to ``liboracle.so``): the log-likelihood of
-    Eq. 1, the rate gradient of Eq. 3 and the Hessian diagonal of Eq. 4, plus
+    Eq. 1, the rate gradient of Eq. 4 and the Hessian diagonal of Eq. 5, plus
     the hyperparameter derivatives, as plain FP64 double loops;
   * ``philox.py``: the Philox-4x32-10 counter-based generator;
   * ``mlp.py``: FP64 forward/backward of the small preconditioner network;
@@ -117,7 +117,7 @@ def row_sums(t, x, y, theta, hyper, rows=None, nthreads=0):
 
 
 def col_sums(t, x, y, hyper, lam, cols=None, nthreads=0):
-    """Eq. 3 / Eq. 4 column sums (G_j, H_j) for the given columns, given lambda for all events."""
+    """Eq. 4 / Eq. 5 column sums (G_j, H_j) for the given columns, given lambda for all events."""
     lib = _load()
     t, x, y, hy, lam = _c(t), _c(x), _c(y), _c(hyper), _c(lam)
     n = t.shape[0]

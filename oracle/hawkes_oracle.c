@@ -34,8 +34,8 @@
  *   loglik = sum_i log lambda_i - Lambda                       (Eq. 1)
  *   ell_n  = log lambda_n - Lambda_n   (per-event split of Eq. 1)
  *   d loglik / d theta_j    = sum_{t_i > t_j} c_e E_ij / lambda_i
- *                             - theta0 (1 - exp(-omega (T1 - t_j)))   (Eq. 3)
- *   -d2 loglik / d theta_j^2 = sum_{t_i > t_j} (c_e E_ij / lambda_i)^2 (Eq. 4,
+ *                             - theta0 (1 - exp(-omega (T1 - t_j)))   (Eq. 4)
+ *   -d2 loglik / d theta_j^2 = sum_{t_i > t_j} (c_e E_ij / lambda_i)^2 (Eq. 5,
  *                             exact because lambda_i and Lambda are linear in theta_j)
  *
  * Hyperparameter derivatives (mu0, tau_x, tau_t, theta0, omega, h) are not in
@@ -129,7 +129,7 @@ int oracle_row_sums(int64_t n, const double *t, const double *x, const double *y
 }
 
 /*
- * Column sums of Eq. 3 and Eq. 4 for columns cols[0..ncols-1] (all when NULL),
+ * Column sums of Eq. 4 and Eq. 5 for columns cols[0..ncols-1] (all when NULL),
  * given lambda for every event: G_j = sum_{t_i>t_j} c_e E_ij / lambda_i and
  * H_j = sum_{t_i>t_j} (c_e E_ij / lambda_i)^2.
  */

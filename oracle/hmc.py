@@ -51,7 +51,7 @@ def hmc_iteration(es_t, es_x, es_y, theta_full, idx, z0, mass, hyper, t0, eps, L
 
 def z_hessian_diag(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z):
     """-d2 log pi / dz_k^2 = theta_k^2 H_k - theta_k g_k + 1/sigma_z^2 (chain rule on
-    theta = exp(z) with Eq. 3 and Eq. 4)."""
+    theta = exp(z) with Eq. 4 and Eq. 5)."""
     th = theta_full.copy()
     th[idx] = np.exp(z)
     r = evaluate(es_t, es_x, es_y, th, hyper, t0, want=("grad_theta", "negH_theta"))

@@ -1,4 +1,4 @@
-// Evaluation of Eq. 1 (log-likelihood), Eq. 3 (rate gradient), Eq. 4 (rate
+// Evaluation of Eq. 1 (log-likelihood), Eq. 4 (rate gradient), Eq. 5 (rate
 // Hessian diagonal) and the hyperparameter derivatives on gfx950.
 //
 // Kernels, in launch order:
@@ -13,7 +13,7 @@
 //              terms; fixed-order block reduction (DPP within the wavefront)
 //   k_fin2     one block: block partials -> loglik, grad/negH of hyperparameters
 //   k_col      column pass: G_j = sum_{t_i > t_j} E_ij w_i, H_j = sum (E_ij w_i)^2
-//   k_colfin   G_j, H_j -> Eq. 3 / Eq. 4 in the caller's order
+//   k_colfin   G_j, H_j -> Eq. 4 / Eq. 5 in the caller's order
 #include <hip/hip_runtime.h>
 #include <math.h>
 

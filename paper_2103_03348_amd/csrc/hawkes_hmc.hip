@@ -9,7 +9,7 @@
 // The static part costs one O(N^2) row pass per hyperparameter setting and is
 // cached; each gradient inside a trajectory then costs one row pass over
 // N x M pairs (subset excitation) and one column pass over M x N pairs
-// (Eq. 3 and Eq. 4 restricted to the subset), i.e. O(N M) as the paper notes.
+// (Eq. 4 and Eq. 5 restricted to the subset), i.e. O(N M) as the paper notes.
 //
 // Kernels:
 //   k_sub_static   partial sums of the static row pass -> lambda_static_i
@@ -17,7 +17,7 @@
 //   k_sub_row      X_i = sum_{k in M, t_k < t_i} theta_k E_ik (rows = all events)
 //   k_sub_fin      lambda_i, w_i = c_e / lambda_i, block sums of log lambda_i
 //   k_sub_col      G_k = sum_{t_i > t_k} E_ik w_i, H_k = sum (E_ik w_i)^2
-//   k_sub_colfin   Eq. 3 / Eq. 4 on the subset; gradient in z with the prior
+//   k_sub_colfin   Eq. 4 / Eq. 5 on the subset; gradient in z with the prior
 //   k_hmc_*        momenta (Philox-4x32-10 + Box-Muller), leapfrog, energy, accept
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -51,8 +51,8 @@ struct hk_subset {
     double *xs;          // [npad] subset excitation sums per event
     float *xmom;         // [npad] sum theta E a_e per event (spatial-constant rounding)
     double *colG;        // [n_items][2][HK_TILE]
-    double *gsub;        // [mpad] Eq. 3 on the subset, time order
-    double *hsub;        // [mpad] Eq. 4 on the subset, time order
+    double *gsub;        // [mpad] Eq. 4 on the subset, time order
+    double *hsub;        // [mpad] Eq. 5 on the subset, time order
     double *sums;        // [8] loglik pieces of the last evaluation
     // HMC state
     double *z0, *p, *gz; // [m] slot order
@@ -721,7 +721,7 @@ hawkes_status ensure_static(hawkes_plan p, const hawkes_hyper *hy, const double 
     return HAWKES_OK;
 }
 
-// One subset evaluation at z (slot order): theta, lambda, w, Eq. 3 (and Eq. 4)
+// One subset evaluation at z (slot order): theta, lambda, w, Eq. 4 (and Eq. 5)
 // on the subset, block partial sums of log lambda in p->blockpart.
 void sub_eval(hawkes_plan p, const double *z, double *theta_full, bool with_h, const PairConst &kc,
               const FinConst &fc, hipStream_t stream) {

@@ -133,7 +133,7 @@ struct FinConst {
 };
 
 bool hk_hyper_ok(const hawkes_hyper *h);
-// Eq. 3 and Eq. 4 on the subset at the rates d_theta (O(N M) path); device
+// Eq. 4 and Eq. 5 on the subset at the rates d_theta (O(N M) path); device
 // pointers to the results in time order
 hawkes_status hk_subset_exact(hawkes_plan p, const hawkes_hyper *hy, const double *d_theta, hipStream_t stream,
                               const double **gsub, const double **hsub);

@@ -4,7 +4,7 @@
 //
 // The network predicts, from cheap features of free event m, the log of the
 // exact diagonal mass estimate max(theta_m^2 H_m - theta_m g_m, 0) + 1/sigma_z^2
-// built from Eq. 3 and Eq. 4 (the z-space curvature of the log posterior).  The
+// built from Eq. 4 and Eq. 5 (the z-space curvature of the log posterior).  The
 // exact column pass remains the training target, the periodic fallback and the
 // judge, so the sampler stays exact: any positive mass leaves the target
 // distribution invariant.

@@ -2,7 +2,7 @@
 
 A 12 -> 64 -> 64 -> 1 tanh network predicts, for free event k, the log of the
 exact diagonal mass estimate max(theta_k^2 H_k - theta_k g_k, 0) + 1/sigma_z^2
-(the z-space curvature from Eq. 3 and the Eq. 4 Hessian diagonal) from cheap
+(the z-space curvature from Eq. 4 and the Eq. 5 Hessian diagonal) from cheap
 per-event features (grid-cell counts, recent-window counts, log theta, time
 rank, time to the window end).  It is trained on the GPU by the library's own
 forward, back-propagation and Adam kernels on exact estimates collected at

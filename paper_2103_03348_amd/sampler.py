@@ -11,7 +11,7 @@ per iteration.  Between iterations it adapts:
   * the diagonal mass matrix, as the running average of preconditioner
     estimates computed at a fixed interval (the paper's adaptation, which keeps
     Monte Carlo estimates asymptotically unbiased).  The estimate is either the
-    exact z-space curvature theta^2 H - theta g + 1/sigma_z^2 (Eq. 3 and Eq. 4 by
+    exact z-space curvature theta^2 H - theta g + 1/sigma_z^2 (Eq. 4 and Eq. 5 by
     the O(N M) subset path, floored at the prior precision), or the learned
     prediction of a small network (preconditioner.py), or the identity-scaled
     prior precision (no preconditioning).
@@ -83,7 +83,7 @@ class HmcSampler:
 
     # ---- preconditioner estimates ----------------------------------------------------------
     def exact_curvature(self) -> torch.Tensor:
-        """-d2 log pi / dz^2 on the subset at the current state (chain rule on Eq. 3, 4)."""
+        """-d2 log pi / dz^2 on the subset at the current state (chain rule on Eq. 4, 5)."""
         _lib.check(_lib.lib().hawkes_subset_grad(self.plan.handle, ctypes.byref(self.hyper), _lib.ptr(self.theta),
                                                  0, None, _lib.ptr(self._g), _lib.ptr(self._h),
                                                  _lib.stream_handle()), "hawkes_subset_grad")
@@ -92,7 +92,7 @@ class HmcSampler:
         return torch.clamp(th * th * self._h - th * self._g, min=0.0) + prec
 
     def exact_theta_hessian(self) -> torch.Tensor:
-        """Eq. 4 on the subset (the learned preconditioner's training target)."""
+        """Eq. 5 on the subset (the learned preconditioner's training target)."""
         _lib.check(_lib.lib().hawkes_subset_grad(self.plan.handle, ctypes.byref(self.hyper), _lib.ptr(self.theta),
                                                  0, None, None, _lib.ptr(self._h), _lib.stream_handle()),
                    "hawkes_subset_grad")

@@ -31,7 +31,7 @@ def errors(es, gpu, ref):
       loglik_rel : |dl| / |l|
       loglik_mag : |dl| / (sum_i |log lambda_i| + Lambda)
       lam_rel    : max_i |dlambda_i| / lambda_i
-      g_rel      : max_j |dg_j| / (a_j + sum_i c_e E_ij / lambda_i)   (Eq. 3's two terms)
+      g_rel      : max_j |dg_j| / (a_j + sum_i c_e E_ij / lambda_i)   (Eq. 4's two terms)
       h_rel      : max_j |dH_j| / H_j  over H_j > 0, and max |H_j| where H_j = 0
       gh_rel     : per hyperparameter |dg_p| / max(|g_p|, scale_p)
     """
@@ -50,7 +50,7 @@ def errors(es, gpu, ref):
         out["g_rel"] = float(np.max(np.abs(gpu["grad_theta"] - ref["grad_theta"]) / np.maximum(scale, 1e-300)))
         H = ref["negH_theta"]
         pos = H > 0
-        # the squared terms of Eq. 4 underflow FP32 below ~1e-38; 1e-30 is the floor
+        # the squared terms of Eq. 5 underflow FP32 below ~1e-38; 1e-30 is the floor
         hrel = np.abs(gpu["negH_theta"] - H) / (H + 1e-30)
         out["h_rel_all"] = float(np.max(hrel))
         hmax = H.max() if H.size else 0.0

@@ -43,7 +43,7 @@ def _subset_grad(plan, es, theta, refresh=0):
 
 @pytest.mark.parametrize("cfg", ["small", "n23422"])
 def test_subset_grad_matches_oracle(gpu, cfg):
-    """Eq. 1, 3, 4 restricted to the free rates, by the cached-static O(N M) path."""
+    """Eq. 1, 4, 5 restricted to the free rates, by the cached-static O(N M) path."""
     es = synth.small(1500, seed=21, ties=6, all_free=False) if cfg == "small" else synth.config(1)
     plan, idx = _setup(es)
     ll, g, h = _subset_grad(plan, es, es.theta)

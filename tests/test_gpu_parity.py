@@ -7,7 +7,7 @@ Tolerances (FP32 pair arithmetic, compensated sums, FP64 finals):
     |dl| <= 2e-6 * N (the lambda tolerance below, summed).
   * lambda_i: 2e-6 relative (a sum of FP32 terms with ~1e-7 error each, bounded
     with margin for sets where one term dominates).
-  * rate gradient: 1e-6 relative to the magnitude of Eq. 3's two terms.
+  * rate gradient: 1e-6 relative to the magnitude of Eq. 4's two terms.
   * Hessian diagonal: 1e-6 relative (all terms positive) on every entry of
     at least 1e-4 of the largest, and 1e-6 norm-wise.  A term with FP32
     exponent argument a carries a relative error up to ~2 ln2 2^-24 |a| from the

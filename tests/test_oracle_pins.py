@@ -30,7 +30,7 @@ def _es(n, seed, ties=0, dup_xy=0, t_end=None):
 
 
 def test_n2_golden_case():
-    """Sec. 2.1 / Eq. 1, 3, 4 on the two-event case (tests/golden/n2_case.json)."""
+    """Sec. 2.1 / Eq. 1, 4, 5 on the two-event case (tests/golden/n2_case.json)."""
     g = json.load(open(os.path.join(GOLDEN, "n2_case.json")))
     r = oracle.evaluate(g["t"], g["x"], g["y"], g["theta"], g["hyper"], g["t0"])
     np.testing.assert_allclose(r["lam"], g["lam"], rtol=1e-14)
@@ -115,7 +115,7 @@ def test_spatial_density_integrates_to_one():
 def test_background_only_closed_form():
     """theta0 = 0: lambda_i = c_b B0_i, so loglik(mu0) = N log mu0 + const - mu0 C,
     d loglik/d mu0 = N/mu0 - C with C = sum_n [Phi(u1_n) - Phi(u0_n)], and the rate
-    gradient and Hessian vanish identically (Eq. 3, 4 carry a factor theta0)."""
+    gradient and Hessian vanish identically (Eq. 4, 5 carry a factor theta0)."""
     es = _es(40, seed=5)
     hy = (0.7, 2.0, 5.0, 0.0, 0.5, 0.3)
     r = oracle.evaluate_es(es, hyper=hy)
@@ -144,7 +144,7 @@ def test_euler_homogeneity():
 
 
 def test_row_column_consistency():
-    """theta0 dl/dtheta0 (row sums) equals sum_m theta_m dl/dtheta_m (column sums of Eq. 3):
+    """theta0 dl/dtheta0 (row sums) equals sum_m theta_m dl/dtheta_m (column sums of Eq. 4):
     both are sum_i c_e X0_i / lambda_i - theta0 sum_n theta_n (1 - e^{-omega (T1 - t_n)})."""
     es = _es(80, seed=9, ties=4)
     r = oracle.evaluate_es(es)
@@ -162,7 +162,7 @@ def _fd_loglik(fn, p0, step):
 
 @pytest.mark.parametrize("seed", [21, 22])
 def test_fd_rate_gradient_and_hessian(seed):
-    """Eq. 3 and Eq. 4 against central finite differences of Eq. 1 (step 1e-6 for
+    """Eq. 4 and Eq. 5 against central finite differences of Eq. 1 (step 1e-6 for
     the gradient, 1e-4 on the gradient for the Hessian)."""
     es = _es(50, seed=seed, ties=2)
     r = oracle.evaluate_es(es)
