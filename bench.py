@@ -66,7 +66,7 @@ def cpu_baseline(es, budget_s=12.0):
                       f"derivatives) of the N={n} workload, {el:.1f} s"}
 
 
-def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_states=200, seed=7, n_chains=3):
+def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_states=200, seed=7, n_chains=4):
     """HMC ESS/s on the free log-rates with the exact and the learned diagonal
     preconditioner (and, for reference, none), each chain adapting its step size
     by dual averaging during its own warm-up, then `n_iter` timed iterations;

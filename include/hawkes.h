@@ -58,7 +58,9 @@ typedef enum {
     HAWKES_E_NONFINITE = 3,      /* a NaN/Inf appeared in a device result                      */
     HAWKES_E_DEVICE = 4,         /* a HIP runtime call failed                                  */
     HAWKES_E_NOMEM = 5,          /* device allocation failed                                   */
-    HAWKES_E_UNSUPPORTED = 6     /* the call needs state that is not set (e.g. no subset)     */
+    HAWKES_E_UNSUPPORTED = 6,    /* the call needs state that is not set (e.g. no subset)     */
+    HAWKES_E_STALE = 7           /* the plan's intensities are not those the call refers to
+                                    (see hawkes_grad_theta_from_last); nothing was enqueued   */
 } hawkes_status;
 
 /* Hyperparameters, in the order (mu0, tau_x, tau_t, theta0, omega, h) used for
@@ -114,6 +116,22 @@ hawkes_status hawkes_hessdiag(hawkes_plan p, const hawkes_hyper *hyper, const do
 /* Synchronise the plan's last stream, return the sticky device status and
  * clear it. */
 hawkes_status hawkes_plan_status(hawkes_plan p);
+
+/* Number of intensity evaluations the plan has run so far: every hawkes_eval
+ * (and every subset evaluation of the HMC path) increments it.  Host-side,
+ * no synchronisation. */
+int64_t hawkes_plan_epoch(hawkes_plan p);
+
+/* The backward half of an evaluation (Eq. 4, and Eq. 5 when d_negH_theta is
+ * not NULL): only the column pass runs, on the intensities lambda_i and the
+ * integral terms left by the plan's most recent hawkes_eval.  The call pairs
+ * with that evaluation: `epoch` must be the value hawkes_plan_epoch returned
+ * right after it and *hyper must equal the hyperparameters it used.  If either
+ * differs -- the plan has evaluated something else since -- nothing is
+ * enqueued and HAWKES_E_STALE is returned; the caller then runs hawkes_grad.
+ * Outputs as in hawkes_eval (caller order, FP64, device). */
+hawkes_status hawkes_grad_theta_from_last(hawkes_plan p, const hawkes_hyper *hyper, int64_t epoch,
+                                          double *d_grad_theta, double *d_negH_theta, hipStream_t stream);
 
 /* Per-event intermediate results of the last hawkes_eval, caller order:
  * d_lambda [n] the intensities lambda_i (FP64).  Enqueued on `stream`. */

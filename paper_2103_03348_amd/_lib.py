@@ -28,8 +28,9 @@ STATUS = {
     4: "HAWKES_E_DEVICE",
     5: "HAWKES_E_NOMEM",
     6: "HAWKES_E_UNSUPPORTED",
+    7: "HAWKES_E_STALE",
 }
-OK, E_INVALID, E_ZERO_INTENSITY, E_NONFINITE, E_DEVICE, E_NOMEM, E_UNSUPPORTED = range(7)
+OK, E_INVALID, E_ZERO_INTENSITY, E_NONFINITE, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_STALE = range(8)
 
 
 class HawkesError(RuntimeError):
@@ -71,6 +72,8 @@ SIGNATURES = {
     "hawkes_hessdiag": (ctypes.c_int, [_vp, _HyP, _vp, _vp, _vp, _vp]),
     "hawkes_plan_status": (ctypes.c_int, [_vp]),
     "hawkes_copy_lambda": (ctypes.c_int, [_vp, _vp, _vp]),
+    "hawkes_plan_epoch": (_i64, [_vp]),
+    "hawkes_grad_theta_from_last": (ctypes.c_int, [_vp, _HyP, _i64, _vp, _vp, _vp]),
     "hawkes_plan_set_subset": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
     "hawkes_subset_grad": (ctypes.c_int, [_vp, _HyP, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "hmc_step": (ctypes.c_int, [_vp, _HyP, ctypes.POINTER(HmcArgs), _vp]),

@@ -752,6 +752,40 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     fc->t1 = p->t1;
 }
 
+// Column pass and its finalisation on the plan's current w, a (Eq. 4, Eq. 5).
+static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, double *d_grad_theta,
+                       double *d_negH_theta, hipStream_t stream) {
+    hk_prof_mark(p, HK_PROF_COL, true, stream);
+    if (d_negH_theta)
+        hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->w,
+                           p->wlo, p->g, p->col_items, p->col_block0, p->colG, kc);
+    else
+        hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
+                           p->w, p->wlo, p->g, p->col_items, p->col_block0, p->colG, kc);
+    hk_prof_mark(p, HK_PROF_COL, false, stream);
+    hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(256), 0, stream, p->perm, p->n, p->col_item0, p->col_nseg,
+                       p->colG, p->a, fc, d_grad_theta, d_negH_theta);
+}
+
+extern "C" int64_t hawkes_plan_epoch(hawkes_plan p) { return p ? p->epoch : -1; }
+
+extern "C" hawkes_status hawkes_grad_theta_from_last(hawkes_plan p, const hawkes_hyper *hyper, int64_t epoch,
+                                                     double *d_grad_theta, double *d_negH_theta,
+                                                     hipStream_t stream) {
+    if (!p || !hk_hyper_ok(hyper) || (!d_grad_theta && !d_negH_theta)) return HAWKES_E_INVALID;
+    const hawkes_hyper &h = p->eval_hyper;
+    const bool same = h.mu0 == hyper->mu0 && h.tau_x == hyper->tau_x && h.tau_t == hyper->tau_t &&
+                      h.theta0 == hyper->theta0 && h.omega == hyper->omega && h.h == hyper->h;
+    if (p->eval_epoch == 0 || epoch != p->eval_epoch || p->epoch != p->eval_epoch || !same) return HAWKES_E_STALE;
+    p->last_stream = stream;
+    PairConst kc;
+    FinConst fc;
+    hk_make_consts(p, hyper, &kc, &fc);
+    launch_col(p, kc, fc, d_grad_theta, d_negH_theta, stream);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
 extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
                                      double *d_loglik, double *d_grad_theta, double *d_grad_hyper,
                                      double *d_negH_theta, double *d_negH_hyper, hipStream_t stream) {
@@ -786,18 +820,10 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 #undef HK_FIN
     hipLaunchKernelGGL(k_fin2, dim3(1), dim3(HK_NSUM * HK_FIN2_LANES), 0, stream, p->blockpart, p->nchunks,
                        d_loglik, d_grad_hyper, d_negH_hyper, p->status);
-    if (d_grad_theta || d_negH_theta) {
-        hk_prof_mark(p, HK_PROF_COL, true, stream);
-        if (d_negH_theta)
-            hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                               p->w, p->wlo, p->g, p->col_items, p->col_block0, p->colG, kc);
-        else
-            hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                               p->w, p->wlo, p->g, p->col_items, p->col_block0, p->colG, kc);
-        hk_prof_mark(p, HK_PROF_COL, false, stream);
-        hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(256), 0, stream, p->perm, p->n, p->col_item0,
-                           p->col_nseg, p->colG, p->a, fc, d_grad_theta, d_negH_theta);
-    }
+    p->epoch += 1;
+    p->eval_epoch = p->epoch;
+    p->eval_hyper = *hyper;
+    if (d_grad_theta || d_negH_theta) launch_col(p, kc, fc, d_grad_theta, d_negH_theta, stream);
     hk_prof_mark(p, HK_PROF_EVAL, false, stream);
     HK_CHECK(hipGetLastError());
     return HAWKES_OK;

@@ -726,6 +726,7 @@ hawkes_status ensure_static(hawkes_plan p, const hawkes_hyper *hy, const double 
 void sub_eval(hawkes_plan p, const double *z, double *theta_full, bool with_h, const PairConst &kc,
               const FinConst &fc, hipStream_t stream) {
     hk_subset *s = p->sub;
+    p->epoch += 1;  // p->lam and p->w are overwritten below
     hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, s->slot, s->cidx, s->m,
                        s->mpad, s->theta32, theta_full);
     hipLaunchKernelGGL(k_sub_row, dim3(p->nchunks), dim3(SUB_ROW_THREADS), 0, stream, p->ts, p->xi, p->yi, p->g,

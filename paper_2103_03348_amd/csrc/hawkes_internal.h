@@ -88,6 +88,9 @@ struct hawkes_plan_s {
     double *blockpart;        // [nchunks][HK_NSUM] per-block partial sums
     int *status;              // sticky device status bits
     hipStream_t last_stream;
+    int64_t epoch;            // intensity evaluations so far (host counter)
+    int64_t eval_epoch;       // epoch of the last hawkes_eval (its lam, w, a are current)
+    hawkes_hyper eval_hyper;  // hyperparameters of that evaluation
     struct hk_profile *prof;  // HIP-event timing of the passes (NULL when off)
     struct hk_subset *sub;    // free-rate subset for the HMC path (NULL until set)
 };

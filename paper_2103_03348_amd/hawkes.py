@@ -87,6 +87,24 @@ class Plan:
                                      stream_handle()), "hawkes_eval")
         return o
 
+    def epoch(self) -> int:
+        """hawkes_plan_epoch: evaluations run so far (pairs a backward with its forward)."""
+        return int(_lib.lib().hawkes_plan_epoch(self._h))
+
+    def grad_theta_from_last(self, hyper, epoch: int, negH: bool = False):
+        """hawkes_grad_theta_from_last: the column pass alone on the intensities of
+        the evaluation numbered `epoch`.  Returns (grad_theta, negH_theta or None),
+        or None if the plan has evaluated something else since (HAWKES_E_STALE)."""
+        g = self._vec(self.n)
+        h = self._vec(self.n) if negH else None
+        hy = Hyper.of(hyper)
+        code = _lib.lib().hawkes_grad_theta_from_last(self._h, ctypes.byref(hy), int(epoch), ptr(g), ptr(h),
+                                                      stream_handle())
+        if code == _lib.E_STALE:
+            return None
+        check(code, "hawkes_grad_theta_from_last")
+        return g, h
+
     def lam(self) -> torch.Tensor:
         """lambda_i of the last evaluation, caller order."""
         out = self._vec(self.n)

@@ -9,12 +9,17 @@ Tolerances (FP32 pair arithmetic, compensated sums, FP64 finals):
     with margin for sets where one term dominates).
   * rate gradient: 1e-6 relative to the magnitude of Eq. 4's two terms.
   * Hessian diagonal: 1e-6 relative (all terms positive) on every entry of
-    at least 1e-4 of the largest, and 1e-6 norm-wise.  A term with FP32
-    exponent argument a carries a relative error up to ~2 ln2 2^-24 |a| from the
-    argument's rounding (doubled by the square); entries of at least 1e-4 of the
-    largest are made of terms with |a| below ~7.  On all entries (|a| up to the
-    FP32 underflow at ~126): 3e-5, with an absolute floor of 1e-30 where the
-    squared terms underflow.
+    at least 1e-4 of the largest, and 1e-6 norm-wise.  The column pass forms
+    each exponent in FP64 and rounds it once, so a term with exponent a (log2
+    units) carries a relative error up to ~2 ln2 2^-25 |a| from that rounding,
+    doubled by the square; entries of at least 1e-4 of the largest are made of
+    terms with |a| below ~7.  On all entries (|a| up to the FP32 underflow at
+    ~126): 3e-5, with an absolute floor of 1e-30 where the squared terms
+    underflow.
+  * sparse data (chunks of 64 events spanning more than 40/omega in time), where
+    the pair passes use the direct exponent instead of the split time factor:
+    the row pass's FP32 exponent then carries the time term too, and lambda and
+    Eq. 5 inherit its rounding: Hessian 5e-6 on the significant entries.
   * hyperparameter derivatives on sets below 256 events, where a handful of
     FP32 terms carry each sum without averaging and the second derivatives in
     tau_x and h cancel three such sums: 5e-5 instead of 1e-6.
@@ -66,6 +71,21 @@ def test_small_ragged(gpu, n, seed, ties, dup):
     gpu_r = run_gpu(es)
     ref = oracle.evaluate_es(es)
     _check(es, gpu_r, ref, tiny=True)
+
+
+@pytest.mark.parametrize("n,seed", [(300, 31), (700, 32)])
+def test_sparse_fallback(gpu, n, seed):
+    es = synth.small(n, seed=seed, t_end=3.0 * n, ties=2)
+    g = run_gpu(es)
+    ref = oracle.evaluate_es(es)
+    e = errors(es, g, ref)
+    print(f"\n[sparse n={n}] " + " ".join(f"{k}={np.max(v):.3e}" for k, v in e.items()), flush=True)
+    assert g["status"] == 0
+    assert abs(g["loglik"] - ref["loglik"]) <= 2e-6 * es.n
+    assert e["lam_rel"] < 2e-6
+    assert e["g_rel"] < 1e-6
+    assert e["h_rel"] < 5e-6
+    assert e["h_rel_norm"] < 1e-6
 
 
 def test_workload_n1000(gpu):
