@@ -42,6 +42,28 @@ FLOPS_PER_PAIR = FLOPS_ROW_PER_PAIR + FLOPS_COL_PER_PAIR
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
+# HBM traffic of one k_row launch at N = 23,422, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by a device-to-device copy of known size (summary and
+# commands in profiles/k_row_k_col_N23422_counters.md): 5.7 MB read + 64.7 MB
+# written.  It holds only for the kernel sources it was measured on, so it is
+# reported only while their hashes match.
+K_ROW_TRAFFIC_BYTES = (2785.4375 * 2.0 + 63220.0 * 1.0) * 1024
+K_ROW_TRAFFIC_SOURCES = {
+    "paper_2103_03348_amd/csrc/hawkes_eval.hip": "ef2d723cbad81c2a047decda5b1cc69fab0ec953019971dd5f7c498c9dc7e9ab",
+    "paper_2103_03348_amd/csrc/hawkes_internal.h": "b066e375ca0fc397ce3a61c740c56e4fe75a8bdd95087b693c8102053deea3ec",
+    "paper_2103_03348_amd/csrc/hawkes_plan.hip": "0208d7a9d4e83b6b866ab7c7bdab277e8cfbac6d97f6dd6358b782f8d07b32d5",
+}
+
+
+def k_row_traffic():
+    import hashlib
+    for rel, digest in K_ROW_TRAFFIC_SOURCES.items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return K_ROW_TRAFFIC_BYTES
+
+
 CONFIGS = {1: "N23422_branching_M1610", 0: "N1000_uniform_mix5", 2: "N100000_branching_M6874",
            4: "N250000_branching_mix20_M17185"}
 
@@ -238,7 +260,8 @@ def main():
             "peak": PEAK_FP32_NONPACKED_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-            "traffic": None,
+            "traffic": k_row_traffic() if args.config == 1 else None,
+            "traffic_unit": "bytes per launch (HBM read + write)",
             "flops_per_pair": FLOPS_ROW_PER_PAIR,
             "kernel_ms": row_ms,
             "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
