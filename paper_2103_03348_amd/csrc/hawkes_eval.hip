@@ -574,29 +574,51 @@ __global__ __launch_bounds__(HK_NSUM * HK_FIN2_LANES) void k_fin2(const double *
 // each term E_ij w_i is good to a few FP32 roundings (H squares it, which
 // doubles its relative error, and an absolute rounding of the exponent becomes
 // a relative error of the term, so the exponent must not carry more).
+template <bool MASKED, bool FACT>
+__device__ __forceinline__ float col_term(const double2 *__restrict__ rxy, const float2 *__restrict__ rv,
+                                          const double *__restrict__ rtd, const int *__restrict__ rg, int s,
+                                          int jcol, double tsj, double xj, double yj, const PairConst kc) {
+    // coordinates pre-scaled in FP64, so that the spatial exponent is minus a
+    // squared distance, formed in FP64 and rounded once
+    const double2 p = rxy[s];
+    const double dx = p.x - xj, dy = p.y - yj;
+    const double aed = -fma(dx, dx, dy * dy);
+    // with the time term when the chunk is too wide for the split
+    float E = fexp2(FACT ? (float)aed : (float)fma(rtd[s] - tsj, kc.kw_d, aed));
+    if (MASKED) {
+        if (!(jcol < rg[s])) E = 0.0f;
+    }
+    const float2 v = rv[s];
+    return fmaf(E, v.y, E * v.x);
+}
+
+// Two interleaved streams of steps (even and odd rows of the chunk) with their
+// own accumulators: the FP64 exponent chains of neighbouring steps overlap.
+// The loop is kept short (HK_COL_UNROLL pairs of steps per iteration): a
+// deeper unroll hoists more LDS loads into registers, and at 130 VGPRs only
+// three wavefronts per SIMD fit, too few to hide the FP64 and exp latencies.
+#ifndef HK_COL_UNROLL
+#define HK_COL_UNROLL 2
+#endif
 template <bool WITH_H, bool MASKED, bool FACT>
 __device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const float2 *__restrict__ rv,
                                           const double *__restrict__ rtd, const int *__restrict__ rg, int jcol,
                                           double tsj, double xj, double yj, const PairConst kc, float &G, float &H) {
 #pragma clang fp contract(off)
-#pragma unroll 16
-    for (int s = 0; s < HK_WAVE; ++s) {
-        // coordinates pre-scaled in FP64, so that the spatial exponent is minus a
-        // squared distance, formed in FP64 and rounded once
-        const double2 p = rxy[s];
-        const double dx = p.x - xj, dy = p.y - yj;
-        const double aed = -fma(dx, dx, dy * dy);
-        // with the time term when the chunk is too wide for the split
-        const float E = fexp2(FACT ? (float)aed : (float)fma(rtd[s] - tsj, kc.kw_d, aed));
-        float Em = E;
-        if (MASKED) {
-            if (!(jcol < rg[s])) Em = 0.0f;
+    float G1 = 0.0f, H1 = 0.0f;
+#pragma unroll HK_COL_UNROLL
+    for (int s = 0; s < HK_WAVE; s += 2) {
+        const float e0 = col_term<MASKED, FACT>(rxy, rv, rtd, rg, s, jcol, tsj, xj, yj, kc);
+        const float e1 = col_term<MASKED, FACT>(rxy, rv, rtd, rg, s + 1, jcol, tsj, xj, yj, kc);
+        G += e0;
+        G1 += e1;
+        if (WITH_H) {
+            H = fmaf(e0, e0, H);
+            H1 = fmaf(e1, e1, H1);
         }
-        const float2 v = rv[s];
-        const float ew = fmaf(Em, v.y, Em * v.x);
-        G += ew;
-        if (WITH_H) H = fmaf(ew, ew, H);
     }
+    G += G1;
+    H += H1;
 }
 
 template <bool WITH_H>
