@@ -163,6 +163,56 @@ def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_
     return out
 
 
+def bench_hmc_large(es, iters=10, L=20, learned_every=50, exact_every=500, seed=11):
+    """Time of one full HMC iteration on the N = 250,000 workload (17,185 free
+    rates): L leapfrog steps, each an O(N M) subset evaluation (rate gradient
+    of Eq. 4 through the subset row and column passes), with the FP64 energy
+    and the accept decision on the device.  The mass refreshes are timed apart
+    and amortised over the schedule: a learned estimate (features + network
+    forward + mass update) every `learned_every` iterations and an exact one
+    (Eq. 5 on the subset) every `exact_every`.  The static part (one O(N^2)
+    row pass) is cached across iterations and timed as well."""
+    import numpy as np
+    import torch
+
+    from paper_2103_03348_amd.hawkes import Plan
+    from paper_2103_03348_amd.preconditioner import LearnedPreconditioner
+    from paper_2103_03348_amd.sampler import HmcSampler
+
+    dev = torch.device("cuda:0")
+    t = torch.as_tensor(es.t, device=dev)
+    xy = torch.as_tensor(np.stack([es.x, es.y], 1), device=dev).contiguous()
+    plan = Plan(t, xy, es.t0)
+    smp = HmcSampler(plan, torch.as_tensor(es.theta, device=dev), torch.as_tensor(es.subset, device=dev),
+                     es.hyper, sigma_z=0.5, L=L, seed=seed)
+    pre = LearnedPreconditioner(smp, t, xy, seed=seed)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    eps = 0.1
+    t_static = timed(lambda: smp.exact_curvature(), 1)  # first call builds the cached static part
+    smp.step(eps)
+    t_iter = timed(lambda: smp.step(eps), iters)
+    t_exact = timed(lambda: smp.fold_exact(), 3)
+    t_learned = timed(lambda: pre.fold_into_mass(smp), 3)
+    acc = float(smp.out[0].item())
+    plan.close()
+    n, m = es.n, int(es.subset.shape[0])
+    return {"n_events": n, "free_rates": m, "leapfrog": L,
+            "iteration_ms": 1e3 * t_iter,
+            "exact_refresh_ms": 1e3 * t_exact, "learned_refresh_ms": 1e3 * t_learned,
+            "first_subset_eval_with_static_ms": 1e3 * t_static,
+            "amortised_iteration_ms": 1e3 * (t_iter + t_learned / learned_every + t_exact / exact_every),
+            "schedule": {"learned_every": learned_every, "exact_every": exact_every},
+            "subset_pairs_per_leapfrog": float(n) * m, "last_accept": acc}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +225,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (HBM counter calibration)")
     ap.add_argument("--hmc-iters", type=int, default=2000)
+    ap.add_argument("--no-hmc-large", action="store_true",
+                    help="skip the HMC iteration timing on the N=250,000 workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path is built and measured on a single MI355X; "
@@ -273,6 +325,8 @@ def main():
     }
     if not args.no_hmc and args.config == 1:
         rec["hmc"] = bench_hmc(synth.config(3), n_iter=args.hmc_iters)
+    if not args.no_hmc and not args.no_hmc_large and args.config == 1:
+        rec["hmc_iteration_N250000"] = bench_hmc_large(synth.config(4))
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(es, args.cpu_budget)
     print(json.dumps(rec), flush=True)
