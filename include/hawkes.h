@@ -117,6 +117,16 @@ hawkes_status hawkes_hessdiag(hawkes_plan p, const hawkes_hyper *hyper, const do
  * clear it. */
 hawkes_status hawkes_plan_status(hawkes_plan p);
 
+/* Underflow cutoff (off by default).  When enabled, the pair passes skip a
+ * (row wavefront, column chunk) block whose time gap alone puts every term's
+ * exponent below -160 in log2 units -- exp(-omega dt) and
+ * exp(-dt^2/(2 tau_t^2)) under 2^-160 -- terms that are exactly zero in the
+ * FP32 background and below 1e-48 of a unit term in the excitation.  This is
+ * not part of the paper's method, which sums all pairs (Sec. 3.1); throughput
+ * with the cutoff is therefore reported apart from pair-evaluations.  Applies
+ * to hawkes_eval and the calls built on it. */
+hawkes_status hawkes_plan_set_cutoff(hawkes_plan p, int enabled);
+
 /* Number of intensity evaluations the plan has run so far: every hawkes_eval
  * (and every subset evaluation of the HMC path) increments it.  Host-side,
  * no synchronisation. */

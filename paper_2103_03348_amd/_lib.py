@@ -73,6 +73,7 @@ SIGNATURES = {
     "hawkes_plan_status": (ctypes.c_int, [_vp]),
     "hawkes_copy_lambda": (ctypes.c_int, [_vp, _vp, _vp]),
     "hawkes_plan_epoch": (_i64, [_vp]),
+    "hawkes_plan_set_cutoff": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hawkes_grad_theta_from_last": (ctypes.c_int, [_vp, _HyP, _i64, _vp, _vp, _vp]),
     "hawkes_plan_set_subset": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
     "hawkes_subset_grad": (ctypes.c_int, [_vp, _HyP, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),

@@ -232,6 +232,7 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         const int xr = xi[irow], yr = yi[irow], gr = g[irow];
         const int wave_chunk = I * HK_CHUNKS_PER_TILE + wv;
         const int wave_gmin = g[(int64_t)wave_chunk * HK_WAVE];  // g is non-decreasing
+        const double wave_tmin = ts[(int64_t)wave_chunk * HK_WAVE];  // the wave's earliest row
         const int64_t stride = (int64_t)(I + 1) * HK_TILE;
         float *__restrict__ cp = colpart + colpart_off[I];
 
@@ -271,7 +272,10 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
             for (int a = 0; a < HK_NROW; ++a) blk[a] = 0.0f;
 #pragma unroll
             for (int a = 0; a < HK_NCOL; ++a) C[a] = 0.0f;
-            if (c <= wave_chunk) {
+            // optional underflow cutoff: a chunk that ends more than dt_cut before
+            // the wave's earliest row contributes only terms below 2^-160
+            const bool live = c <= wave_chunk && !(wave_tmin - ts[(int64_t)c * HK_WAVE + HK_WAVE - 1] > kc.dt_cut);
+            if (live) {
                 if (fact)
                     row_sweep_masked<MODE, true>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
                                                  blk, C, B0d, X0c, C0d);
@@ -643,6 +647,7 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
         const double tsj = ts[jcol];
         const double xj = (double)xi[jcol] * kc.sx, yj = (double)yi[jcol] * kc.sx;
         const int wave_first = (int)(col0 + wv * HK_WAVE);
+        const double wave_tmax = ts[(int64_t)wave_first + HK_WAVE - 1];  // the wave's latest column
 
         double Gd = 0.0, Hd = 0.0;
         for (int c = it.c_begin; c < it.c_end; ++c) {
@@ -665,7 +670,9 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
             }
             __syncthreads();
             const int gmax = rg[HK_WAVE - 1], gmin = rg[0];
-            if (gmax > wave_first) {
+            // optional underflow cutoff: rows that all start more than dt_cut_ex
+            // after the wave's latest column give excitation terms below 2^-160
+            if (gmax > wave_first && !(Tc - wave_tmax > kc.dt_cut_ex)) {
                 const bool fact = fact_sh != 0;
                 float G = 0.0f, H = 0.0f;
                 const bool masked = gmin <= wave_first + HK_WAVE - 1;
@@ -753,6 +760,15 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     kc->omega = hy->omega;
     kc->kex_d = kex;
     kc->kw_d = kw;
+    // time gaps beyond which every background term (exponent <= kbt dt^2) and
+    // every excitation term (exponent <= kw dt) is below 2^-160: exactly zero in
+    // FP32, and below 1e-48 of a unit term in the split form
+    if (p->cutoff) {
+        kc->dt_cut_ex = -160.0 / kw;
+        kc->dt_cut = fmax(sqrt(-160.0 / kbt), kc->dt_cut_ex);
+    } else {
+        kc->dt_cut = kc->dt_cut_ex = INFINITY;
+    }
     kc->sx = sqrt(-kex);
     fc->rho_bx = ((double)kc->kbx - kbx) / (double)kc->kbx;
     fc->dkbt = (double)kc->kbt - kbt;
@@ -790,6 +806,12 @@ static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, d
 }
 
 extern "C" int64_t hawkes_plan_epoch(hawkes_plan p) { return p ? p->epoch : -1; }
+
+extern "C" hawkes_status hawkes_plan_set_cutoff(hawkes_plan p, int enabled) {
+    if (!p) return HAWKES_E_INVALID;
+    p->cutoff = enabled != 0;
+    return HAWKES_OK;
+}
 
 extern "C" hawkes_status hawkes_grad_theta_from_last(hawkes_plan p, const hawkes_hyper *hyper, int64_t epoch,
                                                      double *d_grad_theta, double *d_negH_theta,

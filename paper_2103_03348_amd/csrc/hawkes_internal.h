@@ -89,6 +89,7 @@ struct hawkes_plan_s {
     int *status;              // sticky device status bits
     hipStream_t last_stream;
     int64_t epoch;            // intensity evaluations so far (host counter)
+    int cutoff;               // skip chunk pairs whose terms all underflow (off by default)
     int64_t eval_epoch;       // epoch of the last hawkes_eval (its lam, w, a are current)
     hawkes_hyper eval_hyper;  // hyperparameters of that evaluation
     struct hk_profile *prof;  // HIP-event timing of the passes (NULL when off)
@@ -117,6 +118,8 @@ struct PairConst {
     double kex_d;  // kex and kw in FP64 (the column pass forms its exponent in FP64)
     double kw_d;
     double sx;     // sqrt(-kex): fixed-point coordinate -> coordinate whose squared distance is -a_e
+    double dt_cut;     // row pass: time gap past which both terms are below 2^-160 (INFINITY: no cutoff)
+    double dt_cut_ex;  // column pass: the same for the excitation term alone
 };
 
 struct FinConst {

@@ -87,6 +87,10 @@ class Plan:
                                      stream_handle()), "hawkes_eval")
         return o
 
+    def set_cutoff(self, enabled: bool):
+        """hawkes_plan_set_cutoff: skip pair blocks whose terms all underflow."""
+        check(_lib.lib().hawkes_plan_set_cutoff(self._h, int(bool(enabled))), "hawkes_plan_set_cutoff")
+
     def epoch(self) -> int:
         """hawkes_plan_epoch: evaluations run so far (pairs a backward with its forward)."""
         return int(_lib.lib().hawkes_plan_epoch(self._h))
