@@ -202,6 +202,11 @@ def bench_hmc_large(es, iters=10, L=20, learned_every=50, exact_every=500, seed=
     t_exact = timed(lambda: smp.fold_exact(), 3)
     t_learned = timed(lambda: pre.fold_into_mass(smp), 3)
     acc = float(smp.out[0].item())
+    # the same iteration with the underflow cutoff (reported apart)
+    plan.set_cutoff(True)
+    smp.step(eps)
+    t_iter_cut = timed(lambda: smp.step(eps), iters)
+    plan.set_cutoff(False)
     plan.close()
     n, m = es.n, int(es.subset.shape[0])
     return {"n_events": n, "free_rates": m, "leapfrog": L,
@@ -210,6 +215,7 @@ def bench_hmc_large(es, iters=10, L=20, learned_every=50, exact_every=500, seed=
             "first_subset_eval_with_static_ms": 1e3 * t_static,
             "amortised_iteration_ms": 1e3 * (t_iter + t_learned / learned_every + t_exact / exact_every),
             "schedule": {"learned_every": learned_every, "exact_every": exact_every},
+            "iteration_ms_with_underflow_cutoff": 1e3 * t_iter_cut,
             "subset_pairs_per_leapfrog": float(n) * m, "last_accept": acc}
 
 

@@ -241,7 +241,16 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         for (int a = 0; a < HK_NROW; ++a) hi[a] = lo[a] = 0.0f;
         double B0d = 0.0, X0d = 0.0;
 
+        const double tile_tmin = ts[row0];
         for (int c = it.c_begin; c < it.c_end; ++c) {
+            // under the cutoff a chunk that ends more than dt_cut before the
+            // tile's first row is skipped by the whole block: its column
+            // partials are zero
+            if (tile_tmin - ts[(int64_t)c * HK_WAVE + HK_WAVE - 1] > kc.dt_cut) {
+                for (int e = tid; e < NC * HK_WAVE; e += HK_TILE)
+                    cp[(e / HK_WAVE) * stride + (int64_t)c * HK_WAVE + e % HK_WAVE] = 0.0f;
+                continue;
+            }
             // times relative to the chunk's first event: for the pairs that carry
             // the sums (close in time) both operands of dt are then small and
             // exact to FP32
@@ -649,9 +658,13 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
         const int wave_first = (int)(col0 + wv * HK_WAVE);
         const double wave_tmax = ts[(int64_t)wave_first + HK_WAVE - 1];  // the wave's latest column
 
+        const double tile_tmax = ts[col0 + HK_TILE - 1];
         double Gd = 0.0, Hd = 0.0;
         for (int c = it.c_begin; c < it.c_end; ++c) {
             const double Tc = ts[(int64_t)c * HK_WAVE];
+            // under the cutoff, rows starting more than dt_cut_ex after the
+            // tile's latest column end the sweep (times are sorted)
+            if (Tc - tile_tmax > kc.dt_cut_ex) break;
             if (tid < HK_WAVE) {
                 // the staging threads are wavefront 0: one vote decides the split
                 const int64_t i = (int64_t)c * HK_WAVE + tid;

@@ -285,7 +285,11 @@ __global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
     const int nsub = cnt[b];
     double acc = 0.0;  // every term in FP64 (see the row pass: FP32 sums drop small terms)
     float mae = 0.0f;  // sum theta E a_e (rounding of the FP32 spatial constant)
+    // under the cutoff, batches whose last entry precedes the chunk's first row
+    // by more than dt_cut_ex are skipped (entries are in time order)
+    const double chunk_tmin = ts[(int64_t)b * HK_WAVE];
     for (int c0 = 0; c0 < nsub; c0 += HK_WAVE) {
+        if (chunk_tmin - ts[pos[min(c0 + HK_WAVE, nsub) - 1]] > kc.dt_cut_ex) continue;
         const double Tr = ts[pos[c0]];
         bool fact;
         {
@@ -391,9 +395,14 @@ __global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ 
     const int pj = live ? pos[r] : 0;
     const double tsj = ts[pj];
     const double xj = (double)xi[pj] * kc.sx, yj = (double)yi[pj] * kc.sx;
+    // the tile's latest entry (entries are in time order; padding entries
+    // repeat position 0 and do not raise it)
+    const int64_t r_last = min((int64_t)it.tile * HK_TILE + HK_TILE, m) - 1;
+    const double tile_tmax = ts[pos[r_last]];
     double Gd = 0.0, Hd = 0.0;
     for (int c = it.c_begin; c < it.c_end; ++c) {
         const double Tc = ts[(int64_t)c * HK_WAVE];
+        if (Tc - tile_tmax > kc.dt_cut_ex) break;  // cutoff: all later rows too far
         if (tid < HK_WAVE) {
             const int64_t i = (int64_t)c * HK_WAVE + tid;
             const double ti = ts[i];
