@@ -177,9 +177,27 @@ hawkes_status hawkes_subset_grad(hawkes_plan p, const hawkes_hyper *hyper, const
                                  int refresh_static, double *d_loglik, double *d_grad_sub, double *d_negH_sub,
                                  hipStream_t stream);
 
+/* Eq. 1 and its gradients in the log-rates z and the temporal-trend
+ * coefficient beta of Sec. 2.2, where the subset rates are
+ * theta_k = exp(z_k + beta t_k) (f(t) = t) and every other rate is fixed:
+ *   d loglik / d z_k  = theta_k (Eq. 4)_k
+ *   d loglik / d beta = sum_k t_k theta_k (Eq. 4)_k          -- O(M) after Eq. 4
+ *   d_z        [m] log-rates, slot order (device, read)
+ *   beta       trend coefficient (finite; 0 = no trend)
+ *   d_theta    [n] full rates, caller order: read off the subset (fixed rates),
+ *              written on the subset with exp(z_k + beta t_k)
+ *   d_loglik [1], d_grad_z [m] (slot order), d_grad_beta [1]: outputs, each may be NULL
+ * Needs hawkes_plan_set_subset first (else HAWKES_E_UNSUPPORTED). */
+hawkes_status hawkes_subset_trend_grad(hawkes_plan p, const hawkes_hyper *hyper, const double *d_z, double beta,
+                                       double *d_theta, double *d_loglik, double *d_grad_z, double *d_grad_beta,
+                                       hipStream_t stream);
+
 /* One HMC iteration on z (slot order) with target
- *   log pi(z) = loglik(theta(z)) - sum_k z_k^2 / (2 sigma_z^2)
- * (the prior of Eq. 2 with V = I), energy H = -log pi(z) + p^T M^{-1} p / 2, and
+ *   log pi(z) = loglik(theta(z)) - sum_k z_k^2 / (2 sigma_z^2),
+ *   theta_k = exp(z_k + beta t_k)
+ * (the prior of Eq. 2 with V = I; beta is the temporal-trend coefficient of
+ * Sec. 2.2, held fixed within the iteration), energy
+ * H = -log pi(z) + p^T M^{-1} p / 2, and
  * L leapfrog steps of size eps with dz/dt = M^{-1} p.  Momenta p_k = sqrt(M_k) *
  * N(0,1) from Philox-4x32-10 (Salmon et al. 2011) with key `seed` and counter
  * (k, 0, counter_lo, counter_hi), standard normals by Box-Muller
@@ -189,7 +207,7 @@ hawkes_status hawkes_subset_grad(hawkes_plan p, const hawkes_hyper *hyper, const
 typedef struct {
     double *d_z;           /* [m] log-rates, slot order (in: current; out: next state)         */
     double *d_theta;       /* [n] full rates, caller order; entries of the subset are written  */
-                           /*     with exp(z), the others are read as the fixed rates          */
+                           /*     with exp(z + beta t), the others are read as the fixed rates */
     const double *d_mass;  /* [m] diagonal mass matrix M (momentum covariance), slot order     */
     double eps;            /* leapfrog step size > 0                                            */
     int L;                 /* leapfrog steps >= 1                                               */
@@ -199,6 +217,7 @@ typedef struct {
     int refresh_static;    /* non-zero: recompute the cached static part first                  */
     double *d_out;         /* [8] device: accepted (1/0), H1 - H0, loglik and log pi at the
                               returned state, min(1, exp(-(H1-H0))), loglik at the proposal, H0, H1 */
+    double beta;           /* temporal-trend coefficient (0: theta_k = exp(z_k))              */
 } hawkes_hmc_args;
 
 hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawkes_hmc_args *args, hipStream_t stream);

@@ -2,8 +2,8 @@
 in FP64 on the CPU (Sec. 2.3.2).  Test infrastructure only.
 
 Target: log pi(z) = loglik(theta(z)) - sum_k z_k^2 / (2 sigma_z^2), with
-theta_{idx_k} = exp(z_k) and every other rate held fixed (Sec. 2.2 with
-beta = 0; the phylogenetic prior of Eq. 2 with V = I).  Energy
+theta_{idx_k} = exp(z_k + beta t_{idx_k}) and every other rate held fixed
+(Sec. 2.2 with f(t) = t; the phylogenetic prior of Eq. 2 with V = I).  Energy
 H(z, p) = -log pi(z) + p^T M^{-1} p / 2 with a diagonal mass M.  The leapfrog
 integrator uses dz/dt = M^{-1} p (the paper prints a factor 1/2 there, read
 here as a typo).  Momenta and the Metropolis uniform come from Philox-4x32-10
@@ -17,28 +17,45 @@ import numpy as np
 from . import evaluate, philox
 
 
-def log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z):
-    th = theta_full.copy()
-    th[idx] = np.exp(z)
+def rates(es_t, theta_full, idx, z, beta=0.0):
+    """theta with the subset entries exp(z_k + beta t_k) (Sec. 2.2, f(t) = t)."""
+    th = np.array(theta_full, dtype=np.float64, copy=True)
+    th[idx] = np.exp(np.asarray(z) + beta * np.asarray(es_t)[idx])
+    return th
+
+
+def trend_grad(es_t, es_x, es_y, theta_full, idx, z, beta, hyper, t0):
+    """loglik and its gradients in z and beta by the chain rule through
+    theta_k = exp(z_k + beta t_k):  d/dz_k = theta_k g_k,
+    d/dbeta = sum_k t_k theta_k g_k, with g = Eq. 4 on the subset."""
+    th = rates(es_t, theta_full, idx, z, beta)
+    r = evaluate(es_t, es_x, es_y, th, hyper, t0, want=("loglik", "grad_theta"))
+    gz = th[idx] * r["grad_theta"][idx]
+    return r["loglik"], gz, float(np.sum(np.asarray(es_t)[idx] * gz))
+
+
+def log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z, beta=0.0):
+    th = rates(es_t, theta_full, idx, z, beta)
     r = evaluate(es_t, es_x, es_y, th, hyper, t0, want=("loglik", "grad_theta", "negH_theta"))
     ll = r["loglik"]
     g = r["grad_theta"][idx]
     lp = ll - float(np.sum(z * z)) / (2.0 * sigma_z ** 2)
-    grad_z = np.exp(z) * g - z / sigma_z ** 2
+    grad_z = th[idx] * g - z / sigma_z ** 2
     return lp, grad_z, ll, r
 
 
-def hmc_iteration(es_t, es_x, es_y, theta_full, idx, z0, mass, hyper, t0, eps, L, sigma_z, seed, counter):
+def hmc_iteration(es_t, es_x, es_y, theta_full, idx, z0, mass, hyper, t0, eps, L, sigma_z, seed, counter,
+                  beta=0.0):
     """Returns dict(z, accepted, dH, loglik, logpost, z_proposal, H0, H1)."""
     z0 = np.asarray(z0, dtype=np.float64)
     mass = np.asarray(mass, dtype=np.float64)
     p0 = np.sqrt(mass) * philox.normals(seed, counter, z0.shape[0])
-    lp0, g, ll0, _ = log_post(es_t, es_x, es_y, theta_full, idx, z0, hyper, t0, sigma_z)
+    lp0, g, ll0, _ = log_post(es_t, es_x, es_y, theta_full, idx, z0, hyper, t0, sigma_z, beta)
     z = z0.copy()
     p = p0 + 0.5 * eps * g
     for step in range(L):
         z = z + eps * p / mass
-        lp, g, ll, _ = log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z)
+        lp, g, ll, _ = log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z, beta)
         p = p + (eps if step < L - 1 else 0.5 * eps) * g
     H0 = -lp0 + 0.5 * float(np.sum(p0 * p0 / mass))
     H1 = -lp + 0.5 * float(np.sum(p * p / mass))

@@ -13,7 +13,8 @@
 //
 // Kernels:
 //   k_sub_static   partial sums of the static row pass -> lambda_static_i
-//   k_sub_theta    theta_k = exp(z_k) into FP32 subset order and the caller's theta
+//   k_sub_offset   temporal-trend offsets beta t_k (Sec. 2.2)
+//   k_sub_theta    theta_k = exp(z_k + beta t_k) into FP32 subset order and the caller's theta
 //   k_sub_row      X_i = sum_{k in M, t_k < t_i} theta_k E_ik (rows = all events)
 //   k_sub_fin      lambda_i, w_i = c_e / lambda_i, block sums of log lambda_i
 //   k_sub_col      G_k = sum_{t_i > t_k} E_ik w_i, H_k = sum (E_ik w_i)^2
@@ -56,6 +57,7 @@ struct hk_subset {
     double *sums;        // [8] loglik pieces of the last evaluation
     // HMC state
     double *z0, *p, *gz; // [m] slot order
+    double *off;         // [m] temporal-trend offsets beta t_k, slot order
     double *scal;        // [16] energies and flags
     // feature grids of the learned preconditioner
     int *grid;
@@ -222,15 +224,28 @@ __global__ void k_sub_a(const double *__restrict__ ts, const int *__restrict__ p
 }
 
 // ---- per-evaluation kernels ---------------------------------------------------------------
+// log theta_k = z_k + off_k: off is the temporal-trend term beta f(t_k) of Sec.
+// 2.2 (slot order), or NULL for none.
+__device__ __forceinline__ double zeff(const double *__restrict__ z, const double *__restrict__ off, int64_t k) {
+    return off ? z[k] + off[k] : z[k];
+}
+
+// off_k = beta t_k for the subset events (their times, slot order)
+__global__ void k_sub_offset(const double *__restrict__ ts, const int *__restrict__ pos,
+                             const int *__restrict__ slot, int64_t m, double beta, double *__restrict__ off) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r < m) off[slot[r]] = beta * ts[pos[r]];
+}
+
 // theta_k = exp(z_k): FP32 copy in time order, FP64 into the caller's full rate vector
-__global__ void k_sub_theta(const double *__restrict__ z, const int *__restrict__ slot,
-                            const int64_t *__restrict__ cidx, int64_t m, int64_t mpad, float *__restrict__ theta32,
-                            double *__restrict__ theta_full) {
+__global__ void k_sub_theta(const double *__restrict__ z, const double *__restrict__ off,
+                            const int *__restrict__ slot, const int64_t *__restrict__ cidx, int64_t m, int64_t mpad,
+                            float *__restrict__ theta32, double *__restrict__ theta_full) {
     int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= mpad) return;
     if (r < m) {
         const int k = slot[r];
-        const double th = exp(z[k]);
+        const double th = exp(zeff(z, off, k));
         theta32[r] = (float)th;
         if (theta_full) theta_full[cidx[k]] = th;
     } else {
@@ -465,7 +480,8 @@ __global__ void k_sub_scatter(const int *__restrict__ slot, int64_t m, const dou
 // out[0] = sum log lambda (from block partials), out[1] = sum theta_k a_k,
 // out[2] = sum z_k^2, out[3] = sum p_k^2 / M_k
 __global__ __launch_bounds__(256) void k_sub_energy(const double *__restrict__ loglam_part, int nb,
-                                                    const double *__restrict__ z, const double *__restrict__ p,
+                                                    const double *__restrict__ z, const double *__restrict__ off,
+                                                    const double *__restrict__ p,
                                                     const double *__restrict__ mass, const int *__restrict__ slot,
                                                     const double *__restrict__ a, int64_t m,
                                                     double *__restrict__ out) {
@@ -474,7 +490,7 @@ __global__ __launch_bounds__(256) void k_sub_energy(const double *__restrict__ l
     for (int b = threadIdx.x; b < nb; b += 256) s[0] += loglam_part[b];
     for (int64_t r = threadIdx.x; r < m; r += 256) {
         const int k = slot[r];
-        s[1] += exp(z[k]) * a[r];
+        s[1] += exp(zeff(z, off, k)) * a[r];
         s[2] += z[k] * z[k];
         if (p) s[3] += p[k] * p[k] / mass[k];
     }
@@ -527,11 +543,12 @@ __global__ void k_hmc_init(int64_t m, uint64_t seed, uint64_t counter, const dou
 
 // grad_z log pi = theta_k g_k - z_k / sigma^2 in slot order
 __global__ void k_hmc_gradz(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
-                            const double *__restrict__ z, double inv_s2, double *__restrict__ gz) {
+                            const double *__restrict__ z, const double *__restrict__ off, double inv_s2,
+                            double *__restrict__ gz) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= m) return;
     const int k = slot[r];
-    gz[k] = exp(z[k]) * gsub[r] - z[k] * inv_s2;
+    gz[k] = exp(zeff(z, off, k)) * gsub[r] - z[k] * inv_s2;
 }
 
 // p += a_p * grad; then (if a_z != 0) z += a_z * p / M
@@ -580,10 +597,10 @@ __global__ void k_hmc_accept(const double *__restrict__ scal, const double *__re
 }
 
 // theta_full[idx_k] = exp(z_k) (after a rejection restores z)
-__global__ void k_sub_theta_full(const double *__restrict__ z, const int64_t *__restrict__ cidx, int64_t m,
-                                 double *__restrict__ theta_full) {
+__global__ void k_sub_theta_full(const double *__restrict__ z, const double *__restrict__ off,
+                                 const int64_t *__restrict__ cidx, int64_t m, double *__restrict__ theta_full) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k < m) theta_full[cidx[k]] = exp(z[k]);
+    if (k < m) theta_full[cidx[k]] = exp(zeff(z, off, k));
 }
 
 template <class T>
@@ -599,7 +616,7 @@ void hk_subset_free(hawkes_plan p) {
     hk_subset *s = p->sub;
     if (!s) return;
     void *ptrs[] = {s->pos, s->slot, s->cidx, s->cnt, s->items, s->item0, s->nseg, s->lam_static, s->Lam_static,
-                    s->a, s->theta32, s->xs, s->xmom, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->scal,
+                    s->a, s->theta32, s->xs, s->xmom, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->off, s->scal,
                     s->grid};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -694,6 +711,7 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     SC(dalloc(&s->z0, m));
     SC(dalloc(&s->p, m));
     SC(dalloc(&s->gz, m));
+    SC(dalloc(&s->off, m));
     SC(dalloc(&s->scal, 16));
 #undef SC
     s->static_valid = false;
@@ -732,11 +750,11 @@ hawkes_status ensure_static(hawkes_plan p, const hawkes_hyper *hy, const double 
 
 // One subset evaluation at z (slot order): theta, lambda, w, Eq. 4 (and Eq. 5)
 // on the subset, block partial sums of log lambda in p->blockpart.
-void sub_eval(hawkes_plan p, const double *z, double *theta_full, bool with_h, const PairConst &kc,
-              const FinConst &fc, hipStream_t stream) {
+void sub_eval(hawkes_plan p, const double *z, const double *off, double *theta_full, bool with_h,
+              const PairConst &kc, const FinConst &fc, hipStream_t stream) {
     hk_subset *s = p->sub;
     p->epoch += 1;  // p->lam and p->w are overwritten below
-    hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, s->slot, s->cidx, s->m,
+    hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, off, s->slot, s->cidx, s->m,
                        s->mpad, s->theta32, theta_full);
     hipLaunchKernelGGL(k_sub_row, dim3(p->nchunks), dim3(SUB_ROW_THREADS), 0, stream, p->ts, p->xi, p->yi, p->g,
                        s->pos, s->theta32, s->cnt, kc, s->xs, s->xmom);
@@ -757,6 +775,30 @@ __global__ void k_z_from_theta(const double *__restrict__ theta, const int64_t *
                                double *__restrict__ z) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k < m) z[k] = log(theta[cidx[k]]);
+}
+
+// d loglik / d z_k = theta_k g_k and d loglik / d beta = sum_k t_k theta_k g_k
+// for log theta_k = z_k + beta t_k; one block, fixed-order tree reduction.
+__global__ __launch_bounds__(256) void k_sub_trend_out(const int *__restrict__ slot, const int *__restrict__ pos,
+                                                       const double *__restrict__ ts, int64_t m,
+                                                       const double *__restrict__ gsub, const double *__restrict__ z,
+                                                       const double *__restrict__ off, double *__restrict__ grad_z,
+                                                       double *__restrict__ grad_beta) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t r = threadIdx.x; r < m; r += 256) {
+        const int k = slot[r];
+        const double gz = exp(zeff(z, off, k)) * gsub[r];
+        if (grad_z) grad_z[k] = gz;
+        acc += ts[pos[r]] * gz;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && grad_beta) grad_beta[0] = sh[0];
 }
 
 __global__ void k_sub_loglik_out(const double *__restrict__ e, const double *__restrict__ Lam_static,
@@ -780,12 +822,13 @@ extern "C" hawkes_status hawkes_subset_grad(hawkes_plan p, const hawkes_hyper *h
     if (st != HAWKES_OK) return st;
     // z = log theta on the subset (the rates are taken from d_theta as given)
     hipLaunchKernelGGL(k_z_from_theta, dim3(nblk(s->m, 256)), dim3(256), 0, stream, d_theta, s->cidx, s->m, s->z0);
-    sub_eval(p, s->z0, nullptr, d_negH_sub != nullptr, kc, fc, stream);
+    sub_eval(p, s->z0, nullptr, nullptr, d_negH_sub != nullptr, kc, fc, stream);
     hipLaunchKernelGGL(k_sub_scatter, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->slot, s->m, s->gsub, s->hsub,
                        d_grad_sub, d_negH_sub);
     if (d_loglik) {
         hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, s->z0,
-                           (const double *)nullptr, (const double *)nullptr, s->slot, s->a, s->m, s->scal);
+                           (const double *)nullptr, (const double *)nullptr, (const double *)nullptr, s->slot, s->a,
+                           s->m, s->scal);
         hipLaunchKernelGGL(k_sub_loglik_out, dim3(1), dim3(64), 0, stream, s->scal, s->Lam_static, d_loglik);
     }
     HK_CHECK(hipGetLastError());
@@ -808,27 +851,65 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
     const int64_t m = s->m;
     const double inv_s2 = 1.0 / (a->sigma_z * a->sigma_z);
     const unsigned gb = nblk(m, 256);
+    // temporal trend: log theta_k = z_k + beta t_k
+    const double *off = nullptr;
+    if (a->beta != 0.0) {
+        hipLaunchKernelGGL(k_sub_offset, dim3(gb), dim3(256), 0, stream, p->ts, s->pos, s->slot, m, a->beta, s->off);
+        off = s->off;
+    }
     hipLaunchKernelGGL(k_hmc_init, dim3(gb), dim3(256), 0, stream, m, a->seed, a->counter, a->d_mass, a->d_z, s->p,
                        s->z0);
     // start of the trajectory
-    sub_eval(p, a->d_z, a->d_theta, false, kc, fc, stream);
-    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, s->p,
+    sub_eval(p, a->d_z, off, a->d_theta, false, kc, fc, stream);
+    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal);
-    hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, inv_s2, s->gz);
+    hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, off, inv_s2, s->gz);
     for (int l = 0; l < a->L; ++l) {
         // half kick at the start, full kicks between drifts
         hipLaunchKernelGGL(k_hmc_kick_drift, dim3(gb), dim3(256), 0, stream, m, l == 0 ? 0.5 * a->eps : a->eps,
                            s->gz, a->eps, a->d_mass, s->p, a->d_z);
-        sub_eval(p, a->d_z, a->d_theta, false, kc, fc, stream);
-        hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, inv_s2, s->gz);
+        sub_eval(p, a->d_z, off, a->d_theta, false, kc, fc, stream);
+        hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, off, inv_s2,
+                           s->gz);
     }
     hipLaunchKernelGGL(k_hmc_kick_drift, dim3(gb), dim3(256), 0, stream, m, 0.5 * a->eps, s->gz, 0.0, a->d_mass,
                        s->p, a->d_z);
-    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, s->p,
+    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal + 4);
     hipLaunchKernelGGL(k_hmc_accept, dim3(1), dim3(256), 0, stream, s->scal, s->Lam_static, inv_s2, a->seed,
                        a->counter, m, s->z0, a->d_z, a->d_out, (int *)(s->scal + 8));
-    hipLaunchKernelGGL(k_sub_theta_full, dim3(gb), dim3(256), 0, stream, a->d_z, s->cidx, m, a->d_theta);
+    hipLaunchKernelGGL(k_sub_theta_full, dim3(gb), dim3(256), 0, stream, a->d_z, off, s->cidx, m, a->d_theta);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
+extern "C" hawkes_status hawkes_subset_trend_grad(hawkes_plan p, const hawkes_hyper *hyper, const double *d_z,
+                                                  double beta, double *d_theta, double *d_loglik, double *d_grad_z,
+                                                  double *d_grad_beta, hipStream_t stream) {
+    if (!p || !hk_hyper_ok(hyper) || !d_z || !d_theta || !isfinite(beta)) return HAWKES_E_INVALID;
+    if (!p->sub) return HAWKES_E_UNSUPPORTED;
+    hk_subset *s = p->sub;
+    p->last_stream = stream;
+    PairConst kc;
+    FinConst fc;
+    hk_make_consts(p, hyper, &kc, &fc);
+    hawkes_status st = ensure_static(p, hyper, d_theta, false, kc, fc, stream);
+    if (st != HAWKES_OK) return st;
+    const unsigned gb = nblk(s->m, 256);
+    const double *off = nullptr;
+    if (beta != 0.0) {
+        hipLaunchKernelGGL(k_sub_offset, dim3(gb), dim3(256), 0, stream, p->ts, s->pos, s->slot, s->m, beta, s->off);
+        off = s->off;
+    }
+    sub_eval(p, d_z, off, d_theta, false, kc, fc, stream);
+    if (d_grad_z || d_grad_beta)
+        hipLaunchKernelGGL(k_sub_trend_out, dim3(1), dim3(256), 0, stream, s->slot, s->pos, p->ts, s->m, s->gsub, d_z,
+                           off, d_grad_z, d_grad_beta);
+    if (d_loglik) {
+        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, d_z, off,
+                           (const double *)nullptr, (const double *)nullptr, s->slot, s->a, s->m, s->scal);
+        hipLaunchKernelGGL(k_sub_loglik_out, dim3(1), dim3(64), 0, stream, s->scal, s->Lam_static, d_loglik);
+    }
     HK_CHECK(hipGetLastError());
     return HAWKES_OK;
 }
@@ -866,7 +947,7 @@ hawkes_status hk_subset_exact(hawkes_plan p, const hawkes_hyper *hy, const doubl
     hawkes_status st = ensure_static(p, hy, d_theta, false, kc, fc, stream);
     if (st != HAWKES_OK) return st;
     hipLaunchKernelGGL(k_z_from_theta, dim3(nblk(s->m, 256)), dim3(256), 0, stream, d_theta, s->cidx, s->m, s->z0);
-    sub_eval(p, s->z0, nullptr, true, kc, fc, stream);
+    sub_eval(p, s->z0, nullptr, nullptr, true, kc, fc, stream);
     HK_CHECK(hipGetLastError());
     *gsub = s->gsub;
     *hsub = s->hsub;

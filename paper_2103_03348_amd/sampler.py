@@ -59,7 +59,7 @@ class HmcSampler:
     """HMC over z = log theta on the subset `idx` of a plan's events."""
 
     def __init__(self, plan: Plan, theta: torch.Tensor, idx: torch.Tensor, hyper, sigma_z=0.5, L=20, seed=1,
-                 jitter=0.5):
+                 jitter=0.5, beta=0.0):
         self.plan = plan
         self.dev = theta.device
         self.theta = theta.clone().contiguous()
@@ -73,8 +73,10 @@ class HmcSampler:
         self.seed = int(seed)
         self.counter = 0
         self.jitter = float(jitter)
+        self.beta = float(beta)  # temporal trend: theta_k = exp(z_k + beta t_k) (Sec. 2.2)
         self._jrng = np.random.default_rng(seed)
-        self.z = torch.log(self.theta[self.idx]).contiguous()
+        t_sub = plan._t[self.idx]
+        self.z = (torch.log(self.theta[self.idx]) - self.beta * t_sub).contiguous()
         self.mass = torch.full((self.m,), 1.0 / self.sigma_z ** 2, dtype=torch.float64, device=self.dev)
         self.mass_count = 0
         self.out = torch.zeros(8, dtype=torch.float64, device=self.dev)
@@ -105,12 +107,25 @@ class HmcSampler:
                                                  _lib.stream_handle()), "hawkes_mass_update")
         self.mass_count += 1
 
+    def trend_grad(self, beta=None):
+        """hawkes_subset_trend_grad at the current z: (loglik, d/dz [m], d/dbeta) as
+        device tensors; also writes theta on the subset for that beta."""
+        b = self.beta if beta is None else float(beta)
+        ll = torch.empty(1, dtype=torch.float64, device=self.dev)
+        gz = torch.empty(self.m, dtype=torch.float64, device=self.dev)
+        gb = torch.empty(1, dtype=torch.float64, device=self.dev)
+        _lib.check(_lib.lib().hawkes_subset_trend_grad(self.plan.handle, ctypes.byref(self.hyper),
+                                                       _lib.ptr(self.z), b, _lib.ptr(self.theta), _lib.ptr(ll),
+                                                       _lib.ptr(gz), _lib.ptr(gb), _lib.stream_handle()),
+                   "hawkes_subset_trend_grad")
+        return ll, gz, gb
+
     # ---- one iteration ------------------------------------------------------------------------
     def step(self, eps):
         if self.jitter > 0:
             eps = eps * self._jrng.uniform(1.0 - self.jitter, 1.0 + self.jitter)
         args = _lib.HmcArgs(self.z.data_ptr(), self.theta.data_ptr(), self.mass.data_ptr(), float(eps), self.L,
-                            self.sigma_z, self.seed, self.counter, 0, self.out.data_ptr())
+                            self.sigma_z, self.seed, self.counter, 0, self.out.data_ptr(), self.beta)
         _lib.check(_lib.lib().hmc_step(self.plan.handle, ctypes.byref(self.hyper), ctypes.byref(args),
                                        _lib.stream_handle()), "hmc_step")
         self.counter += 1

@@ -158,3 +158,77 @@ def test_hmc_samples_prior_without_excitation(gpu):
     assert abs(d.mean()) < 0.03
     assert abs(d.var() - sig ** 2) < 0.02
     assert stats.kstest(d[::7, 0] / sig, "norm").pvalue > 1e-3
+
+
+def test_trend_gradient_matches_oracle(gpu):
+    """Sec. 2.2's temporal trend theta_k = exp(z_k + beta t_k): loglik, d/dz and
+    d/dbeta of the subset path against the oracle's chain rule (itself pinned
+    by finite differences in test_oracle_pins)."""
+    import torch
+
+    from paper_2103_03348_amd import _lib
+
+    es = synth.small(1500, seed=43, ties=4, all_free=False)
+    plan, idx = _setup(es)
+    m = es.subset.shape[0]
+    rng = np.random.default_rng(43)
+    z = 0.4 * rng.standard_normal(m)
+    beta = -0.006   # times span [0, 150]
+    dz = torch.as_tensor(z, device="cuda:0")
+    th = torch.as_tensor(es.theta.copy(), device="cuda:0")
+    ll = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    gz = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+    gb = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    hy = _lib.Hyper.of(es.hyper)
+    _lib.check(_lib.lib().hawkes_subset_trend_grad(plan.handle, ctypes.byref(hy), _lib.ptr(dz), beta, _lib.ptr(th),
+                                                   _lib.ptr(ll), _lib.ptr(gz), _lib.ptr(gb), _lib.stream_handle()),
+               "trend")
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    ll_o, gz_o, gb_o = ohmc.trend_grad(es.t, es.x, es.y, es.theta, es.subset, z, beta, es.hyper, es.t0)
+    th_o = ohmc.rates(es.t, es.theta, es.subset, z, beta)
+    np.testing.assert_allclose(th.cpu().numpy(), th_o, rtol=1e-15)
+    a = es.hyper[3] * (1.0 - np.exp(-es.hyper[4] * (es.t.max() - es.t[es.subset])))
+    r = oracle.evaluate_es(es, theta=th_o, want=("grad_theta",))
+    scale_z = th_o[es.subset] * (np.abs(r["grad_theta"][es.subset]) + 2 * a)   # C11 scale through the chain rule
+    rel_l = abs(float(ll.item()) - ll_o) / abs(ll_o)
+    rel_z = np.max(np.abs(gz.cpu().numpy() - gz_o) / scale_z)
+    rel_b = abs(float(gb.item()) - gb_o) / float(np.sum(es.t[es.subset] * scale_z))
+    print(f"\ntrend: loglik {rel_l:.2e} d/dz {rel_z:.2e} d/dbeta {rel_b:.2e}")
+    assert rel_l < 2e-6 * es.n / abs(ll_o)
+    assert rel_z < 1e-6
+    assert rel_b < 1e-6
+
+
+def test_hmc_step_with_trend_replays_oracle(gpu):
+    es = synth.small(400, seed=44, ties=3, all_free=False)
+    plan, idx = _setup(es)
+    m = es.subset.shape[0]
+    z0 = np.log(es.theta[es.subset]) + 0.05
+    mass = np.full(m, 6.0)
+    beta = -0.01
+
+    import torch
+
+    from paper_2103_03348_amd import _lib
+
+    for counter in range(2):
+        z = torch.as_tensor(z0.copy(), device="cuda:0")
+        th = torch.as_tensor(es.theta.copy(), device="cuda:0")
+        ms = torch.as_tensor(mass, device="cuda:0")
+        out = torch.zeros(8, dtype=torch.float64, device="cuda:0")
+        args = _lib.HmcArgs(z.data_ptr(), th.data_ptr(), ms.data_ptr(), 0.05, 8, 0.5, 91, counter, 0,
+                            out.data_ptr(), beta)
+        hy = _lib.Hyper.of(es.hyper)
+        _lib.check(_lib.lib().hmc_step(plan.handle, ctypes.byref(hy), ctypes.byref(args), _lib.stream_handle()),
+                   "hmc")
+        torch.cuda.synchronize()
+        r = ohmc.hmc_iteration(es.t, es.x, es.y, es.theta, es.subset, z0, mass, es.hyper, 0.0, 0.05, 8, 0.5, 91,
+                               counter, beta=beta)
+        o = out.cpu().numpy()
+        print(f"\ntrend counter {counter}: gpu dH {o[1]:.9f} | oracle dH {r['dH']:.9f}")
+        assert abs(o[1] - r["dH"]) < 1e-5
+        if abs(np.log(r["u"]) + r["dH"]) > 1e-4:
+            assert bool(o[0]) == r["accepted"]
+        if r["accepted"]:
+            np.testing.assert_allclose(z.cpu().numpy(), r["z_proposal"], atol=1e-6)

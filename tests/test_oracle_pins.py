@@ -391,3 +391,36 @@ def test_ess_of_ar1_chain():
             x[k] = rho * x[k - 1] + np.sqrt(1 - rho * rho) * e[k]
         expect = n * (1 - rho) / (1 + rho)
         assert ess.ess_1d(x) == pytest.approx(expect, rel=0.1)
+
+
+def test_fd_temporal_trend_gradient():
+    """Sec. 2.2's rates theta_k = exp(z_k + beta t_k): the chain-rule gradients
+    d/dz_k = theta_k (Eq. 4)_k and d/dbeta = sum_k t_k theta_k (Eq. 4)_k against
+    central finite differences of Eq. 1 in beta and in two z_k."""
+    from oracle import hmc as ohmc
+
+    es = _es(60, seed=41, ties=2)
+    idx = np.arange(0, es.n, 3)
+    z = 0.3 * np.random.default_rng(41).standard_normal(idx.shape[0])
+    beta = -0.04
+    ll, gz, gb = ohmc.trend_grad(es.t, es.x, es.y, es.theta, idx, z, beta, es.hyper, es.t0)
+
+    def ell_beta(b):
+        th = ohmc.rates(es.t, es.theta, idx, z, b)
+        return oracle.evaluate_es(es, theta=th, want=("ell_n",))["ell_n"]
+
+    fd = _fd_loglik(ell_beta, beta, 1e-6)
+    assert gb == pytest.approx(fd, rel=1e-7, abs=1e-9)
+    for k in (0, idx.shape[0] // 2):
+        def ell_z(v, k=k):
+            zz = z.copy()
+            zz[k] = v
+            return oracle.evaluate_es(es, theta=ohmc.rates(es.t, es.theta, idx, zz, beta), want=("ell_n",))["ell_n"]
+
+        assert gz[k] == pytest.approx(_fd_loglik(ell_z, z[k], 1e-6), rel=1e-7, abs=1e-9)
+    # beta = 0 reduces to theta_k = exp(z_k)
+    _, gz0, _ = ohmc.trend_grad(es.t, es.x, es.y, es.theta, idx, z, 0.0, es.hyper, es.t0)
+    th = es.theta.copy()
+    th[idx] = np.exp(z)
+    r = oracle.evaluate_es(es, theta=th, want=("grad_theta",))
+    np.testing.assert_allclose(gz0, np.exp(z) * r["grad_theta"][idx], rtol=1e-15)
