@@ -232,3 +232,38 @@ def test_hmc_step_with_trend_replays_oracle(gpu):
             assert bool(o[0]) == r["accepted"]
         if r["accepted"]:
             np.testing.assert_allclose(z.cpu().numpy(), r["z_proposal"], atol=1e-6)
+
+
+def test_gibbs_log_target_and_iterations(gpu):
+    """The Metropolis-within-Gibbs layer: its log target at a state is the
+    oracle's log-likelihood (rates exp(z + beta t) on the subset) plus the log
+    prior; a few Gibbs iterations (HMC on z + univariate MH on the
+    hyperparameters and beta) keep a finite target and move the parameters."""
+    import torch
+
+    from paper_2103_03348_amd.hawkes import Plan
+    from paper_2103_03348_amd.mcmc import HawkesGibbs
+    from paper_2103_03348_amd.sampler import HmcSampler
+
+    es = synth.small(800, seed=45, all_free=False)
+    dev = "cuda:0"
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
+    smp = HmcSampler(plan, torch.as_tensor(es.theta, device=dev), torch.as_tensor(es.subset, device=dev),
+                     es.hyper, sigma_z=0.5, L=5, seed=4, beta=-0.002)
+    gibbs = HawkesGibbs(smp, n_mh=6, seed=4)
+    z = smp.z.cpu().numpy()
+    th = ohmc.rates(es.t, es.theta, es.subset, z, -0.002)
+    ll_o = oracle.evaluate_es(es, theta=th, want=("loglik",))["loglik"]
+    lp_o = ll_o + gibbs.log_prior(gibbs.state)
+    print(f"\ngibbs: log target {gibbs.logp:.9f} oracle {lp_o:.9f}")
+    assert abs(gibbs.logp - lp_o) < 2e-6 * es.n
+    start = dict(gibbs.state)
+    for _ in range(25):
+        gibbs.iteration(0.1)
+        assert np.isfinite(gibbs.logp)
+    moved = [k for k in start if gibbs.state[k] != start[k]]
+    acc = gibbs.mh.acceptance()
+    print("gibbs acceptance", acc, "moved", moved)
+    assert len(moved) >= 3
+    assert plan.status() == 0
+    plan.close()
