@@ -218,9 +218,40 @@ typedef struct {
     double *d_out;         /* [8] device: accepted (1/0), H1 - H0, loglik and log pi at the
                               returned state, min(1, exp(-(H1-H0))), loglik at the proposal, H0, H1 */
     double beta;           /* temporal-trend coefficient (0: theta_k = exp(z_k))              */
+    int prior;             /* 0: z ~ N(0, sigma_z^2 I); 1: the phylogenetic prior of Eq. 2,
+                              z ~ N(0, sigma_z^2 V) for the tree set by hawkes_plan_set_tree
+                              (its tips must be the subset slots)                          */
 } hawkes_hmc_args;
 
 hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawkes_hmc_args *args, hipStream_t stream);
+
+/* ---- Phylogenetic Brownian prior (Sec. 2.2, Eq. 2) ----
+ *
+ * The log-rates z of the subset are the tips of a bifurcating tree on which a
+ * Brownian motion diffuses: root ~ N(0, tau0 sigma^2), child = parent +
+ * N(0, w sigma^2) for branch length w.  Then z ~ N(0, sigma^2 V) with
+ * V_nm = tau0 + length of the root-to-common-ancestor path of tips n and m.
+ * The library evaluates log p(z) and its gradient in O(M) by message passing
+ * over the tree, never forming V. */
+
+/* Set the tree (host arrays, copied).
+ *   n_nodes   2M - 1 (M tips); nodes 0..M-1 are the tips, node k = subset slot k
+ *   parent    [n_nodes] parent of each node, -1 for the root (exactly one)
+ *   length    [n_nodes] branch length to the parent (>= 0, finite; the root's is ignored)
+ *   tau0      root variance factor > 0
+ * Every internal node must have exactly two children and no two sibling
+ * subtrees may both have zero variance.  HAWKES_E_INVALID otherwise. */
+hawkes_status hawkes_plan_set_tree(hawkes_plan p, int64_t n_nodes, const int64_t *parent, const double *length,
+                                   double tau0);
+
+/* log p(z) of Eq. 2 for the plan's tree, with its gradient:
+ *   d_z [M] (slot order), sigma > 0;
+ *   d_logp [1] = -(M log(2 pi sigma^2) + log|V| + z^T V^{-1} z / sigma^2) / 2   (may be NULL)
+ *   d_grad [M] = -V^{-1} z / sigma^2                                           (may be NULL)
+ *   d_quad [1] = z^T V^{-1} z                                                   (required)
+ * HAWKES_E_UNSUPPORTED if no tree is set. */
+hawkes_status hawkes_tree_prior(hawkes_plan p, const double *d_z, double sigma, double *d_logp, double *d_grad,
+                                double *d_quad, hipStream_t stream);
 
 /* ---- Learned preconditioner (a small network predicting the diagonal mass) ----
  *

@@ -34,28 +34,32 @@ def trend_grad(es_t, es_x, es_y, theta_full, idx, z, beta, hyper, t0):
     return r["loglik"], gz, float(np.sum(np.asarray(es_t)[idx] * gz))
 
 
-def log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z, beta=0.0):
+def log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z, beta=0.0, prior_v=None):
+    """prior_v: None for z ~ N(0, sigma_z^2 I), else the dense covariance V of
+    the phylogenetic prior (Eq. 2), z ~ N(0, sigma_z^2 V).  Constants of the
+    prior are dropped (they cancel in the energy difference)."""
     th = rates(es_t, theta_full, idx, z, beta)
     r = evaluate(es_t, es_x, es_y, th, hyper, t0, want=("loglik", "grad_theta", "negH_theta"))
     ll = r["loglik"]
     g = r["grad_theta"][idx]
-    lp = ll - float(np.sum(z * z)) / (2.0 * sigma_z ** 2)
-    grad_z = th[idx] * g - z / sigma_z ** 2
+    vz = z if prior_v is None else np.linalg.solve(prior_v, z)
+    lp = ll - float(z @ vz) / (2.0 * sigma_z ** 2)
+    grad_z = th[idx] * g - vz / sigma_z ** 2
     return lp, grad_z, ll, r
 
 
 def hmc_iteration(es_t, es_x, es_y, theta_full, idx, z0, mass, hyper, t0, eps, L, sigma_z, seed, counter,
-                  beta=0.0):
+                  beta=0.0, prior_v=None):
     """Returns dict(z, accepted, dH, loglik, logpost, z_proposal, H0, H1)."""
     z0 = np.asarray(z0, dtype=np.float64)
     mass = np.asarray(mass, dtype=np.float64)
     p0 = np.sqrt(mass) * philox.normals(seed, counter, z0.shape[0])
-    lp0, g, ll0, _ = log_post(es_t, es_x, es_y, theta_full, idx, z0, hyper, t0, sigma_z, beta)
+    lp0, g, ll0, _ = log_post(es_t, es_x, es_y, theta_full, idx, z0, hyper, t0, sigma_z, beta, prior_v)
     z = z0.copy()
     p = p0 + 0.5 * eps * g
     for step in range(L):
         z = z + eps * p / mass
-        lp, g, ll, _ = log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z, beta)
+        lp, g, ll, _ = log_post(es_t, es_x, es_y, theta_full, idx, z, hyper, t0, sigma_z, beta, prior_v)
         p = p + (eps if step < L - 1 else 0.5 * eps) * g
     H0 = -lp0 + 0.5 * float(np.sum(p0 * p0 / mass))
     H1 = -lp + 0.5 * float(np.sum(p * p / mass))

@@ -43,7 +43,7 @@ class HmcArgs(ctypes.Structure):
     _fields_ = [("d_z", ctypes.c_void_p), ("d_theta", ctypes.c_void_p), ("d_mass", ctypes.c_void_p),
                 ("eps", ctypes.c_double), ("L", ctypes.c_int), ("sigma_z", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("counter", ctypes.c_uint64), ("refresh_static", ctypes.c_int),
-                ("d_out", ctypes.c_void_p), ("beta", ctypes.c_double)]
+                ("d_out", ctypes.c_void_p), ("beta", ctypes.c_double), ("prior", ctypes.c_int)]
 
 
 class Hyper(ctypes.Structure):
@@ -79,6 +79,8 @@ SIGNATURES = {
     "hawkes_subset_grad": (ctypes.c_int, [_vp, _HyP, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "hmc_step": (ctypes.c_int, [_vp, _HyP, ctypes.POINTER(HmcArgs), _vp]),
     "hawkes_subset_trend_grad": (ctypes.c_int, [_vp, _HyP, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
+    "hawkes_plan_set_tree": (ctypes.c_int, [_vp, _i64, _vp, _vp, ctypes.c_double]),
+    "hawkes_tree_prior": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp]),
     "hawkes_mlp_num_params": (_i64, []),
     "hawkes_mlp_workspace_floats": (_i64, [_i64]),
     "hawkes_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),

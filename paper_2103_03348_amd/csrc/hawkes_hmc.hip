@@ -58,6 +58,7 @@ struct hk_subset {
     // HMC state
     double *z0, *p, *gz; // [m] slot order
     double *off;         // [m] temporal-trend offsets beta t_k, slot order
+    double *vz;          // [m] V^{-1} z of the phylogenetic prior, slot order
     double *scal;        // [16] energies and flags
     // feature grids of the learned preconditioner
     int *grid;
@@ -542,13 +543,14 @@ __global__ void k_hmc_init(int64_t m, uint64_t seed, uint64_t counter, const dou
 }
 
 // grad_z log pi = theta_k g_k - z_k / sigma^2 in slot order
+// prior term: pv = z for the iid prior, V^{-1} z for the phylogenetic one
 __global__ void k_hmc_gradz(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
-                            const double *__restrict__ z, const double *__restrict__ off, double inv_s2,
-                            double *__restrict__ gz) {
+                            const double *__restrict__ z, const double *__restrict__ off,
+                            const double *__restrict__ pv, double inv_s2, double *__restrict__ gz) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= m) return;
     const int k = slot[r];
-    gz[k] = exp(zeff(z, off, k)) * gsub[r] - z[k] * inv_s2;
+    gz[k] = exp(zeff(z, off, k)) * gsub[r] - pv[k] * inv_s2;
 }
 
 // p += a_p * grad; then (if a_z != 0) z += a_z * p / M
@@ -616,7 +618,7 @@ void hk_subset_free(hawkes_plan p) {
     hk_subset *s = p->sub;
     if (!s) return;
     void *ptrs[] = {s->pos, s->slot, s->cidx, s->cnt, s->items, s->item0, s->nseg, s->lam_static, s->Lam_static,
-                    s->a, s->theta32, s->xs, s->xmom, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->off, s->scal,
+                    s->a, s->theta32, s->xs, s->xmom, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->off, s->vz, s->scal,
                     s->grid};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -712,6 +714,7 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     SC(dalloc(&s->p, m));
     SC(dalloc(&s->gz, m));
     SC(dalloc(&s->off, m));
+    SC(dalloc(&s->vz, m));
     SC(dalloc(&s->scal, 16));
 #undef SC
     s->static_valid = false;
@@ -841,6 +844,8 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
         !(a->eps > 0.0) || !(a->sigma_z > 0.0))
         return HAWKES_E_INVALID;
     if (!p->sub) return HAWKES_E_UNSUPPORTED;
+    if (a->prior != 0 && a->prior != 1) return HAWKES_E_INVALID;
+    if (a->prior == 1 && hk_tree_tips(p) != p->sub->m) return HAWKES_E_UNSUPPORTED;
     hk_subset *s = p->sub;
     p->last_stream = stream;
     PairConst kc;
@@ -849,6 +854,8 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
     hawkes_status st = ensure_static(p, hyper, a->d_theta, a->refresh_static != 0, kc, fc, stream);
     if (st != HAWKES_OK) return st;
     const int64_t m = s->m;
+    const bool tree = a->prior == 1;
+    const double *pv = tree ? s->vz : a->d_z;  // prior gradient direction (times 1/sigma^2)
     const double inv_s2 = 1.0 / (a->sigma_z * a->sigma_z);
     const unsigned gb = nblk(m, 256);
     // temporal trend: log theta_k = z_k + beta t_k
@@ -863,19 +870,24 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
     sub_eval(p, a->d_z, off, a->d_theta, false, kc, fc, stream);
     hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal);
-    hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, off, inv_s2, s->gz);
+    // phylogenetic prior: the quadratic form z^T V^{-1} z replaces sum z^2
+    if (tree && (st = hk_tree_launch(p, a->d_z, s->vz, s->scal + 2, stream)) != HAWKES_OK) return st;
+    hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, off, pv, inv_s2,
+                       s->gz);
     for (int l = 0; l < a->L; ++l) {
         // half kick at the start, full kicks between drifts
         hipLaunchKernelGGL(k_hmc_kick_drift, dim3(gb), dim3(256), 0, stream, m, l == 0 ? 0.5 * a->eps : a->eps,
                            s->gz, a->eps, a->d_mass, s->p, a->d_z);
         sub_eval(p, a->d_z, off, a->d_theta, false, kc, fc, stream);
-        hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, off, inv_s2,
-                           s->gz);
+        if (tree && (st = hk_tree_launch(p, a->d_z, s->vz, nullptr, stream)) != HAWKES_OK) return st;
+        hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, off, pv,
+                           inv_s2, s->gz);
     }
     hipLaunchKernelGGL(k_hmc_kick_drift, dim3(gb), dim3(256), 0, stream, m, 0.5 * a->eps, s->gz, 0.0, a->d_mass,
                        s->p, a->d_z);
     hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal + 4);
+    if (tree && (st = hk_tree_launch(p, a->d_z, nullptr, s->scal + 6, stream)) != HAWKES_OK) return st;
     hipLaunchKernelGGL(k_hmc_accept, dim3(1), dim3(256), 0, stream, s->scal, s->Lam_static, inv_s2, a->seed,
                        a->counter, m, s->z0, a->d_z, a->d_out, (int *)(s->scal + 8));
     hipLaunchKernelGGL(k_sub_theta_full, dim3(gb), dim3(256), 0, stream, a->d_z, off, s->cidx, m, a->d_theta);

@@ -94,9 +94,15 @@ struct hawkes_plan_s {
     hawkes_hyper eval_hyper;  // hyperparameters of that evaluation
     struct hk_profile *prof;  // HIP-event timing of the passes (NULL when off)
     struct hk_subset *sub;    // free-rate subset for the HMC path (NULL until set)
+    struct hk_tree *tree;     // phylogenetic prior on the subset log-rates (NULL until set)
 };
 
 hipError_t hk_sort_pairs(double *key, int *idx, int64_t n2, hipStream_t stream);
+// Phylogenetic prior (hawkes_tree.hip): d_vz [m] = V^{-1} z and d_quad [1] =
+// z^T V^{-1} z for z [m] in subset slot order (either output may be NULL).
+hawkes_status hk_tree_launch(hawkes_plan p, const double *d_z, double *d_vz, double *d_quad, hipStream_t stream);
+int64_t hk_tree_tips(hawkes_plan p);
+void hk_tree_free(hawkes_plan p);
 // Blocks of a pair pass (0 = row, 1 = column) resident at once on `device`:
 // compute units times the pass kernels' occupancy.
 int64_t hk_pass_slots(int device, int pass);

@@ -149,6 +149,7 @@ void free_plan(hawkes_plan p) {
     if (!p) return;
     hk_prof_free(p);
     hk_subset_free(p);
+    hk_tree_free(p);
     void *ptrs[] = {p->ts, p->xi, p->yi, p->perm, p->g, p->row_items, p->row_block0, p->row_item0, p->row_nseg,
                     p->colpart_off, p->col_items, p->col_block0, p->col_item0, p->col_nseg, p->theta_s, p->rowpart,
                     p->colpart, p->lam, p->w, p->wlo, p->a, p->colG, p->blockpart, p->status};

@@ -74,6 +74,7 @@ class HmcSampler:
         self.counter = 0
         self.jitter = float(jitter)
         self.beta = float(beta)  # temporal trend: theta_k = exp(z_k + beta t_k) (Sec. 2.2)
+        self.prior = 0           # 0: z ~ N(0, sigma_z^2 I); 1: phylogenetic prior (set_tree)
         self._jrng = np.random.default_rng(seed)
         t_sub = plan._t[self.idx]
         self.z = (torch.log(self.theta[self.idx]) - self.beta * t_sub).contiguous()
@@ -107,6 +108,20 @@ class HmcSampler:
                                                  _lib.stream_handle()), "hawkes_mass_update")
         self.mass_count += 1
 
+    def set_tree(self, parent, length, tau0):
+        """Use the phylogenetic Brownian prior of Eq. 2 on z (tips = subset slots):
+        parent [2m - 1] (-1 at the root), branch lengths [2m - 1], root factor tau0.
+        The prior's variance scale is sigma_z."""
+        import numpy as np
+        par = np.ascontiguousarray(parent, dtype=np.int64)
+        ln = np.ascontiguousarray(length, dtype=np.float64)
+        if par.shape[0] != 2 * self.m - 1 or ln.shape[0] != par.shape[0]:
+            raise ValueError("the tree must have 2m - 1 nodes for m subset slots")
+        _lib.check(_lib.lib().hawkes_plan_set_tree(self.plan.handle, par.shape[0], par.ctypes.data_as(ctypes.c_void_p),
+                                                   ln.ctypes.data_as(ctypes.c_void_p), float(tau0)),
+                   "hawkes_plan_set_tree")
+        self.prior = 1
+
     def trend_grad(self, beta=None):
         """hawkes_subset_trend_grad at the current z: (loglik, d/dz [m], d/dbeta) as
         device tensors; also writes theta on the subset for that beta."""
@@ -125,7 +140,7 @@ class HmcSampler:
         if self.jitter > 0:
             eps = eps * self._jrng.uniform(1.0 - self.jitter, 1.0 + self.jitter)
         args = _lib.HmcArgs(self.z.data_ptr(), self.theta.data_ptr(), self.mass.data_ptr(), float(eps), self.L,
-                            self.sigma_z, self.seed, self.counter, 0, self.out.data_ptr(), self.beta)
+                            self.sigma_z, self.seed, self.counter, 0, self.out.data_ptr(), self.beta, self.prior)
         _lib.check(_lib.lib().hmc_step(self.plan.handle, ctypes.byref(self.hyper), ctypes.byref(args),
                                        _lib.stream_handle()), "hmc_step")
         self.counter += 1

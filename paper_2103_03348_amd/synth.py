@@ -143,6 +143,33 @@ def config(k: int) -> EventSet:
     raise ValueError(f"no workload {k}")
 
 
+def coalescent_tree(m, seed=0, scale=1.0):
+    """A random bifurcating tree over m tips by Kingman's coalescent: with k
+    lineages left, the next merger comes after Exp(k (k - 1) / 2) time (times
+    `scale`) and joins two lineages drawn uniformly.  Returns (parent [2m - 1],
+    length [2m - 1]) with the tips first and the root last (parent -1)."""
+    rng = np.random.default_rng(seed)
+    n = 2 * m - 1
+    parent = np.full(n, -1, dtype=np.int64)
+    length = np.zeros(n)
+    height = np.zeros(n)
+    live = list(range(m))
+    t = 0.0
+    nxt = m
+    while len(live) > 1:
+        k = len(live)
+        t += scale * rng.exponential(2.0 / (k * (k - 1)))
+        i, j = rng.choice(k, size=2, replace=False)
+        a, b = live[i], live[j]
+        for c in (a, b):
+            parent[c] = nxt
+            length[c] = t - height[c]
+        height[nxt] = t
+        live = [v for q, v in enumerate(live) if q not in (i, j)] + [nxt]
+        nxt += 1
+    return parent, length
+
+
 def small(n, seed=7, t_end=None, k=3, all_free=True, ties=0, dup_xy=0):
     """Small ragged test sets.  ``ties`` events copy another event's time and
     ``dup_xy`` copy another event's location (edge cases of the indicators)."""

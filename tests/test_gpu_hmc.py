@@ -267,3 +267,80 @@ def test_gibbs_log_target_and_iterations(gpu):
     assert len(moved) >= 3
     assert plan.status() == 0
     plan.close()
+
+
+def test_tree_prior_matches_oracle(gpu):
+    """Eq. 2 by O(M) message passing on the device against the dense-V oracle
+    (Cholesky), on coalescent trees of 1, 2, 57 and 1,610 tips."""
+    import torch
+
+    from oracle import tree as otree
+    from paper_2103_03348_amd import _lib
+    from paper_2103_03348_amd.hawkes import Plan
+
+    es = synth.small(300, seed=46)
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
+    for m in (1, 2, 57, 1610):
+        par, ln = synth.coalescent_tree(m, seed=m, scale=float(m))
+        par, ln = np.ascontiguousarray(par), np.ascontiguousarray(ln)
+        _lib.check(_lib.lib().hawkes_plan_set_tree(plan.handle, 2 * m - 1, par.ctypes.data_as(ctypes.c_void_p),
+                                                   ln.ctypes.data_as(ctypes.c_void_p), 0.9), "set_tree")
+        z = np.random.default_rng(m).standard_normal(m)
+        dz = torch.as_tensor(z, device="cuda:0")
+        lp = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        g = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+        q = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        _lib.check(_lib.lib().hawkes_tree_prior(plan.handle, _lib.ptr(dz), 0.5, _lib.ptr(lp), _lib.ptr(g),
+                                                _lib.ptr(q), _lib.stream_handle()), "tree_prior")
+        torch.cuda.synchronize()
+        lpo, go, qo = otree.logpdf_and_grad(z, otree.covariance(par, ln, 0.9), 0.5)
+        rel_l = abs(float(lp.item()) - lpo) / abs(lpo)
+        rel_g = np.max(np.abs(g.cpu().numpy() - go)) / np.max(np.abs(go))
+        print(f"\ntree M={m}: logp {rel_l:.2e} grad {rel_g:.2e}")
+        assert rel_l < 1e-10 and rel_g < 1e-9
+    # a malformed tree is rejected
+    bad = np.ascontiguousarray(np.array([2, 2, 3, -1, 3], dtype=np.int64))
+    ln = np.ascontiguousarray(np.ones(5))
+    assert _lib.lib().hawkes_plan_set_tree(plan.handle, 5, bad.ctypes.data_as(ctypes.c_void_p),
+                                           ln.ctypes.data_as(ctypes.c_void_p), 0.9) == _lib.E_INVALID
+    plan.close()
+
+
+def test_hmc_step_with_tree_prior_replays_oracle(gpu):
+    """hmc_step with the phylogenetic prior (prior = 1) against the oracle's
+    iteration with the dense V, same Philox seed and counter."""
+    import torch
+
+    from oracle import tree as otree
+    from paper_2103_03348_amd import _lib
+
+    es = synth.small(400, seed=47, ties=2, all_free=False)
+    plan, idx = _setup(es)
+    m = es.subset.shape[0]
+    par, ln = synth.coalescent_tree(m, seed=47, scale=float(m))
+    par, ln = np.ascontiguousarray(par), np.ascontiguousarray(ln)
+    _lib.check(_lib.lib().hawkes_plan_set_tree(plan.handle, 2 * m - 1, par.ctypes.data_as(ctypes.c_void_p),
+                                               ln.ctypes.data_as(ctypes.c_void_p), 1.0), "set_tree")
+    V = otree.covariance(par, ln, 1.0)
+    z0 = np.log(es.theta[es.subset])
+    mass = np.full(m, 8.0)
+    for counter in range(2):
+        z = torch.as_tensor(z0.copy(), device="cuda:0")
+        th = torch.as_tensor(es.theta.copy(), device="cuda:0")
+        ms = torch.as_tensor(mass, device="cuda:0")
+        out = torch.zeros(8, dtype=torch.float64, device="cuda:0")
+        args = _lib.HmcArgs(z.data_ptr(), th.data_ptr(), ms.data_ptr(), 0.05, 6, 0.5, 93, counter, 0,
+                            out.data_ptr(), 0.0, 1)
+        hy = _lib.Hyper.of(es.hyper)
+        _lib.check(_lib.lib().hmc_step(plan.handle, ctypes.byref(hy), ctypes.byref(args), _lib.stream_handle()),
+                   "hmc")
+        torch.cuda.synchronize()
+        r = ohmc.hmc_iteration(es.t, es.x, es.y, es.theta, es.subset, z0, mass, es.hyper, 0.0, 0.05, 6, 0.5, 93,
+                               counter, prior_v=V)
+        o = out.cpu().numpy()
+        print(f"\ntree prior counter {counter}: gpu dH {o[1]:.9f} | oracle dH {r['dH']:.9f}")
+        assert abs(o[1] - r["dH"]) < 1e-5
+        if abs(np.log(r["u"]) + r["dH"]) > 1e-4:
+            assert bool(o[0]) == r["accepted"]
+        if r["accepted"]:
+            np.testing.assert_allclose(z.cpu().numpy(), r["z_proposal"], atol=1e-6)

@@ -424,3 +424,35 @@ def test_fd_temporal_trend_gradient():
     th[idx] = np.exp(z)
     r = oracle.evaluate_es(es, theta=th, want=("grad_theta",))
     np.testing.assert_allclose(gz0, np.exp(z) * r["grad_theta"][idx], rtol=1e-15)
+
+
+def test_tree_prior_closed_form_and_scipy():
+    """Eq. 2's covariance from a tree: a two-tip tree by hand, and the oracle's
+    log density and gradient against scipy's multivariate normal and central
+    differences on a coalescent tree."""
+    from scipy.stats import multivariate_normal
+
+    from oracle import tree as otree
+
+    # two tips joined at the root: V = [[tau0 + w0, tau0], [tau0, tau0 + w1]]
+    V2 = otree.covariance([2, 2, -1], [0.3, 0.7, 0.0], 1.5)
+    np.testing.assert_allclose(V2, [[1.8, 1.5], [1.5, 2.2]], rtol=1e-15)
+    parent, length = synth.coalescent_tree(40, seed=3)
+    V = otree.covariance(parent, length, 0.8)
+    assert np.allclose(V, V.T) and np.all(np.linalg.eigvalsh(V) > 0)
+    z = np.random.default_rng(3).standard_normal(40)
+    sigma = 0.6
+    logp, grad, quad = otree.logpdf_and_grad(z, V, sigma)
+    assert logp == pytest.approx(multivariate_normal(np.zeros(40), sigma ** 2 * V).logpdf(z), rel=1e-10)
+    for k in (0, 17, 39):
+        e = np.zeros(40)
+        e[k] = 1e-6
+        fd = (otree.logpdf_and_grad(z + e, V, sigma)[0] - otree.logpdf_and_grad(z - e, V, sigma)[0]) / 2e-6
+        assert grad[k] == pytest.approx(fd, rel=1e-6)
+    # tip variances: tau0 + root-to-tip path length
+    k = 5
+    d, v = 0.0, k
+    while parent[v] >= 0:
+        d += length[v]
+        v = parent[v]
+    assert V[k, k] == pytest.approx(0.8 + d, rel=1e-14)
