@@ -219,6 +219,48 @@ def bench_hmc_large(es, iters=10, L=20, learned_every=50, exact_every=500, seed=
             "subset_pairs_per_leapfrog": float(n) * m, "last_accept": acc}
 
 
+def bench_larger(configs=(2, 4), steps=(20, 8)):
+    """The same full evaluation on the larger workloads (N = 100,000 and
+    250,000): time per evaluation, pair-evaluations per second, and the row
+    pass's algorithmic FP32 rate against the non-packed peak."""
+    import numpy as np
+    import torch
+
+    from paper_2103_03348_amd import _lib, synth
+    from paper_2103_03348_amd.hawkes import Plan
+
+    res = {}
+    lib = _lib.lib()
+    for cfg, k in zip(configs, steps):
+        es = synth.config(cfg)
+        plan = Plan.from_numpy(es.t, es.x, es.y, es.t0, device="cuda:0")
+        theta = torch.as_tensor(es.theta, device="cuda:0")
+        out = {}
+        for _ in range(2):
+            plan.eval(theta, es.hyper, loglik=True, grad_theta=True, grad_hyper=True, negH_theta=True,
+                      negH_hyper=True, out=out)
+        torch.cuda.synchronize()
+        _lib.check(lib.hawkes_profile_enable(plan.handle, 1), "profile_enable")
+        t0 = time.perf_counter()
+        for _ in range(k):
+            plan.eval(theta, es.hyper, loglik=True, grad_theta=True, grad_hyper=True, negH_theta=True,
+                      negH_hyper=True, out=out)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / k
+        prof = (ctypes.c_double * 6)()
+        _lib.check(lib.hawkes_profile_read(plan.handle, prof), "profile_read")
+        row_ms = prof[0] / max(prof[1], 1)
+        pairs = es.n * (es.n - 1) / 2
+        if plan.status() != 0 or not np.isfinite(float(out["loglik"].item())):
+            raise RuntimeError(f"evaluation failed on {CONFIGS[cfg]}")
+        achieved = FLOPS_ROW_PER_PAIR * pairs / (row_ms * 1e-3) / 1e12
+        res[CONFIGS[cfg]] = {"n_events": es.n, "steps": k, "ms_per_step": 1e3 * el,
+                             "pair_evals_per_s": pairs / el, "row_ms": row_ms, "col_ms": prof[2] / max(prof[3], 1),
+                             "row_tflops": achieved, "row_frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS}
+        plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +273,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (HBM counter calibration)")
     ap.add_argument("--hmc-iters", type=int, default=2000)
+    ap.add_argument("--no-larger", action="store_true", help="skip the N=100,000 and 250,000 evaluations")
     ap.add_argument("--no-hmc-large", action="store_true",
                     help="skip the HMC iteration timing on the N=250,000 workload")
     args = ap.parse_args()
@@ -350,6 +393,8 @@ def main():
                                   "note": "skips pair blocks whose terms are all below 2^-160; not counted as "
                                           "pair-evaluations"},
     }
+    if not args.no_larger and args.config == 1:
+        rec["larger_workloads"] = bench_larger()
     if not args.no_hmc and args.config == 1:
         rec["hmc"] = bench_hmc(synth.config(3), n_iter=args.hmc_iters)
     if not args.no_hmc and not args.no_hmc_large and args.config == 1:
