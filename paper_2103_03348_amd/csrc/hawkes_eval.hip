@@ -2,7 +2,8 @@
 // Hessian diagonal) and the hyperparameter derivatives on gfx950.
 //
 // Kernels, in launch order:
-//   k_gather   theta to sorted order (FP32), validity check
+//   k_tfac     theta to sorted order (FP32), validity check, staged rates of
+//              the split excitation time factor and the per-chunk split flags
 //   k_row      row pass over causal tile pairs: for each row i the background
 //              moments over j < i and the excitation moments over t_j < t_i;
 //              the background is symmetric, so each pair also adds its
@@ -94,17 +95,33 @@ __device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float v) {
 }
 
 // ------------------------------------------------------------------------------------
-__global__ void k_gather(const double *__restrict__ theta, const int *__restrict__ perm, int64_t n,
-                         int64_t npad, float *__restrict__ theta_s, int *__restrict__ status) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= npad) return;
-    float v = 0.0f;
-    if (i < n) {
-        double th = theta[perm[i]];
-        if (!(th >= 0.0) || !isfinite(th)) atomicOr(status, HK_ST_BADTHETA);
-        v = (float)th;
+// Per evaluation, before the row pass: the sorted FP32 rates (gathered from the
+// caller's order when FROM_CALLER, else already in theta_s), and for the split
+// excitation time factor the staged rate of each event,
+// theta_v_j = theta_j exp(omega (t_j - T_c)) with T_c its chunk's first time,
+// plus a flag per chunk that spans more than HK_FACT_SPAN / omega (those chunks
+// use the direct exponent and stage theta_j itself).  One wavefront per chunk.
+template <bool FROM_CALLER>
+__global__ __launch_bounds__(256) void k_tfac(const double *__restrict__ theta, const int *__restrict__ perm,
+                                              const double *__restrict__ ts, int64_t n, double omega,
+                                              float *__restrict__ theta_s, float *__restrict__ theta_v,
+                                              int *__restrict__ chunk_wide, int *__restrict__ status) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // grid covers npad exactly
+    const int lane = threadIdx.x & (HK_WAVE - 1);
+    double th = 0.0;
+    if (FROM_CALLER) {
+        if (i < n) {
+            th = theta[perm[i]];
+            if (!(th >= 0.0) || !isfinite(th)) atomicOr(status, HK_ST_BADTHETA);
+        }
+        theta_s[i] = (float)th;
+    } else {
+        th = (double)theta_s[i];
     }
-    theta_s[i] = v;
+    const double dti = ts[i] - ts[i - lane];
+    const bool wide = __any(i < n && omega * dti > HK_FACT_SPAN);
+    theta_v[i] = (!wide && th > 0.0) ? (float)(th * exp(omega * dti)) : (float)th;
+    if (lane == 0) chunk_wide[i / HK_WAVE] = wide;
 }
 
 // ------------------------------------------------------------------------------------
@@ -117,7 +134,6 @@ __global__ void k_gather(const double *__restrict__ theta, const int *__restrict
 // both factors far inside the FP32 range; a chunk that spans more time (sparse
 // data) takes the direct exponent instead, with the rounding of the FP32 rate
 // constant corrected to first order inside the loop.
-#define HK_FACT_SPAN 40.0
 
 // One sweep of a 64-column chunk by one wavefront: 64 steps, each lane pairing
 // its row with column (lane + s) mod 64 of the chunk.
@@ -208,7 +224,8 @@ __device__ __forceinline__ void row_sweep_masked(const float4 *__restrict__ rec,
 
 template <int MODE>
 __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, const int *__restrict__ xi,
-                                                  const int *__restrict__ yi, const float *__restrict__ theta_s,
+                                                  const int *__restrict__ yi, const float *__restrict__ theta_v,
+                                                  const int *__restrict__ chunk_wide,
                                                   const int *__restrict__ g, const hk_item *__restrict__ items,
                                                   const int *__restrict__ block0,
                                                   const int64_t *__restrict__ colpart_off,
@@ -218,7 +235,6 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
     __shared__ double rtd[2 * HK_WAVE];
     __shared__ float colbuf[HK_WAVES][HK_NCOL][HK_WAVE];
     __shared__ double colbuf0[HK_WAVES][HK_WAVE];
-    __shared__ int fact_sh;
     constexpr int NC = MODE == HK_MODE_LOGLIK ? 1 : (MODE == HK_MODE_GRAD ? 3 : 5);
     const int tid = threadIdx.x, lane = tid & (HK_WAVE - 1), wv = tid / HK_WAVE;
     const int q_end = block0[blockIdx.x + 1];
@@ -236,9 +252,9 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         const int64_t stride = (int64_t)(I + 1) * HK_TILE;
         float *__restrict__ cp = colpart + colpart_off[I];
 
-        float hi[HK_NROW], lo[HK_NROW];
+        double mom[HK_NROW];  // derivative moments, FP64 across chunks (slots 0 and 5 unused)
 #pragma unroll
-        for (int a = 0; a < HK_NROW; ++a) hi[a] = lo[a] = 0.0f;
+        for (int a = 0; a < HK_NROW; ++a) mom[a] = 0.0;
         double B0d = 0.0, X0d = 0.0;
 
         const double tile_tmin = ts[row0];
@@ -257,24 +273,19 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
             const double Tc = ts[(int64_t)c * HK_WAVE];
             const float ti = (float)(tsi - Tc);
             if (tid < HK_WAVE) {
-                // the staging threads are wavefront 0: one vote decides the split
                 const int64_t j = (int64_t)c * HK_WAVE + tid;
-                const double dtj = ts[j] - Tc;
-                const float th = theta_s[j];
-                const bool wide = th > 0.0f && kc.omega * dtj > HK_FACT_SPAN;
-                const bool fact = !__any(wide);
+                const double tj = ts[j];
                 float4 r;
-                r.x = (float)dtj;
+                r.x = (float)(tj - Tc);
                 r.y = __int_as_float(xi[j]);
                 r.z = __int_as_float(yi[j]);
-                r.w = (fact && th > 0.0f) ? (float)((double)th * exp(kc.omega * dtj)) : th;
+                r.w = theta_v[j];  // theta_j, times exp(omega (t_j - T_c)) when the chunk is split
                 rec[tid] = r;
                 rec[tid + HK_WAVE] = r;
-                rtd[tid] = rtd[tid + HK_WAVE] = ts[j];
-                if (tid == 0) fact_sh = fact;
+                rtd[tid] = rtd[tid + HK_WAVE] = tj;
             }
             __syncthreads();
-            const bool fact = fact_sh != 0;
+            const bool fact = chunk_wide[c] == 0;
             float blk[HK_NROW], C[HK_NCOL];
             double C0d = 0.0, X0c = 0.0;
 #pragma unroll
@@ -319,7 +330,7 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
             for (int a = 0; a < HK_NROW; ++a) {
                 const bool used = (MODE >= HK_MODE_GRAD && (a == 1 || a == 2 || a == 6 || a == 7)) ||
                                   (MODE >= HK_MODE_HESS && a != 0 && a != 5);
-                if (used) two_sum_acc(hi[a], lo[a], blk[a]);
+                if (used) mom[a] += (double)blk[a];
             }
         }
         float *__restrict__ rp = rowpart + (int64_t)q * HK_NROW * HK_TILE;
@@ -329,7 +340,7 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         for (int a = 0; a < HK_NROW; ++a) {
             const bool used = (MODE >= HK_MODE_GRAD && (a == 1 || a == 2 || a == 6 || a == 7)) ||
                               (MODE >= HK_MODE_HESS && a != 0 && a != 5);
-            if (used) rp[a * HK_TILE + tid] = (float)((double)hi[a] + (double)lo[a]);
+            if (used) rp[a * HK_TILE + tid] = (float)mom[a];
         }
     }
 }
@@ -383,11 +394,13 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
                                              const int *__restrict__ row_item0, const int *__restrict__ row_nseg,
                                              const float *__restrict__ rowpart, const float *__restrict__ colpart,
                                              const int64_t *__restrict__ colpart_off, const FinConst fc,
+                                             const int *__restrict__ chunk_wide,
                                              double *__restrict__ lam, float *__restrict__ w, float *__restrict__ wlo,
+                                             float *__restrict__ wv, float *__restrict__ wvlo,
                                              double *__restrict__ a_out,
                                              double *__restrict__ blockpart, int *__restrict__ status) {
     __shared__ double part[HK_WAVES][HK_NROW][HK_WAVE];
-    const int lane = threadIdx.x & (HK_WAVE - 1), wv = threadIdx.x / HK_WAVE;
+    const int lane = threadIdx.x & (HK_WAVE - 1), wq = threadIdx.x / HK_WAVE;
     const int64_t i = (int64_t)blockIdx.x * HK_WAVE + lane;
     const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
     {
@@ -395,7 +408,7 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
 #pragma unroll
         for (int k = 0; k < HK_NROW; ++k) acc[k] = 0.0;
         const int it0 = row_item0[I], ns = row_nseg[I];
-        for (int sg = wv; sg < ns; sg += HK_WAVES) {
+        for (int sg = wq; sg < ns; sg += HK_WAVES) {
             const float *rp = rowpart + (int64_t)(it0 + sg) * HK_NROW * HK_TILE + r;
             acc[0] += rp[0];
             acc[5] += rp[5 * HK_TILE];
@@ -413,7 +426,7 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
             }
         }
         // background from later events: the column partials of row tiles J >= I
-        for (int J = I + wv; J < ntiles; J += HK_WAVES) {
+        for (int J = I + wq; J < ntiles; J += HK_WAVES) {
             const int64_t stride = (int64_t)(J + 1) * HK_TILE;
             const float *cp = colpart + colpart_off[J] + i;
             acc[0] += (double)cp[0];
@@ -427,10 +440,10 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
             }
         }
 #pragma unroll
-        for (int k = 0; k < HK_NROW; ++k) part[wv][k][lane] = acc[k];
+        for (int k = 0; k < HK_NROW; ++k) part[wq][k][lane] = acc[k];
     }
     __syncthreads();
-    if (wv != 0) return;
+    if (wq != 0) return;
 
     double s[HK_NSUM];
 #pragma unroll
@@ -459,6 +472,11 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
             const float whi = (float)wd;
             w[i] = whi;
             wlo[i] = (float)(wd - (double)whi);
+            // the column pass stages w_i exp(-omega (t_i - T_c)) on split chunks
+            const double v = chunk_wide[blockIdx.x] ? wd : wd * exp(-fc.omega * (ts[i] - ts[i - lane]));
+            const float vhi = (float)v;
+            wv[i] = vhi;
+            wvlo[i] = (float)(v - (double)vhi);
         }
         s[0] = log(lamv);
         const double inv = 1.0 / lamv;
@@ -513,6 +531,8 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
         lam[i] = 1.0;
         w[i] = 0.0f;
         wlo[i] = 0.0f;
+        wv[i] = 0.0f;
+        wvlo[i] = 0.0f;
         a_out[i] = 0.0;
     }
 #pragma unroll
@@ -636,16 +656,16 @@ __device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const
 
 template <bool WITH_H>
 __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, const int *__restrict__ xi,
-                                                  const int *__restrict__ yi, const float *__restrict__ w,
-                                                  const float *__restrict__ wlo, const int *__restrict__ g,
+                                                  const int *__restrict__ yi, const float *__restrict__ wv,
+                                                  const float *__restrict__ wvlo, const int *__restrict__ chunk_wide,
+                                                  const int *__restrict__ g,
                                                   const hk_item *__restrict__ items, const int *__restrict__ block0,
                                                   double *__restrict__ colG, const PairConst kc) {
     __shared__ double2 rxy[HK_WAVE];
     __shared__ float2 rv[HK_WAVE];
     __shared__ double rtd[HK_WAVE];
     __shared__ int rg[HK_WAVE];
-    __shared__ int fact_sh;
-    const int tid = threadIdx.x, wv = tid / HK_WAVE;
+    const int tid = threadIdx.x, wvi = tid / HK_WAVE;
     const int q_end = block0[blockIdx.x + 1];
 
     for (int q = block0[blockIdx.x]; q < q_end; ++q) {
@@ -655,7 +675,7 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
         const int jcol = (int)(col0 + tid);
         const double tsj = ts[jcol];
         const double xj = (double)xi[jcol] * kc.sx, yj = (double)yi[jcol] * kc.sx;
-        const int wave_first = (int)(col0 + wv * HK_WAVE);
+        const int wave_first = (int)(col0 + wvi * HK_WAVE);
         const double wave_tmax = ts[(int64_t)wave_first + HK_WAVE - 1];  // the wave's latest column
 
         const double tile_tmax = ts[col0 + HK_TILE - 1];
@@ -666,27 +686,18 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
             // tile's latest column end the sweep (times are sorted)
             if (Tc - tile_tmax > kc.dt_cut_ex) break;
             if (tid < HK_WAVE) {
-                // the staging threads are wavefront 0: one vote decides the split
                 const int64_t i = (int64_t)c * HK_WAVE + tid;
-                const double ti = ts[i];
-                const double dti = ti - Tc;
-                const double wd = (double)w[i] + (double)wlo[i];
-                const bool wide = wd > 0.0 && kc.omega * dti > HK_FACT_SPAN;
-                const bool fact = !__any(wide);
-                const double v = fact ? wd * exp(-kc.omega * dti) : wd;
-                const float vhi = (float)v;
                 rxy[tid] = make_double2((double)xi[i] * kc.sx, (double)yi[i] * kc.sx);
-                rv[tid] = make_float2(vhi, (float)(v - (double)vhi));
-                rtd[tid] = ti;
+                rv[tid] = make_float2(wv[i], wvlo[i]);  // w_i exp(-omega (t_i - T_c)) on split chunks
+                rtd[tid] = ts[i];
                 rg[tid] = g[i];
-                if (tid == 0) fact_sh = fact;
             }
             __syncthreads();
             const int gmax = rg[HK_WAVE - 1], gmin = rg[0];
             // optional underflow cutoff: rows that all start more than dt_cut_ex
             // after the wave's latest column give excitation terms below 2^-160
             if (gmax > wave_first && !(Tc - wave_tmax > kc.dt_cut_ex)) {
-                const bool fact = fact_sh != 0;
+                const bool fact = chunk_wide[c] == 0;
                 float G = 0.0f, H = 0.0f;
                 const bool masked = gmin <= wave_first + HK_WAVE - 1;
                 if (fact) {
@@ -808,11 +819,11 @@ static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, d
                        double *d_negH_theta, hipStream_t stream) {
     hk_prof_mark(p, HK_PROF_COL, true, stream);
     if (d_negH_theta)
-        hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->w,
-                           p->wlo, p->g, p->col_items, p->col_block0, p->colG, kc);
+        hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->wv,
+                           p->wvlo, p->chunk_wide, p->g, p->col_items, p->col_block0, p->colG, kc);
     else
         hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                           p->w, p->wlo, p->g, p->col_items, p->col_block0, p->colG, kc);
+                           p->wv, p->wvlo, p->chunk_wide, p->g, p->col_items, p->col_block0, p->colG, kc);
     hk_prof_mark(p, HK_PROF_COL, false, stream);
     hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(256), 0, stream, p->perm, p->n, p->col_item0, p->col_nseg,
                        p->colG, p->a, fc, d_grad_theta, d_negH_theta);
@@ -857,17 +868,17 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
     const int64_t npad = p->npad;
 
     hk_prof_mark(p, HK_PROF_EVAL, true, stream);
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)(npad / 256)), dim3(256), 0, stream, d_theta, p->perm, p->n, npad,
-                       p->theta_s, p->status);
+    hipLaunchKernelGGL(k_tfac<true>, dim3((unsigned)(npad / 256)), dim3(256), 0, stream, d_theta, p->perm, p->ts,
+                       p->n, kc.omega, p->theta_s, p->theta_v, p->chunk_wide, p->status);
     hk_prof_mark(p, HK_PROF_ROW, true, stream);
 #define HK_ROW(M)                                                                                              \
     hipLaunchKernelGGL(k_row<M>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,          \
-                       p->theta_s, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart, p->colpart,   \
-                       kc)
+                       p->theta_v, p->chunk_wide, p->g, p->row_items, p->row_block0, p->colpart_off,             \
+                       p->rowpart, p->colpart, kc)
 #define HK_FIN(M)                                                                                              \
     hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->n,          \
                        p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart_off, fc,             \
-                       p->lam, p->w, p->wlo, p->a, p->blockpart, p->status)
+                       p->chunk_wide, p->lam, p->w, p->wlo, p->wv, p->wvlo, p->a, p->blockpart, p->status)
     if (mode == HK_MODE_GRAD) HK_ROW(HK_MODE_GRAD);
     else HK_ROW(HK_MODE_HESS);
     hk_prof_mark(p, HK_PROF_ROW, false, stream);
@@ -887,8 +898,11 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 }
 
 void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream) {
+    hipLaunchKernelGGL(k_tfac<false>, dim3((unsigned)(p->npad / 256)), dim3(256), 0, stream, (const double *)nullptr,
+                       p->perm, p->ts, p->n, kc.omega, p->theta_s, p->theta_v, p->chunk_wide, p->status);
     hipLaunchKernelGGL(k_row<HK_MODE_GRAD>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                       p->theta_s, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart, p->colpart, kc);
+                       p->theta_v, p->chunk_wide, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart,
+                       p->colpart, kc);
 }
 
 // Blocks per compute unit in the pair-pass schedules.  Eight blocks of four

@@ -20,6 +20,12 @@
 // Per-event sums reduced by the finalize kernels (see hawkes_eval.hip).
 #define HK_NSUM 20
 
+// The excitation's time factor is split per 64-event chunk (exp(-omega (t_i -
+// t_j)) = exp(-omega (t_i - T_c)) exp(omega (t_j - T_c))) when omega times the
+// chunk's time span is at most this: both factors then stay far inside the
+// FP32 range.
+#define HK_FACT_SPAN 40.0
+
 // Time offset given to padding events: their pair terms underflow to exactly
 // zero while every square stays finite in FP32.
 #define HK_PAD_DT 1.0e15
@@ -77,6 +83,9 @@ struct hawkes_plan_s {
 
     // per-evaluation scratch (device)
     float *theta_s;           // [npad] rates in sorted order (FP32), 0 on padding
+    float *theta_v;           // [npad] staged rates of the row pass (split time factor applied)
+    int *chunk_wide;          // [nchunks] 1 where the chunk takes the direct exponent
+    float *wv, *wvlo;         // [npad] staged column-pass weights w_i exp(-omega (t_i - T_c)) (hi, lo)
     float *rowpart;           // [n_row_items][HK_NROW][HK_TILE] row partial sums of each piece
     float *colpart;           // triangular [tile][HK_NCOL][(tile+1)*HK_TILE]: background column partials
     double *lam;              // [npad] lambda_i, sorted
