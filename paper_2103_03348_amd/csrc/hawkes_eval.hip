@@ -143,9 +143,16 @@ __global__ __launch_bounds__(256) void k_tfac(const double *__restrict__ theta, 
 // positive terms rounds away every term below half an ulp of the running sum,
 // which biases lambda low (by ~2e-8 relative on clustered data).  The moments
 // used only by derivatives stay in FP32 blocks.
+//
+// The spatial exponent of the background is formed in FP64 from coordinates
+// pre-scaled by sqrt(-kbx) (two subtractions, a product and an FMA, rounded
+// once), which costs fewer instructions than integer differences converted to
+// FP32 and scaled, and carries no rounded FP32 scale; the excitation's exponent
+// is that value times the FP32 ratio kex / kbx.
 template <int MODE, bool MASK_BG, bool MASK_EX, bool FACT>
-__device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, const double *__restrict__ rtd,
-                                          double tsi, int lane, float ti, int xr, int yr,
+__device__ __forceinline__ void row_sweep(const float2 *__restrict__ rec, const double2 *__restrict__ rxy,
+                                          const double *__restrict__ rtd,
+                                          double tsi, int lane, float ti, double xr, double yr,
                                           int irow, int gr, int cbase, const PairConst kc,
                                           float (&blk)[HK_NROW], float (&C)[HK_NCOL], double &B0d, double &X0c,
                                           double &C0d) {
@@ -154,17 +161,16 @@ __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, const 
 #pragma clang fp contract(off)
 #pragma unroll 16
     for (int s = 0; s < HK_WAVE; ++s) {
-        const float4 r = rec[lane + s];
+        const float2 r = rec[lane + s];
+        const double2 pj = rxy[lane + s];
         // a chunk that spans a long time takes dt from the FP64 times: relative to
         // the chunk start, both operands could then be large
         const float dt = FACT ? ti - r.x : (float)(tsi - rtd[lane + s]);
-        const float dx = (float)(xr - __float_as_int(r.y));
-        const float dy = (float)(yr - __float_as_int(r.z));
-        const float r2 = fmaf(dx, dx, dy * dy);
+        const double dx = xr - pj.x, dy = yr - pj.y;
+        const float ar = (float)(-fma(dx, dx, dy * dy));
         const float dt2 = dt * dt;
-        const float ar = r2 * kc.kbx;
         float b = fexp2(fmaf(dt2, kc.kbt, ar));
-        const float ae = r2 * kc.kex;
+        const float ae = ar * kc.rex;
         float E;
         if (FACT) {
             E = fexp2(ae);
@@ -177,7 +183,7 @@ __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, const 
             if (MASK_BG && !(j < irow)) b = 0.0f;
             if (!(j < gr)) E = 0.0f;
         }
-        const float te = E * r.w;
+        const float te = E * r.y;
         B0d += (double)b;
         C0d = rot_next_d(C0d) + (double)b;
         if (MODE >= HK_MODE_GRAD) {
@@ -208,18 +214,19 @@ __device__ __forceinline__ void row_sweep(const float4 *__restrict__ rec, const 
 }
 
 template <int MODE, bool FACT>
-__device__ __forceinline__ void row_sweep_masked(const float4 *__restrict__ rec, const double *__restrict__ rtd,
-                                                 double tsi, int lane, float ti, int xr, int yr,
+__device__ __forceinline__ void row_sweep_masked(const float2 *__restrict__ rec, const double2 *__restrict__ rxy,
+                                                 const double *__restrict__ rtd,
+                                                 double tsi, int lane, float ti, double xr, double yr,
                                                  int irow, int gr, int c, int wave_chunk, int wave_gmin,
                                                  const PairConst kc, float (&blk)[HK_NROW],
                                                  float (&C)[HK_NCOL], double &B0d, double &X0c, double &C0d) {
     const int cbase = c * HK_WAVE;
     if (c == wave_chunk)
-        row_sweep<MODE, true, true, FACT>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+        row_sweep<MODE, true, true, FACT>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
     else if (cbase + HK_WAVE - 1 >= wave_gmin)
-        row_sweep<MODE, false, true, FACT>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+        row_sweep<MODE, false, true, FACT>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
     else
-        row_sweep<MODE, false, false, FACT>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+        row_sweep<MODE, false, false, FACT>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
 }
 
 template <int MODE>
@@ -231,7 +238,8 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
                                                   const int64_t *__restrict__ colpart_off,
                                                   float *__restrict__ rowpart, float *__restrict__ colpart,
                                                   const PairConst kc) {
-    __shared__ float4 rec[2 * HK_WAVE];
+    __shared__ float2 rec[2 * HK_WAVE];
+    __shared__ double2 rxy[2 * HK_WAVE];
     __shared__ double rtd[2 * HK_WAVE];
     __shared__ float colbuf[HK_WAVES][HK_NCOL][HK_WAVE];
     __shared__ double colbuf0[HK_WAVES][HK_WAVE];
@@ -245,7 +253,8 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         const int64_t row0 = (int64_t)I * HK_TILE;
         const int irow = (int)(row0 + tid);
         const double tsi = ts[irow];
-        const int xr = xi[irow], yr = yi[irow], gr = g[irow];
+        const double xr = (double)xi[irow] * kc.sbx, yr = (double)yi[irow] * kc.sbx;
+        const int gr = g[irow];
         const int wave_chunk = I * HK_CHUNKS_PER_TILE + wv;
         const int wave_gmin = g[(int64_t)wave_chunk * HK_WAVE];  // g is non-decreasing
         const double wave_tmin = ts[(int64_t)wave_chunk * HK_WAVE];  // the wave's earliest row
@@ -275,13 +284,14 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
             if (tid < HK_WAVE) {
                 const int64_t j = (int64_t)c * HK_WAVE + tid;
                 const double tj = ts[j];
-                float4 r;
+                float2 r;
                 r.x = (float)(tj - Tc);
-                r.y = __int_as_float(xi[j]);
-                r.z = __int_as_float(yi[j]);
-                r.w = theta_v[j];  // theta_j, times exp(omega (t_j - T_c)) when the chunk is split
+                r.y = theta_v[j];  // theta_j, times exp(omega (t_j - T_c)) when the chunk is split
                 rec[tid] = r;
                 rec[tid + HK_WAVE] = r;
+                const double2 pj = make_double2((double)xi[j] * kc.sbx, (double)yi[j] * kc.sbx);
+                rxy[tid] = pj;
+                rxy[tid + HK_WAVE] = pj;
                 rtd[tid] = rtd[tid + HK_WAVE] = tj;
             }
             __syncthreads();
@@ -297,10 +307,10 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
             const bool live = c <= wave_chunk && !(wave_tmin - ts[(int64_t)c * HK_WAVE + HK_WAVE - 1] > kc.dt_cut);
             if (live) {
                 if (fact)
-                    row_sweep_masked<MODE, true>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
+                    row_sweep_masked<MODE, true>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
                                                  blk, C, B0d, X0c, C0d);
                 else
-                    row_sweep_masked<MODE, false>(rec, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
+                    row_sweep_masked<MODE, false>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
                                                   blk, C, B0d, X0c, C0d);
                 // the row's time factor (t_i >= T_c here, so it is at most 1)
                 const double ui = fact ? exp(-kc.omega * (tsi - Tc)) : 1.0;
@@ -458,7 +468,7 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
         double b0 = acc[0], x0 = acc[5];
         if (MODE >= HK_MODE_GRAD) {
             const double ln2 = 0.6931471805599453;
-            b0 -= ln2 * (fc.rho_bx * acc[1] + fc.dkbt * acc[2]);
+            b0 -= ln2 * fc.dkbt * acc[2];
             x0 -= ln2 * fc.rho_ex * acc[7];
         }
         const double B0 = b0 * fc.corr, X0 = x0 * fc.corr;
@@ -633,13 +643,14 @@ __device__ __forceinline__ float col_term(const double2 *__restrict__ rxy, const
 #ifndef HK_COL_UNROLL
 #define HK_COL_UNROLL 2
 #endif
+constexpr int kColUnroll = HK_COL_UNROLL;
 template <bool WITH_H, bool MASKED, bool FACT>
 __device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const float2 *__restrict__ rv,
                                           const double *__restrict__ rtd, const int *__restrict__ rg, int jcol,
                                           double tsj, double xj, double yj, const PairConst kc, float &G, float &H) {
 #pragma clang fp contract(off)
     float G1 = 0.0f, H1 = 0.0f;
-#pragma unroll HK_COL_UNROLL
+#pragma unroll kColUnroll
     for (int s = 0; s < HK_WAVE; s += 2) {
         const float e0 = col_term<MASKED, FACT>(rxy, rv, rtd, rg, s, jcol, tsj, xj, yj, kc);
         const float e1 = col_term<MASKED, FACT>(rxy, rv, rtd, rg, s + 1, jcol, tsj, xj, yj, kc);
@@ -794,9 +805,11 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
         kc->dt_cut = kc->dt_cut_ex = INFINITY;
     }
     kc->sx = sqrt(-kex);
-    fc->rho_bx = ((double)kc->kbx - kbx) / (double)kc->kbx;
+    kc->sbx = sqrt(-kbx);
+    kc->rex = (float)(kex / kbx);
     fc->dkbt = (double)kc->kbt - kbt;
-    fc->rho_ex = ((double)kc->kex - kex) / (double)kc->kex;
+    fc->rho_ex = ((double)kc->rex - kex / kbx) / (double)kc->rex;
+    fc->rho_exs = ((double)kc->kex - kex) / (double)kc->kex;
     const double corr = 1.0 / (1.0 + HK_EXP2_BIAS);
     const double two_pi = 6.283185307179586;
     fc->mu0 = hy->mu0; fc->tau_x = hy->tau_x; fc->tau_t = hy->tau_t;

@@ -167,11 +167,10 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
     double lam_part = 0.0;
     if (i < n) {
         const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
-        double b0 = 0.0, x0 = 0.0, b1 = 0.0, b2 = 0.0, x2 = 0.0;
+        double b0 = 0.0, x0 = 0.0, b2 = 0.0, x2 = 0.0;
         for (int sg = 0; sg < row_nseg[I]; ++sg) {
             const float *rp = rowpart + (int64_t)(row_item0[I] + sg) * HK_NROW * HK_TILE + r;
             b0 += rp[0];
-            b1 += rp[1 * HK_TILE];
             b2 += rp[2 * HK_TILE];
             x0 += rp[5 * HK_TILE];
             x2 += rp[7 * HK_TILE];
@@ -179,12 +178,11 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
         for (int J = I; J < ntiles; ++J) {
             const int64_t stride = (int64_t)(J + 1) * HK_TILE;
             b0 += (double)colpart[colpart_off[J] + i];
-            b1 += (double)colpart[colpart_off[J] + stride + i];
             b2 += (double)colpart[colpart_off[J] + 2 * stride + i];
         }
         // first-order correction for the rounded FP32 exponent constants
         const double ln2 = 0.6931471805599453;
-        b0 -= ln2 * (fc.rho_bx * b1 + fc.dkbt * b2);
+        b0 -= ln2 * fc.dkbt * b2;
         x0 -= ln2 * fc.rho_ex * x2;
         lam_static[i] = fc.c_b * b0 * fc.corr + fc.c_e * x0 * fc.corr;
         // integral term: background (all events) + excitation of the fixed-rate events
@@ -350,7 +348,7 @@ __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_
     double v = 0.0;
     if (i < n) {
         const double ln2 = 0.6931471805599453;
-        const double x = xs[i] - ln2 * fc.rho_ex * (double)xmom[i];
+        const double x = xs[i] - ln2 * fc.rho_exs * (double)xmom[i];
         const double l = lam_static[i] + fc.c_e * fc.corr * x;
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);

@@ -133,6 +133,8 @@ struct PairConst {
     double kex_d;  // kex and kw in FP64 (the column pass forms its exponent in FP64)
     double kw_d;
     double sx;     // sqrt(-kex): fixed-point coordinate -> coordinate whose squared distance is -a_e
+    double sbx;    // sqrt(-kbx): the same for the background exponent a_b
+    float rex;     // kex / kbx: a_e = a_b rex in the row pass
     double dt_cut;     // row pass: time gap past which both terms are below 2^-160 (INFINITY: no cutoff)
     double dt_cut_ex;  // column pass: the same for the excitation term alone
 };
@@ -146,11 +148,13 @@ struct FinConst {
     double t0, t1;
     // First-order correction for the rounding of the FP32 exponent constants:
     // a term computed as exp2(a + d) equals exp2(a) (1 + d ln 2 + O(d^2)), and d
-    // is linear in r^2, dt^2 (background) and r^2 (excitation), whose weighted
-    // sums are the first moments the row pass accumulates.  (The excitation's
+    // is linear in dt^2 (background) and r^2 (excitation), whose weighted sums
+    // are the first moments the row passes accumulate.  (The background's
+    // spatial exponent is formed in FP64 with an exact scale; the excitation's
     // time term is formed in FP64 or corrected inside the pair loop.)
-    double rho_bx, dkbt;   // (kbx_f - kbx) / kbx_f, kbt_f - kbt
-    double rho_ex;         // (kex_f - kex) / kex_f
+    double dkbt;           // kbt_f - kbt
+    double rho_ex;         // (rex_f - rex) / rex_f: full row pass, a_e = a_b rex_f
+    double rho_exs;        // (kex_f - kex) / kex_f: subset row pass, a_e = r^2 kex_f
 };
 
 bool hk_hyper_ok(const hawkes_hyper *h);
