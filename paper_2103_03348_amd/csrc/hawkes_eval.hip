@@ -100,12 +100,16 @@ __device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float v) {
 // excitation time factor the staged rate of each event,
 // theta_v_j = theta_j exp(omega (t_j - T_c)) with T_c its chunk's first time,
 // plus a flag per chunk that spans more than HK_FACT_SPAN / omega (those chunks
-// use the direct exponent and stage theta_j itself).  One wavefront per chunk.
+// use the direct exponent and stage theta_j itself), and the chunk's step factor
+// tstep_c = exp(-omega (T_{c+1} - T_c)) (0 for the last chunk), with which the
+// pair passes carry a row's or column's own split factor from one chunk to the
+// next instead of evaluating it anew.  One wavefront per chunk.
 template <bool FROM_CALLER>
 __global__ __launch_bounds__(256) void k_tfac(const double *__restrict__ theta, const int *__restrict__ perm,
                                               const double *__restrict__ ts, int64_t n, double omega,
                                               float *__restrict__ theta_s, float *__restrict__ theta_v,
-                                              int *__restrict__ chunk_wide, int *__restrict__ status) {
+                                              int *__restrict__ chunk_wide, double *__restrict__ tstep,
+                                              int *__restrict__ status) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // grid covers npad exactly
     const int lane = threadIdx.x & (HK_WAVE - 1);
     double th = 0.0;
@@ -121,7 +125,11 @@ __global__ __launch_bounds__(256) void k_tfac(const double *__restrict__ theta, 
     const double dti = ts[i] - ts[i - lane];
     const bool wide = __any(i < n && omega * dti > HK_FACT_SPAN);
     theta_v[i] = (!wide && th > 0.0) ? (float)(th * exp(omega * dti)) : (float)th;
-    if (lane == 0) chunk_wide[i / HK_WAVE] = wide;
+    if (lane == 0) {
+        chunk_wide[i / HK_WAVE] = wide;
+        const int64_t nxt = i + HK_WAVE;
+        tstep[i / HK_WAVE] = nxt < (int64_t)gridDim.x * blockDim.x ? exp(-omega * (ts[nxt] - ts[i])) : 0.0;
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -232,7 +240,7 @@ __device__ __forceinline__ void row_sweep_masked(const float2 *__restrict__ rec,
 template <int MODE>
 __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, const int *__restrict__ xi,
                                                   const int *__restrict__ yi, const float *__restrict__ theta_v,
-                                                  const int *__restrict__ chunk_wide,
+                                                  const int *__restrict__ chunk_wide, const double *__restrict__ tstep,
                                                   const int *__restrict__ g, const hk_item *__restrict__ items,
                                                   const int *__restrict__ block0,
                                                   const int64_t *__restrict__ colpart_off,
@@ -267,7 +275,14 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         double B0d = 0.0, X0d = 0.0;
 
         const double tile_tmin = ts[row0];
-        for (int c = it.c_begin; c < it.c_end; ++c) {
+        // the row's split factor exp(-omega (t_i - T_c)) is evaluated at the first
+        // split chunk that pairs with the wave and carried down to earlier chunks
+        // by their step factors (it only decreases, so it cannot overflow); a wide
+        // chunk breaks the chain
+        double ui = 0.0;
+        bool have_ui = false;
+        for (int c = it.c_end - 1; c >= it.c_begin; --c) {
+            if (have_ui) ui *= tstep[c];
             // under the cutoff a chunk that ends more than dt_cut before the
             // tile's first row is skipped by the whole block: its column
             // partials are zero
@@ -313,11 +328,19 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
                     row_sweep_masked<MODE, false>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
                                                   blk, C, B0d, X0c, C0d);
                 // the row's time factor (t_i >= T_c here, so it is at most 1)
-                const double ui = fact ? exp(-kc.omega * (tsi - Tc)) : 1.0;
-                X0d += ui * X0c;
-                const float uf = (float)ui;
+                if (fact) {
+                    if (!have_ui) {
+                        ui = exp(-kc.omega * (tsi - Tc));
+                        have_ui = true;
+                    }
+                    X0d += ui * X0c;
+                    const float uf = (float)ui;
 #pragma unroll
-                for (int a = 6; a < HK_NROW; ++a) blk[a] *= uf;
+                    for (int a = 6; a < HK_NROW; ++a) blk[a] *= uf;
+                } else {
+                    X0d += X0c;
+                    have_ui = false;
+                }
             }
             // after 64 rotation steps lane l holds the accumulators of column (l - 1) mod 64
             const int col = (lane + HK_WAVE - 1) & (HK_WAVE - 1);
@@ -405,8 +428,7 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
                                              const float *__restrict__ rowpart, const float *__restrict__ colpart,
                                              const int64_t *__restrict__ colpart_off, const FinConst fc,
                                              const int *__restrict__ chunk_wide,
-                                             double *__restrict__ lam, float *__restrict__ w, float *__restrict__ wlo,
-                                             float *__restrict__ wv, float *__restrict__ wvlo,
+                                             double *__restrict__ lam, float *__restrict__ wv,
                                              double *__restrict__ a_out,
                                              double *__restrict__ blockpart, int *__restrict__ status) {
     __shared__ double part[HK_WAVES][HK_NROW][HK_WAVE];
@@ -478,15 +500,10 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
             atomicOr(status, isnan(lamv) ? HK_ST_NONFINITE : HK_ST_ZERO);
         }
         {
+            // w_i = c_e / lambda_i, staged for the column pass as w_i exp(-omega (t_i - T_c))
+            // on split chunks, rounded once to FP32
             const double wd = lamv > 0.0 ? fc.c_e / lamv : 0.0;
-            const float whi = (float)wd;
-            w[i] = whi;
-            wlo[i] = (float)(wd - (double)whi);
-            // the column pass stages w_i exp(-omega (t_i - T_c)) on split chunks
-            const double v = chunk_wide[blockIdx.x] ? wd : wd * exp(-fc.omega * (ts[i] - ts[i - lane]));
-            const float vhi = (float)v;
-            wv[i] = vhi;
-            wvlo[i] = (float)(v - (double)vhi);
+            wv[i] = (float)(chunk_wide[blockIdx.x] ? wd : wd * exp(-fc.omega * (ts[i] - ts[i - lane])));
         }
         s[0] = log(lamv);
         const double inv = 1.0 / lamv;
@@ -539,10 +556,7 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
         }
     } else {
         lam[i] = 1.0;
-        w[i] = 0.0f;
-        wlo[i] = 0.0f;
         wv[i] = 0.0f;
-        wvlo[i] = 0.0f;
         a_out[i] = 0.0;
     }
 #pragma unroll
@@ -611,14 +625,15 @@ __global__ __launch_bounds__(HK_NSUM * HK_FIN2_LANES) void k_fin2(const double *
 // ------------------------------------------------------------------------------------
 // Column pass.  G_j = sum_{t_i > t_j} E_ij w_i and H_j = sum (E_ij w_i)^2 for the
 // lanes' columns j against a staged chunk of 64 later rows i.  With the time
-// factorisation the staged row carries v_i = w_i exp(-omega (t_i - T_c)) as an
-// FP32 (hi, lo) pair and the lane applies u_j = exp(omega (t_j - T_c)) to its
-// chunk sums; the spatial exponent is formed in FP64 and rounded once, so that
-// each term E_ij w_i is good to a few FP32 roundings (H squares it, which
-// doubles its relative error, and an absolute rounding of the exponent becomes
-// a relative error of the term, so the exponent must not carry more).
+// factorisation the staged row carries v_i = w_i exp(-omega (t_i - T_c)) in
+// FP32 and the lane applies u_j = exp(omega (t_j - T_c)) to its chunk sums; the
+// spatial exponent is formed in FP64 and rounded once, so that each term
+// E_ij w_i is good to a few FP32 roundings (H squares it, which doubles its
+// relative error, and an absolute rounding of the exponent becomes a relative
+// error of the term, so the exponent must not carry more).  The rounding of
+// v_i itself is independent across rows and averages out in the sums.
 template <bool MASKED, bool FACT>
-__device__ __forceinline__ float col_term(const double2 *__restrict__ rxy, const float2 *__restrict__ rv,
+__device__ __forceinline__ float col_term(const double2 *__restrict__ rxy, const float *__restrict__ rv,
                                           const double *__restrict__ rtd, const int *__restrict__ rg, int s,
                                           int jcol, double tsj, double xj, double yj, const PairConst kc) {
     // coordinates pre-scaled in FP64, so that the spatial exponent is minus a
@@ -631,8 +646,7 @@ __device__ __forceinline__ float col_term(const double2 *__restrict__ rxy, const
     if (MASKED) {
         if (!(jcol < rg[s])) E = 0.0f;
     }
-    const float2 v = rv[s];
-    return fmaf(E, v.y, E * v.x);
+    return E * rv[s];
 }
 
 // Two interleaved streams of steps (even and odd rows of the chunk) with their
@@ -645,7 +659,7 @@ __device__ __forceinline__ float col_term(const double2 *__restrict__ rxy, const
 #endif
 constexpr int kColUnroll = HK_COL_UNROLL;
 template <bool WITH_H, bool MASKED, bool FACT>
-__device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const float2 *__restrict__ rv,
+__device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
                                           const double *__restrict__ rtd, const int *__restrict__ rg, int jcol,
                                           double tsj, double xj, double yj, const PairConst kc, float &G, float &H) {
 #pragma clang fp contract(off)
@@ -668,12 +682,12 @@ __device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const
 template <bool WITH_H>
 __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, const int *__restrict__ xi,
                                                   const int *__restrict__ yi, const float *__restrict__ wv,
-                                                  const float *__restrict__ wvlo, const int *__restrict__ chunk_wide,
-                                                  const int *__restrict__ g,
+                                                  const int *__restrict__ chunk_wide,
+                                                  const double *__restrict__ tstep, const int *__restrict__ g,
                                                   const hk_item *__restrict__ items, const int *__restrict__ block0,
                                                   double *__restrict__ colG, const PairConst kc) {
     __shared__ double2 rxy[HK_WAVE];
-    __shared__ float2 rv[HK_WAVE];
+    __shared__ float rv[HK_WAVE];
     __shared__ double rtd[HK_WAVE];
     __shared__ int rg[HK_WAVE];
     const int tid = threadIdx.x, wvi = tid / HK_WAVE;
@@ -691,7 +705,14 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
 
         const double tile_tmax = ts[col0 + HK_TILE - 1];
         double Gd = 0.0, Hd = 0.0;
+        // the column's split factor exp(omega (t_j - T_c)), evaluated at the first
+        // split chunk with a causal pair and carried to later chunks by their step
+        // factors (decreasing from at most exp(HK_FACT_SPAN)); a wide chunk breaks
+        // the chain
+        double uj = 0.0;
+        bool have_uj = false;
         for (int c = it.c_begin; c < it.c_end; ++c) {
+            if (have_uj) uj *= tstep[c - 1];
             const double Tc = ts[(int64_t)c * HK_WAVE];
             // under the cutoff, rows starting more than dt_cut_ex after the
             // tile's latest column end the sweep (times are sorted)
@@ -699,7 +720,7 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
             if (tid < HK_WAVE) {
                 const int64_t i = (int64_t)c * HK_WAVE + tid;
                 rxy[tid] = make_double2((double)xi[i] * kc.sx, (double)yi[i] * kc.sx);
-                rv[tid] = make_float2(wv[i], wvlo[i]);  // w_i exp(-omega (t_i - T_c)) on split chunks
+                rv[tid] = wv[i];  // w_i exp(-omega (t_i - T_c)) on split chunks
                 rtd[tid] = ts[i];
                 rg[tid] = g[i];
             }
@@ -720,8 +741,15 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
                 }
                 // a column with a causal pair here has t_j < t_i <= T_c + span, so
                 // its factor is finite; the others have nothing to scale
-                if (G != 0.0f) {
-                    const double uj = fact ? exp(kc.omega * (tsj - Tc)) : 1.0;
+                if (!fact) {
+                    Gd += (double)G;
+                    if (WITH_H) Hd += (double)H;
+                    have_uj = false;
+                } else if (G != 0.0f) {
+                    if (!have_uj) {
+                        uj = exp(kc.omega * (tsj - Tc));
+                        have_uj = true;
+                    }
                     Gd += uj * (double)G;
                     if (WITH_H) Hd += (uj * uj) * (double)H;
                 }
@@ -787,13 +815,10 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     const double kbt = -1.0 / (2.0 * hy->tau_t * hy->tau_t * ln2);
     const double kex = -two_m2k / (2.0 * hy->h * hy->h * ln2);
     const double kw = -hy->omega / ln2;
-    kc->kbx = (float)kbx;
     kc->kbt = (float)kbt;
-    kc->kex = (float)kex;
     kc->kw = (float)kw;
     kc->cw = (float)(ln2 * (kw - (double)kc->kw));
     kc->omega = hy->omega;
-    kc->kex_d = kex;
     kc->kw_d = kw;
     // time gaps beyond which every background term (exponent <= kbt dt^2) and
     // every excitation term (exponent <= kw dt) is below 2^-160: exactly zero in
@@ -809,7 +834,6 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     kc->rex = (float)(kex / kbx);
     fc->dkbt = (double)kc->kbt - kbt;
     fc->rho_ex = ((double)kc->rex - kex / kbx) / (double)kc->rex;
-    fc->rho_exs = ((double)kc->kex - kex) / (double)kc->kex;
     const double corr = 1.0 / (1.0 + HK_EXP2_BIAS);
     const double two_pi = 6.283185307179586;
     fc->mu0 = hy->mu0; fc->tau_x = hy->tau_x; fc->tau_t = hy->tau_t;
@@ -833,10 +857,10 @@ static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, d
     hk_prof_mark(p, HK_PROF_COL, true, stream);
     if (d_negH_theta)
         hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->wv,
-                           p->wvlo, p->chunk_wide, p->g, p->col_items, p->col_block0, p->colG, kc);
+                           p->chunk_wide, p->tstep, p->g, p->col_items, p->col_block0, p->colG, kc);
     else
         hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                           p->wv, p->wvlo, p->chunk_wide, p->g, p->col_items, p->col_block0, p->colG, kc);
+                           p->wv, p->chunk_wide, p->tstep, p->g, p->col_items, p->col_block0, p->colG, kc);
     hk_prof_mark(p, HK_PROF_COL, false, stream);
     hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(256), 0, stream, p->perm, p->n, p->col_item0, p->col_nseg,
                        p->colG, p->a, fc, d_grad_theta, d_negH_theta);
@@ -882,16 +906,16 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 
     hk_prof_mark(p, HK_PROF_EVAL, true, stream);
     hipLaunchKernelGGL(k_tfac<true>, dim3((unsigned)(npad / 256)), dim3(256), 0, stream, d_theta, p->perm, p->ts,
-                       p->n, kc.omega, p->theta_s, p->theta_v, p->chunk_wide, p->status);
+                       p->n, kc.omega, p->theta_s, p->theta_v, p->chunk_wide, p->tstep, p->status);
     hk_prof_mark(p, HK_PROF_ROW, true, stream);
 #define HK_ROW(M)                                                                                              \
     hipLaunchKernelGGL(k_row<M>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,          \
-                       p->theta_v, p->chunk_wide, p->g, p->row_items, p->row_block0, p->colpart_off,             \
+                       p->theta_v, p->chunk_wide, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off,             \
                        p->rowpart, p->colpart, kc)
 #define HK_FIN(M)                                                                                              \
     hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->n,          \
                        p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart_off, fc,             \
-                       p->chunk_wide, p->lam, p->w, p->wlo, p->wv, p->wvlo, p->a, p->blockpart, p->status)
+                       p->chunk_wide, p->lam, p->wv, p->a, p->blockpart, p->status)
     if (mode == HK_MODE_GRAD) HK_ROW(HK_MODE_GRAD);
     else HK_ROW(HK_MODE_HESS);
     hk_prof_mark(p, HK_PROF_ROW, false, stream);
@@ -912,9 +936,9 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 
 void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream) {
     hipLaunchKernelGGL(k_tfac<false>, dim3((unsigned)(p->npad / 256)), dim3(256), 0, stream, (const double *)nullptr,
-                       p->perm, p->ts, p->n, kc.omega, p->theta_s, p->theta_v, p->chunk_wide, p->status);
+                       p->perm, p->ts, p->n, kc.omega, p->theta_s, p->theta_v, p->chunk_wide, p->tstep, p->status);
     hipLaunchKernelGGL(k_row<HK_MODE_GRAD>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                       p->theta_v, p->chunk_wide, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart,
+                       p->theta_v, p->chunk_wide, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart,
                        p->colpart, kc);
 }
 

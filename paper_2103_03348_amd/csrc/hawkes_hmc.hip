@@ -50,7 +50,6 @@ struct hk_subset {
     // per-evaluation buffers
     float *theta32;      // [mpad] subset rates, time order
     double *xs;          // [npad] subset excitation sums per event
-    float *xmom;         // [npad] sum theta E a_e per event (spatial-constant rounding)
     double *colG;        // [n_items][2][HK_TILE]
     double *gsub;        // [mpad] Eq. 4 on the subset, time order
     double *hsub;        // [mpad] Eq. 5 on the subset, time order
@@ -256,49 +255,43 @@ __global__ void k_sub_theta(const double *__restrict__ z, const double *__restri
 // entries that precede them (cnt[b]), staged 64 at a time through LDS.  The
 // time factor of E is split at the first staged entry's time as in the full row
 // pass (FP64 factors, spatial exponent in the loop) unless the staged entries
-// span more than HK_SUB_FACT_SPAN / omega in time.
+// span more than HK_SUB_FACT_SPAN / omega in time.  The exponent is formed in
+// FP64 from coordinates pre-scaled by sqrt(-kex) (and, unsplit, the FP64 time
+// term) and rounded once, so it carries no rounded FP32 constant.
 #define HK_SUB_FACT_SPAN 40.0
 
 template <bool FACT>
-__device__ __forceinline__ void sub_row_sweep(const float4 *__restrict__ rec, const double *__restrict__ rtd,
-                                              const int *__restrict__ rpos, double tsi, int xr, int yr, int gr,
-                                              const PairConst kc, double &acc, float &mae) {
+__device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
+                                              const double *__restrict__ rtd, const int *__restrict__ rpos,
+                                              double tsi, double xr, double yr, int gr, const PairConst kc,
+                                              double &acc) {
 #pragma unroll 8
     for (int s = 0; s < HK_WAVE; ++s) {
-        const float4 v = rec[s];
-        const float dx = (float)(xr - __float_as_int(v.y));
-        const float dy = (float)(yr - __float_as_int(v.z));
-        const float r2 = fmaf(dx, dx, dy * dy);
-        const float ae = r2 * kc.kex;
-        float E;
-        if (FACT) {
-            E = fexp2(ae);
-        } else {
-            const float dt = (float)(tsi - rtd[s]);
-            E = fexp2(fmaf(dt, kc.kw, ae)) * fmaf(dt, kc.cw, 1.0f);
-        }
+        const double2 pk = rxy[s];
+        const double dx = xr - pk.x, dy = yr - pk.y;
+        const double aed = -fma(dx, dx, dy * dy);
+        float E = fexp2(FACT ? (float)aed : (float)fma(tsi - rtd[s], kc.kw_d, aed));
         if (!(rpos[s] < gr)) E = 0.0f;
-        const float te = E * v.w;
-        acc += (double)te;
-        mae = fmaf(te, ae, mae);
+        acc += (double)(E * rv[s]);
     }
 }
 
 __global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
     const double *__restrict__ ts, const int *__restrict__ xi, const int *__restrict__ yi, const int *__restrict__ g,
     const int *__restrict__ pos, const float *__restrict__ theta32, const int *__restrict__ cnt,
-    const PairConst kc, double *__restrict__ xs, float *__restrict__ xmom) {
-    __shared__ float4 rec[HK_WAVE];
+    const PairConst kc, double *__restrict__ xs) {
+    __shared__ double2 rxy[HK_WAVE];
+    __shared__ float rv[HK_WAVE];
     __shared__ double rtd[HK_WAVE];
     __shared__ int rpos[HK_WAVE];
     const int b = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t i = (int64_t)b * HK_WAVE + lane;
     const double tsi = ts[i];
-    const int xr = xi[i], yr = yi[i], gr = g[i];
+    const double xr = (double)xi[i] * kc.sx, yr = (double)yi[i] * kc.sx;
+    const int gr = g[i];
     const int nsub = cnt[b];
     double acc = 0.0;  // every term in FP64 (see the row pass: FP32 sums drop small terms)
-    float mae = 0.0f;  // sum theta E a_e (rounding of the FP32 spatial constant)
     // under the cutoff, batches whose last entry precedes the chunk's first row
     // by more than dt_cut_ex are skipped (entries are in time order)
     const double chunk_tmin = ts[(int64_t)b * HK_WAVE];
@@ -312,34 +305,28 @@ __global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
             const double dtk = r < nsub ? ts[pj] - Tr : 0.0;
             const float th = r < nsub ? theta32[r] : 0.0f;
             fact = !__any(th > 0.0f && kc.omega * dtk > HK_SUB_FACT_SPAN);
-            float4 v;
-            v.x = (float)dtk;
-            v.y = __int_as_float(r < nsub ? xi[pj] : 0);
-            v.z = __int_as_float(r < nsub ? yi[pj] : 0);
-            v.w = (fact && th > 0.0f) ? (float)((double)th * exp(kc.omega * dtk)) : th;
-            rec[lane] = v;
+            rxy[lane] = r < nsub ? make_double2((double)xi[pj] * kc.sx, (double)yi[pj] * kc.sx)
+                                 : make_double2(0.0, 0.0);
+            rv[lane] = (fact && th > 0.0f) ? (float)((double)th * exp(kc.omega * dtk)) : th;
             rtd[lane] = r < nsub ? ts[pj] : 0.0;
             rpos[lane] = r < nsub ? pj : 0x7fffffff;
         }
         __syncthreads();
         double accb = 0.0;
-        float maeb = 0.0f;
-        if (fact) sub_row_sweep<true>(rec, rtd, rpos, tsi, xr, yr, gr, kc, accb, maeb);
-        else sub_row_sweep<false>(rec, rtd, rpos, tsi, xr, yr, gr, kc, accb, maeb);
+        if (fact) sub_row_sweep<true>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
+        else sub_row_sweep<false>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
         // a row with a causal pair here has t_i > t_k >= T_r: its factor is at most 1
         if (accb != 0.0) {
             const double ui = fact ? exp(-kc.omega * (tsi - Tr)) : 1.0;
             acc += ui * accb;
-            mae += (float)ui * maeb;
         }
         __syncthreads();
     }
     xs[i] = acc;
-    xmom[i] = mae;
 }
 
 __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_static, const double *__restrict__ xs,
-                                                 const float *__restrict__ xmom, int64_t n, int64_t npad,
+                                                 int64_t n, int64_t npad,
                                                  const FinConst fc,
                                                  double *__restrict__ lam, float *__restrict__ w, float *__restrict__ wlo,
                                                  double *__restrict__ blockpart, int *__restrict__ status) {
@@ -347,9 +334,7 @@ __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double v = 0.0;
     if (i < n) {
-        const double ln2 = 0.6931471805599453;
-        const double x = xs[i] - ln2 * fc.rho_exs * (double)xmom[i];
-        const double l = lam_static[i] + fc.c_e * fc.corr * x;
+        const double l = lam_static[i] + fc.c_e * fc.corr * xs[i];
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
         const double wd = l > 0.0 ? fc.c_e / l : 0.0;
@@ -616,7 +601,7 @@ void hk_subset_free(hawkes_plan p) {
     hk_subset *s = p->sub;
     if (!s) return;
     void *ptrs[] = {s->pos, s->slot, s->cidx, s->cnt, s->items, s->item0, s->nseg, s->lam_static, s->Lam_static,
-                    s->a, s->theta32, s->xs, s->xmom, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->off, s->vz, s->scal,
+                    s->a, s->theta32, s->xs, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->off, s->vz, s->scal,
                     s->grid};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -703,7 +688,6 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     SC(dalloc(&s->a, s->mpad));
     SC(dalloc(&s->theta32, s->mpad));
     SC(dalloc(&s->xs, p->npad));
-    SC(dalloc(&s->xmom, p->npad));
     SC(dalloc(&s->colG, (size_t)s->n_items * 2 * HK_TILE));
     SC(dalloc(&s->gsub, s->mpad));
     SC(dalloc(&s->hsub, s->mpad));
@@ -758,8 +742,8 @@ void sub_eval(hawkes_plan p, const double *z, const double *off, double *theta_f
     hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, off, s->slot, s->cidx, s->m,
                        s->mpad, s->theta32, theta_full);
     hipLaunchKernelGGL(k_sub_row, dim3(p->nchunks), dim3(SUB_ROW_THREADS), 0, stream, p->ts, p->xi, p->yi, p->g,
-                       s->pos, s->theta32, s->cnt, kc, s->xs, s->xmom);
-    hipLaunchKernelGGL(k_sub_fin, dim3(p->nfin_blocks), dim3(256), 0, stream, s->lam_static, s->xs, s->xmom, p->n,
+                       s->pos, s->theta32, s->cnt, kc, s->xs);
+    hipLaunchKernelGGL(k_sub_fin, dim3(p->nfin_blocks), dim3(256), 0, stream, s->lam_static, s->xs, p->n,
                        p->npad, fc,
                        p->lam, p->w, p->wlo, p->blockpart, p->status);
     if (with_h)

@@ -85,12 +85,13 @@ struct hawkes_plan_s {
     float *theta_s;           // [npad] rates in sorted order (FP32), 0 on padding
     float *theta_v;           // [npad] staged rates of the row pass (split time factor applied)
     int *chunk_wide;          // [nchunks] 1 where the chunk takes the direct exponent
-    float *wv, *wvlo;         // [npad] staged column-pass weights w_i exp(-omega (t_i - T_c)) (hi, lo)
+    double *tstep;            // [nchunks] exp(-omega (T_{c+1} - T_c)) of the last k_tfac
+    float *wv;                // [npad] staged column-pass weights w_i exp(-omega (t_i - T_c))
     float *rowpart;           // [n_row_items][HK_NROW][HK_TILE] row partial sums of each piece
     float *colpart;           // triangular [tile][HK_NCOL][(tile+1)*HK_TILE]: background column partials
     double *lam;              // [npad] lambda_i, sorted
-    float *w;                 // [npad] c_e / lambda_i (FP32 high part), 0 on padding
-    float *wlo;               // [npad] FP32 remainder of c_e / lambda_i
+    float *w;                 // [npad] c_e / lambda_i of the subset path (FP32 high part), 0 on padding
+    float *wlo;               // [npad] FP32 remainder of that c_e / lambda_i
     double *a;                // [npad] theta0 (1 - exp(-omega (T1 - t_i)))
     double *colG;             // [n_col_items][2][HK_TILE]: G and H of each column piece
     int nfin_blocks;          // npad / 256 (subset-path reductions)
@@ -124,17 +125,17 @@ int *hk_subset_grid_ptr(hawkes_plan p);
 // Exponent constants of the pair kernels (log2 units) and the FP64 constants of
 // the finalisation; built per call from the hyperparameters.
 struct PairConst {
-    float kbx;  // -2^{-2k} / (2 tau_x^2 ln 2): fixed-point r^2 -> log2 units, background
-    float kbt;  // -1 / (2 tau_t^2 ln 2)
-    float kex;  // -2^{-2k} / (2 h^2 ln 2): fixed-point r^2 -> log2 units, excitation
-    float kw;   // -omega / ln 2
+    // With k the coordinates' fixed-point scale (2^k units per unit length),
+    // kbx = -2^{-2k} / (2 tau_x^2 ln 2) and kex = -2^{-2k} / (2 h^2 ln 2) map a
+    // fixed-point squared distance to the log2 exponents a_b and a_e.
+    float kbt;     // -1 / (2 tau_t^2 ln 2)
+    float kw;      // -omega / ln 2
     float cw;      // ln 2 (kw - kw_f): first-order correction of the rounded kw, per unit dt
+    float rex;     // kex / kbx: a_e = a_b rex in the row pass
     double omega;  // excitation decay rate (time factors formed in FP64)
-    double kex_d;  // kex and kw in FP64 (the column pass forms its exponent in FP64)
-    double kw_d;
+    double kw_d;   // kw in FP64 (exponents formed in FP64)
     double sx;     // sqrt(-kex): fixed-point coordinate -> coordinate whose squared distance is -a_e
     double sbx;    // sqrt(-kbx): the same for the background exponent a_b
-    float rex;     // kex / kbx: a_e = a_b rex in the row pass
     double dt_cut;     // row pass: time gap past which both terms are below 2^-160 (INFINITY: no cutoff)
     double dt_cut_ex;  // column pass: the same for the excitation term alone
 };
@@ -153,8 +154,7 @@ struct FinConst {
     // spatial exponent is formed in FP64 with an exact scale; the excitation's
     // time term is formed in FP64 or corrected inside the pair loop.)
     double dkbt;           // kbt_f - kbt
-    double rho_ex;         // (rex_f - rex) / rex_f: full row pass, a_e = a_b rex_f
-    double rho_exs;        // (kex_f - kex) / kex_f: subset row pass, a_e = r^2 kex_f
+    double rho_ex;         // (rex_f - rex) / rex_f: the row pass forms a_e = a_b rex_f
 };
 
 bool hk_hyper_ok(const hawkes_hyper *h);
