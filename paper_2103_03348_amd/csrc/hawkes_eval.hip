@@ -417,74 +417,84 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 __device__ __forceinline__ double std_pdf(double u) { return 0.3989422804014327 * exp(-0.5 * u * u); }
 __device__ __forceinline__ double std_cdf(double u) { return 0.5 * erfc(-u * 0.7071067811865476); }
 
-// Finalisation, one block per 64-event chunk.  The four wavefronts first split
-// the partial sums of the chunk's events between them (row pieces and column
-// partials of the later row tiles, round robin), the partials are combined in a
-// fixed order through LDS, and the first wavefront finishes the events.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, const double *__restrict__ theta,
-                                             const int *__restrict__ perm, int64_t n, int ntiles,
-                                             const int *__restrict__ row_item0, const int *__restrict__ row_nseg,
-                                             const float *__restrict__ rowpart, const float *__restrict__ colpart,
-                                             const int64_t *__restrict__ colpart_off, const FinConst fc,
-                                             const int *__restrict__ chunk_wide,
-                                             double *__restrict__ lam, float *__restrict__ wv,
-                                             double *__restrict__ a_out,
-                                             double *__restrict__ blockpart, int *__restrict__ status) {
-    __shared__ double part[HK_WAVES][HK_NROW][HK_WAVE];
-    const int lane = threadIdx.x & (HK_WAVE - 1), wq = threadIdx.x / HK_WAVE;
-    const int64_t i = (int64_t)blockIdx.x * HK_WAVE + lane;
-    const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
-    {
-        double acc[HK_NROW];
-#pragma unroll
-        for (int k = 0; k < HK_NROW; ++k) acc[k] = 0.0;
-        const int it0 = row_item0[I], ns = row_nseg[I];
-        for (int sg = wq; sg < ns; sg += HK_WAVES) {
-            const float *rp = rowpart + (int64_t)(it0 + sg) * HK_NROW * HK_TILE + r;
-            acc[0] += rp[0];
-            acc[5] += rp[5 * HK_TILE];
-            if (MODE >= HK_MODE_GRAD) {
-                acc[1] += rp[1 * HK_TILE];
-                acc[2] += rp[2 * HK_TILE];
-                acc[6] += rp[6 * HK_TILE];
-                acc[7] += rp[7 * HK_TILE];
-            }
-            if (MODE >= HK_MODE_HESS) {
-                acc[3] += rp[3 * HK_TILE];
-                acc[4] += rp[4 * HK_TILE];
-                acc[8] += rp[8 * HK_TILE];
-                acc[9] += rp[9 * HK_TILE];
-            }
-        }
-        // background from later events: the column partials of row tiles J >= I
-        for (int J = I + wq; J < ntiles; J += HK_WAVES) {
-            const int64_t stride = (int64_t)(J + 1) * HK_TILE;
-            const float *cp = colpart + colpart_off[J] + i;
-            acc[0] += (double)cp[0];
-            if (MODE >= HK_MODE_GRAD) {
-                acc[1] += (double)cp[stride];
-                acc[2] += (double)cp[2 * stride];
-            }
-            if (MODE >= HK_MODE_HESS) {
-                acc[3] += (double)cp[3 * stride];
-                acc[4] += (double)cp[4 * stride];
-            }
+// Knuth's TwoSum in FP64: the exact rounding error of a + b (independent of
+// the order of the operands).
+__device__ __forceinline__ double two_sum_err(double a, double b, double s) {
+    const double bp = s - a;
+    return (a - (s - bp)) + (b - bp);
+}
+
+// The per-block partials ([HK_NSUM][nblocks]) -> loglik and the hyperparameter
+// derivatives, by HK_NSUM * HK_TOT_LANES threads of one block: lane l of sum k
+// keeps a Neumaier sum over blocks l, l + HK_TOT_LANES, ... (coalesced loads,
+// all in flight together), then the lanes of the sum combine by a butterfly of
+// exact TwoSum steps, so that the result is fixed whatever the timing.
+constexpr int HK_TOT_LANES = 32;
+
+__device__ void fin_totals(const double *__restrict__ blockpart, int nblocks, double *__restrict__ loglik,
+                           double *__restrict__ grad_hyper, double *__restrict__ negH_hyper,
+                           int *__restrict__ status, double *tot) {
+    const int k = threadIdx.x / HK_TOT_LANES, l = threadIdx.x % HK_TOT_LANES;
+    if (k < HK_NSUM) {
+        const double *part = blockpart + (int64_t)k * nblocks;
+        double sum = 0.0, c = 0.0, plain = 0.0;
+#pragma unroll 4
+        for (int b = l; b < nblocks; b += HK_TOT_LANES) {
+            const double v = part[b];
+            const double t = sum + v;
+            c += two_sum_err(sum, v, t);
+            sum = t;
+            plain += v;
         }
 #pragma unroll
-        for (int k = 0; k < HK_NROW; ++k) part[wq][k][lane] = acc[k];
+        for (int off = 1; off < HK_TOT_LANES; off <<= 1) {
+            const double s2 = __shfl_xor(sum, off), c2 = __shfl_xor(c, off), p2 = __shfl_xor(plain, off);
+            const double t = sum + s2;
+            c = (c + c2) + two_sum_err(sum, s2, t);
+            sum = t;
+            plain += p2;
+        }
+        if (l == 0) tot[k] = isfinite(plain) ? sum + c : plain;
     }
     __syncthreads();
-    if (wq != 0) return;
+    if (threadIdx.x == 0) {
+        const double ll = tot[0] - tot[13];
+        if (loglik) loglik[0] = ll;
+        if (isnan(ll)) atomicOr(status, HK_ST_NONFINITE);
+        if (grad_hyper) {
+            const double dL[6] = {tot[14], 0.0, tot[15], tot[16], tot[17], 0.0};
+            for (int p = 0; p < 6; ++p) grad_hyper[p] = tot[1 + p] - dL[p];
+        }
+        if (negH_hyper) {
+            const double d2L[6] = {0.0, 0.0, tot[18], 0.0, tot[19], 0.0};
+            for (int p = 0; p < 6; ++p) negH_hyper[p] = -tot[7 + p] + d2L[p];
+        }
+    }
+}
 
+constexpr int HK_FIN_WAVES = 8;
+
+// The first wavefront of a k_fin block: lambda_i, w_i, the per-event terms of
+// the hyperparameter derivatives and the integral, and their block sums.
+template <int MODE>
+__device__ __forceinline__ void fin_events(const double *__restrict__ ts, const double *__restrict__ theta,
+                                           const int *__restrict__ perm, int64_t n, const FinConst &fc,
+                                           const int *__restrict__ chunk_wide,
+                                           const double (*part)[HK_NROW][HK_WAVE], int lane, int64_t i,
+                                           double *__restrict__ lam, float *__restrict__ wv,
+                                           double *__restrict__ a_out, double *__restrict__ blockpart,
+                                           int *__restrict__ status) {
     double s[HK_NSUM];
 #pragma unroll
     for (int k = 0; k < HK_NSUM; ++k) s[k] = 0.0;
     if (i < n) {
         double acc[HK_NROW];
 #pragma unroll
-        for (int k = 0; k < HK_NROW; ++k)
-            acc[k] = ((part[0][k][lane] + part[1][k][lane]) + part[2][k][lane]) + part[3][k][lane];
+        for (int k = 0; k < HK_NROW; ++k) {
+            double v = part[0][k][lane];
+            for (int q = 1; q < HK_FIN_WAVES; ++q) v += part[q][k][lane];
+            acc[k] = v;
+        }
         // moments corrected for the mean exp2 bias and, when the first moments
         // are present, for the rounding of the FP32 exponent constants
         double b0 = acc[0], x0 = acc[5];
@@ -566,61 +576,80 @@ __global__ __launch_bounds__(256) void k_fin(const double *__restrict__ ts, cons
     }
 }
 
-// Knuth's TwoSum in FP64: the exact rounding error of a + b (independent of
-// the order of the operands).
-__device__ __forceinline__ double two_sum_err(double a, double b, double s) {
-    const double bp = s - a;
-    return (a - (s - bp)) + (b - bp);
-}
 
-// The per-block partials ([HK_NSUM][nblocks]) -> loglik and the
-// hyperparameter derivatives, in one block of HK_NSUM half-wavefronts: lane l of
-// sum k keeps a Neumaier sum over blocks l, l + 32, ... (coalesced loads, all in
-// flight together), then the 32 lanes of the sum combine by a butterfly of
-// exact TwoSum steps, so that the result is fixed whatever the timing.
-constexpr int HK_FIN2_LANES = 32;
-
-__global__ __launch_bounds__(HK_NSUM * HK_FIN2_LANES) void k_fin2(const double *__restrict__ blockpart,
-                                                                  int nblocks, double *__restrict__ loglik,
-                                                                  double *__restrict__ grad_hyper,
-                                                                  double *__restrict__ negH_hyper,
-                                                                  int *__restrict__ status) {
-    __shared__ double tot[HK_NSUM];
-    const int k = threadIdx.x / HK_FIN2_LANES, l = threadIdx.x % HK_FIN2_LANES;
-    const double *part = blockpart + (int64_t)k * nblocks;
-    double sum = 0.0, c = 0.0, plain = 0.0;
-#pragma unroll 4
-    for (int b = l; b < nblocks; b += HK_FIN2_LANES) {
-        const double v = part[b];
-        const double t = sum + v;
-        c += two_sum_err(sum, v, t);
-        sum = t;
-        plain += v;
-    }
+// Finalisation, one block per 64-event chunk.  The HK_FIN_WAVES wavefronts
+// first split the partial sums of the chunk's events between them (row pieces
+// and column partials of the later row tiles, round robin; these reads are the
+// kernel's cost, so many are kept in flight), the partials are combined in a
+// fixed order through LDS, and the first wavefront finishes the events.
+template <int MODE>
+__global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__restrict__ ts, const double *__restrict__ theta,
+                                             const int *__restrict__ perm, int64_t n, int ntiles,
+                                             const int *__restrict__ row_item0, const int *__restrict__ row_nseg,
+                                             const float *__restrict__ rowpart, const float *__restrict__ colpart,
+                                             const FinConst fc, const int *__restrict__ chunk_wide,
+                                             double *__restrict__ lam, float *__restrict__ wv,
+                                             double *__restrict__ a_out,
+                                             double *__restrict__ blockpart, int *__restrict__ status) {
+    __shared__ double part[HK_FIN_WAVES][HK_NROW][HK_WAVE];
+    const int lane = threadIdx.x & (HK_WAVE - 1), wq = threadIdx.x / HK_WAVE;
+    const int64_t i = (int64_t)blockIdx.x * HK_WAVE + lane;
+    const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
+    {
+        double acc[HK_NROW];
 #pragma unroll
-    for (int off = 1; off < HK_FIN2_LANES; off <<= 1) {
-        const double s2 = __shfl_xor(sum, off), c2 = __shfl_xor(c, off), p2 = __shfl_xor(plain, off);
-        const double t = sum + s2;
-        c = (c + c2) + two_sum_err(sum, s2, t);
-        sum = t;
-        plain += p2;
+        for (int k = 0; k < HK_NROW; ++k) acc[k] = 0.0;
+        const int it0 = row_item0[I], ns = row_nseg[I];
+        for (int sg = wq; sg < ns; sg += HK_FIN_WAVES) {
+            const float *rp = rowpart + (int64_t)(it0 + sg) * HK_NROW * HK_TILE + r;
+            acc[0] += rp[0];
+            acc[5] += rp[5 * HK_TILE];
+            if (MODE >= HK_MODE_GRAD) {
+                acc[1] += rp[1 * HK_TILE];
+                acc[2] += rp[2 * HK_TILE];
+                acc[6] += rp[6 * HK_TILE];
+                acc[7] += rp[7 * HK_TILE];
+            }
+            if (MODE >= HK_MODE_HESS) {
+                acc[3] += rp[3 * HK_TILE];
+                acc[4] += rp[4 * HK_TILE];
+                acc[8] += rp[8 * HK_TILE];
+                acc[9] += rp[9 * HK_TILE];
+            }
+        }
+        // background from later events: the column partials of row tiles J >= I
+        // (region J starts at HK_NCOL HK_TILE J (J + 1) / 2)
+        for (int J = I + wq; J < ntiles; J += HK_FIN_WAVES) {
+            const int64_t stride = (int64_t)(J + 1) * HK_TILE;
+            const float *cp = colpart + (int64_t)HK_NCOL * HK_TILE * J * (J + 1) / 2 + i;
+            acc[0] += (double)cp[0];
+            if (MODE >= HK_MODE_GRAD) {
+                acc[1] += (double)cp[stride];
+                acc[2] += (double)cp[2 * stride];
+            }
+            if (MODE >= HK_MODE_HESS) {
+                acc[3] += (double)cp[3 * stride];
+                acc[4] += (double)cp[4 * stride];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < HK_NROW; ++k) part[wq][k][lane] = acc[k];
     }
-    if (l == 0) tot[k] = isfinite(plain) ? sum + c : plain;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double ll = tot[0] - tot[13];
-        if (loglik) loglik[0] = ll;
-        if (isnan(ll)) atomicOr(status, HK_ST_NONFINITE);
-        if (grad_hyper) {
-            const double dL[6] = {tot[14], 0.0, tot[15], tot[16], tot[17], 0.0};
-            for (int p = 0; p < 6; ++p) grad_hyper[p] = tot[1 + p] - dL[p];
-        }
-        if (negH_hyper) {
-            const double d2L[6] = {0.0, 0.0, tot[18], 0.0, tot[19], 0.0};
-            for (int p = 0; p < 6; ++p) negH_hyper[p] = -tot[7 + p] + d2L[p];
-        }
-    }
+    if (wq == 0) fin_events<MODE>(ts, theta, perm, n, fc, chunk_wide, part, lane, i, lam, wv, a_out, blockpart,
+                                  status);
 }
+
+// One block: the partials of every k_fin block -> the scalar results.
+__global__ __launch_bounds__(HK_NSUM * HK_TOT_LANES) void k_fin2(const double *__restrict__ blockpart, int nblocks,
+                                                                double *__restrict__ loglik,
+                                                                double *__restrict__ grad_hyper,
+                                                                double *__restrict__ negH_hyper,
+                                                                int *__restrict__ status) {
+    __shared__ double tot[HK_NSUM];
+    fin_totals(blockpart, nblocks, loglik, grad_hyper, negH_hyper, status, tot);
+}
+
 
 // ------------------------------------------------------------------------------------
 // Column pass.  G_j = sum_{t_i > t_j} E_ij w_i and H_j = sum (E_ij w_i)^2 for the
@@ -762,20 +791,21 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
     }
 }
 
-// Column finalisation, one block per 64-event chunk: the wavefronts split the
-// column pieces round robin, then the first combines them in a fixed order.
-__global__ __launch_bounds__(256) void k_colfin(const int *__restrict__ perm, int64_t n,
+// Column finalisation, one block per 64-event chunk: the HK_FIN_WAVES
+// wavefronts split the column pieces round robin (reads in flight), then the
+// first combines them in a fixed order.
+__global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_colfin(const int *__restrict__ perm, int64_t n,
                                                 const int *__restrict__ col_item0, const int *__restrict__ col_nseg,
                                                 const double *__restrict__ colG, const double *__restrict__ a,
                                                 const FinConst fc, double *__restrict__ grad_theta,
                                                 double *__restrict__ negH_theta) {
-    __shared__ double part[HK_WAVES][2][HK_WAVE];
+    __shared__ double part[HK_FIN_WAVES][2][HK_WAVE];
     const int lane = threadIdx.x & (HK_WAVE - 1), wv = threadIdx.x / HK_WAVE;
     const int64_t j = (int64_t)blockIdx.x * HK_WAVE + lane;
     const int J = (int)(j / HK_TILE), r = (int)(j % HK_TILE);
     const int it0 = col_item0[J], ns = col_nseg[J];
     double G = 0.0, H = 0.0;
-    for (int sg = wv; sg < ns; sg += HK_WAVES) {
+    for (int sg = wv; sg < ns; sg += HK_FIN_WAVES) {
         const double *cg = colG + (int64_t)(it0 + sg) * 2 * HK_TILE + r;
         G += cg[0];
         if (negH_theta) H += cg[HK_TILE];
@@ -784,8 +814,11 @@ __global__ __launch_bounds__(256) void k_colfin(const int *__restrict__ perm, in
     part[wv][1][lane] = H;
     __syncthreads();
     if (wv != 0 || j >= n) return;
-    const double Gs = ((part[0][0][lane] + part[1][0][lane]) + part[2][0][lane]) + part[3][0][lane];
-    const double Hs = ((part[0][1][lane] + part[1][1][lane]) + part[2][1][lane]) + part[3][1][lane];
+    double Gs = part[0][0][lane], Hs = part[0][1][lane];
+    for (int q = 1; q < HK_FIN_WAVES; ++q) {
+        Gs += part[q][0][lane];
+        Hs += part[q][1][lane];
+    }
     const int dst = perm[j];
     if (grad_theta) grad_theta[dst] = Gs * fc.corr - a[j];
     if (negH_theta) negH_theta[dst] = Hs * fc.corr * fc.corr;
@@ -862,7 +895,7 @@ static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, d
         hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
                            p->wv, p->chunk_wide, p->tstep, p->g, p->col_items, p->col_block0, p->colG, kc);
     hk_prof_mark(p, HK_PROF_COL, false, stream);
-    hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(256), 0, stream, p->perm, p->n, p->col_item0, p->col_nseg,
+    hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->perm, p->n, p->col_item0, p->col_nseg,
                        p->colG, p->a, fc, d_grad_theta, d_negH_theta);
 }
 
@@ -913,8 +946,8 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
                        p->theta_v, p->chunk_wide, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off,             \
                        p->rowpart, p->colpart, kc)
 #define HK_FIN(M)                                                                                              \
-    hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->n,          \
-                       p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, p->colpart_off, fc,             \
+    hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->ts, d_theta,       \
+                       p->perm, p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, fc,             \
                        p->chunk_wide, p->lam, p->wv, p->a, p->blockpart, p->status)
     if (mode == HK_MODE_GRAD) HK_ROW(HK_MODE_GRAD);
     else HK_ROW(HK_MODE_HESS);
@@ -923,8 +956,8 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
     else HK_FIN(HK_MODE_HESS);
 #undef HK_ROW
 #undef HK_FIN
-    hipLaunchKernelGGL(k_fin2, dim3(1), dim3(HK_NSUM * HK_FIN2_LANES), 0, stream, p->blockpart, p->nchunks,
-                       d_loglik, d_grad_hyper, d_negH_hyper, p->status);
+    hipLaunchKernelGGL(k_fin2, dim3(1), dim3(HK_NSUM * HK_TOT_LANES), 0, stream, p->blockpart, p->nchunks, d_loglik,
+                       d_grad_hyper, d_negH_hyper, p->status);
     p->epoch += 1;
     p->eval_epoch = p->epoch;
     p->eval_hyper = *hyper;
