@@ -35,12 +35,16 @@ struct hk_subset {
     int *pos;            // [mpad] sorted position of subset entry r (time order); pad = INT_MAX
     int *slot;           // [mpad] caller's subset slot k of entry r
     int64_t *cidx;       // [m] caller index of slot k (copy of the caller's idx)
-    int *cnt;            // [nchunks] number of subset entries with pos < 64 (b + 1)
-    // column pass schedule over subset tiles
+    // row pass schedule: (row chunk, range of subset entries before its end)
+    int n_ritems;
+    hk_item *ritems;     // (row chunk, entry begin, entry end, seg)
+    int *ritem0, *rnseg; // per row chunk
+    double *xpart;       // [n_ritems][HK_WAVE] excitation partial sums of each item
+    // column pass schedule: (64-entry subset chunk, row chunk begin, end)
     int n_items;
-    hk_item *items;      // (subset tile, row chunk begin, end, seg)
-    int *item0, *nseg;   // per subset tile
-    int ntiles;
+    hk_item *items;      // (subset chunk, row chunk begin, end, seg)
+    int *item0, *nseg;   // per subset chunk
+    int nq;              // subset chunks: mpad / HK_WAVE
     // cached static part
     bool static_valid;
     hawkes_hyper static_hyper;
@@ -49,8 +53,7 @@ struct hk_subset {
     double *a;           // [mpad] theta0 (1 - exp(-omega (T1 - t_k))) per subset entry r
     // per-evaluation buffers
     float *theta32;      // [mpad] subset rates, time order
-    double *xs;          // [npad] subset excitation sums per event
-    double *colG;        // [n_items][2][HK_TILE]
+    double *colG;        // [n_items][2][HK_WAVE]
     double *gsub;        // [mpad] Eq. 4 on the subset, time order
     double *hsub;        // [mpad] Eq. 5 on the subset, time order
     double *sums;        // [8] loglik pieces of the last evaluation
@@ -66,7 +69,18 @@ struct hk_subset {
 
 namespace {
 
-constexpr int SUB_ROW_THREADS = HK_WAVE;  // one wavefront per 64-row chunk
+// The subset passes are split into many one-wavefront items (about this many
+// each) so that the whole chip takes part; partial sums per item are combined
+// in a fixed order afterwards.
+#ifndef HK_SUB_ROW_ITEMS
+#define HK_SUB_ROW_ITEMS 8192
+#endif
+#ifndef HK_SUB_COL_ITEMS
+#define HK_SUB_COL_ITEMS 4096
+#endif
+constexpr int64_t SUB_ROW_ITEMS = HK_SUB_ROW_ITEMS;
+constexpr int64_t SUB_COL_ITEMS = HK_SUB_COL_ITEMS;
+constexpr int SUB_FIN_WAVES = 8;
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -116,18 +130,6 @@ __global__ void k_sub_layout(const double *__restrict__ key, const int *__restri
 }
 
 // cnt[b] = number of subset entries with pos < 64 (b + 1) (binary search).
-__global__ void k_sub_count(const int *__restrict__ pos, int64_t m, int nchunks, int *__restrict__ cnt) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nchunks) return;
-    const int lim = HK_WAVE * (b + 1);
-    int64_t lo = 0, hi = m;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (pos[mid] < lim) lo = mid + 1;
-        else hi = mid;
-    }
-    cnt[b] = (int)lo;
-}
 
 // ---- static part ---------------------------------------------------------------------
 // theta with the subset entries zeroed, sorted, FP32
@@ -276,40 +278,45 @@ __device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, c
     }
 }
 
-__global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
+// One item: the 64 rows of a chunk against a range of the subset entries that
+// precede the chunk's end (64 at a time through LDS); the rows' partial sums go
+// to the item's slot.
+__global__ __launch_bounds__(HK_WAVE) void k_sub_row(
     const double *__restrict__ ts, const int *__restrict__ xi, const int *__restrict__ yi, const int *__restrict__ g,
-    const int *__restrict__ pos, const float *__restrict__ theta32, const int *__restrict__ cnt,
-    const PairConst kc, double *__restrict__ xs) {
+    const int *__restrict__ pos, const float *__restrict__ theta32, const hk_item *__restrict__ ritems,
+    const PairConst kc, double *__restrict__ xpart) {
     __shared__ double2 rxy[HK_WAVE];
     __shared__ float rv[HK_WAVE];
     __shared__ double rtd[HK_WAVE];
     __shared__ int rpos[HK_WAVE];
-    const int b = blockIdx.x;
+    const hk_item it = ritems[blockIdx.x];
+    const int b = it.tile;
     const int lane = threadIdx.x;
     const int64_t i = (int64_t)b * HK_WAVE + lane;
     const double tsi = ts[i];
     const double xr = (double)xi[i] * kc.sx, yr = (double)yi[i] * kc.sx;
     const int gr = g[i];
-    const int nsub = cnt[b];
     double acc = 0.0;  // every term in FP64 (see the row pass: FP32 sums drop small terms)
     // under the cutoff, batches whose last entry precedes the chunk's first row
     // by more than dt_cut_ex are skipped (entries are in time order)
     const double chunk_tmin = ts[(int64_t)b * HK_WAVE];
-    for (int c0 = 0; c0 < nsub; c0 += HK_WAVE) {
-        if (chunk_tmin - ts[pos[min(c0 + HK_WAVE, nsub) - 1]] > kc.dt_cut_ex) continue;
+    for (int c0 = it.c_begin; c0 < it.c_end; c0 += HK_WAVE) {
+        const int cend = min(c0 + HK_WAVE, it.c_end);
+        if (chunk_tmin - ts[pos[cend - 1]] > kc.dt_cut_ex) continue;
         const double Tr = ts[pos[c0]];
         bool fact;
         {
             const int r = c0 + lane;
-            const int pj = r < nsub ? pos[r] : 0;
-            const double dtk = r < nsub ? ts[pj] - Tr : 0.0;
-            const float th = r < nsub ? theta32[r] : 0.0f;
+            const bool valid = r < cend;
+            const int pj = valid ? pos[r] : 0;
+            const double dtk = valid ? ts[pj] - Tr : 0.0;
+            const float th = valid ? theta32[r] : 0.0f;
             fact = !__any(th > 0.0f && kc.omega * dtk > HK_SUB_FACT_SPAN);
-            rxy[lane] = r < nsub ? make_double2((double)xi[pj] * kc.sx, (double)yi[pj] * kc.sx)
-                                 : make_double2(0.0, 0.0);
+            rxy[lane] = valid ? make_double2((double)xi[pj] * kc.sx, (double)yi[pj] * kc.sx)
+                              : make_double2(0.0, 0.0);
             rv[lane] = (fact && th > 0.0f) ? (float)((double)th * exp(kc.omega * dtk)) : th;
-            rtd[lane] = r < nsub ? ts[pj] : 0.0;
-            rpos[lane] = r < nsub ? pj : 0x7fffffff;
+            rtd[lane] = valid ? ts[pj] : 0.0;
+            rpos[lane] = valid ? pj : 0x7fffffff;
         }
         __syncthreads();
         double accb = 0.0;
@@ -322,11 +329,12 @@ __global__ __launch_bounds__(SUB_ROW_THREADS) void k_sub_row(
         }
         __syncthreads();
     }
-    xs[i] = acc;
+    xpart[(int64_t)blockIdx.x * HK_WAVE + lane] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_static, const double *__restrict__ xs,
-                                                 int64_t n, int64_t npad,
+__global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_static,
+                                                 const int *__restrict__ ritem0, const int *__restrict__ rnseg,
+                                                 const double *__restrict__ xpart, int64_t n, int64_t npad,
                                                  const FinConst fc,
                                                  double *__restrict__ lam, float *__restrict__ w, float *__restrict__ wlo,
                                                  double *__restrict__ blockpart, int *__restrict__ status) {
@@ -334,7 +342,14 @@ __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double v = 0.0;
     if (i < n) {
-        const double l = lam_static[i] + fc.c_e * fc.corr * xs[i];
+        // the row items of this chunk, in order
+        const int b = (int)(i / HK_WAVE), lane = (int)(i % HK_WAVE);
+        const double *xp = xpart + (int64_t)ritem0[b] * HK_WAVE + lane;
+        double x = 0.0;
+        const int ns = rnseg[b];
+#pragma unroll 4
+        for (int sg = 0; sg < ns; ++sg) x += xp[(int64_t)sg * HK_WAVE];
+        const double l = lam_static[i] + fc.c_e * fc.corr * x;
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
         const double wd = l > 0.0 ? fc.c_e / l : 0.0;
@@ -375,8 +390,10 @@ __device__ __forceinline__ void sub_col_sweep(const double2 *__restrict__ rxy, c
     }
 }
 
+// One item: a chunk of 64 subset entries (the lanes) against a range of row
+// chunks after them; the entries' partial sums go to the item's slot.
 template <bool WITH_H>
-__global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ ts, const int *__restrict__ xi,
+__global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ ts, const int *__restrict__ xi,
                                                       const int *__restrict__ yi, const float *__restrict__ w,
                                                       const float *__restrict__ wlo, const int *__restrict__ g,
                                                       const int *__restrict__ pos, int64_t m,
@@ -386,38 +403,36 @@ __global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ 
     __shared__ float2 rv[HK_WAVE];
     __shared__ double rtd[HK_WAVE];
     __shared__ int rg[HK_WAVE];
-    __shared__ int fact_sh;
     const hk_item it = items[blockIdx.x];
-    const int tid = threadIdx.x;
-    const int64_t r = (int64_t)it.tile * HK_TILE + tid;
+    const int lane = threadIdx.x;
+    const int64_t r = (int64_t)it.tile * HK_WAVE + lane;
     const bool live = r < m;
     const int pj = live ? pos[r] : 0;
     const double tsj = ts[pj];
     const double xj = (double)xi[pj] * kc.sx, yj = (double)yi[pj] * kc.sx;
-    // the tile's latest entry (entries are in time order; padding entries
+    // the chunk's latest entry (entries are in time order; padding entries
     // repeat position 0 and do not raise it)
-    const int64_t r_last = min((int64_t)it.tile * HK_TILE + HK_TILE, m) - 1;
-    const double tile_tmax = ts[pos[r_last]];
+    const int64_t r_last = min((int64_t)it.tile * HK_WAVE + HK_WAVE, m) - 1;
+    const double q_tmax = ts[pos[r_last]];
     double Gd = 0.0, Hd = 0.0;
     for (int c = it.c_begin; c < it.c_end; ++c) {
         const double Tc = ts[(int64_t)c * HK_WAVE];
-        if (Tc - tile_tmax > kc.dt_cut_ex) break;  // cutoff: all later rows too far
-        if (tid < HK_WAVE) {
-            const int64_t i = (int64_t)c * HK_WAVE + tid;
+        if (Tc - q_tmax > kc.dt_cut_ex) break;  // cutoff: all later rows too far
+        bool fact;
+        {
+            const int64_t i = (int64_t)c * HK_WAVE + lane;
             const double ti = ts[i];
             const double dti = ti - Tc;
             const double wd = (double)w[i] + (double)wlo[i];
-            const bool fact = !__any(wd > 0.0 && kc.omega * dti > HK_SUB_FACT_SPAN);
+            fact = !__any(wd > 0.0 && kc.omega * dti > HK_SUB_FACT_SPAN);
             const double vv = fact ? wd * exp(-kc.omega * dti) : wd;
             const float vhi = (float)vv;
-            rxy[tid] = make_double2((double)xi[i] * kc.sx, (double)yi[i] * kc.sx);
-            rv[tid] = make_float2(vhi, (float)(vv - (double)vhi));
-            rtd[tid] = ti;
-            rg[tid] = g[i];
-            if (tid == 0) fact_sh = fact;
+            rxy[lane] = make_double2((double)xi[i] * kc.sx, (double)yi[i] * kc.sx);
+            rv[lane] = make_float2(vhi, (float)(vv - (double)vhi));
+            rtd[lane] = ti;
+            rg[lane] = g[i];
         }
         __syncthreads();
-        const bool fact = fact_sh != 0;
         float G = 0.0f, H = 0.0f;
         if (fact) sub_col_sweep<WITH_H, true>(rxy, rv, rtd, rg, pj, tsj, xj, yj, kc, G, H);
         else sub_col_sweep<WITH_H, false>(rxy, rv, rtd, rg, pj, tsj, xj, yj, kc, G, H);
@@ -428,25 +443,39 @@ __global__ __launch_bounds__(HK_TILE) void k_sub_col(const double *__restrict__ 
         }
         __syncthreads();
     }
-    double *cg = colG + (int64_t)blockIdx.x * 2 * HK_TILE;
-    cg[tid] = live ? Gd : 0.0;
-    if (WITH_H) cg[HK_TILE + tid] = live ? Hd : 0.0;
+    double *cg = colG + (int64_t)blockIdx.x * 2 * HK_WAVE;
+    cg[lane] = live ? Gd : 0.0;
+    if (WITH_H) cg[HK_WAVE + lane] = live ? Hd : 0.0;
 }
 
-__global__ void k_sub_colfin(const int *__restrict__ item0, const int *__restrict__ nseg,
-                             const double *__restrict__ colG, const double *__restrict__ a, int64_t m,
-                             const FinConst fc, bool with_h, double *__restrict__ gsub, double *__restrict__ hsub) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= m) return;
-    const int T = (int)(r / HK_TILE), lr = (int)(r % HK_TILE);
+// Per 64-entry subset chunk: the SUB_FIN_WAVES wavefronts split the chunk's
+// items round robin, then the first combines them in a fixed order.
+__global__ __launch_bounds__(SUB_FIN_WAVES * HK_WAVE) void k_sub_colfin(
+    const int *__restrict__ item0, const int *__restrict__ nseg, const double *__restrict__ colG,
+    const double *__restrict__ a, int64_t m, const FinConst fc, bool with_h, double *__restrict__ gsub,
+    double *__restrict__ hsub) {
+    __shared__ double part[SUB_FIN_WAVES][2][HK_WAVE];
+    const int q = blockIdx.x, lane = threadIdx.x & (HK_WAVE - 1), wq = threadIdx.x / HK_WAVE;
     double G = 0.0, H = 0.0;
-    for (int sg = 0; sg < nseg[T]; ++sg) {
-        const double *cg = colG + (int64_t)(item0[T] + sg) * 2 * HK_TILE + lr;
+    const int ns = nseg[q], i0 = item0[q];
+#pragma unroll 4
+    for (int sg = wq; sg < ns; sg += SUB_FIN_WAVES) {
+        const double *cg = colG + (int64_t)(i0 + sg) * 2 * HK_WAVE + lane;
         G += cg[0];
-        if (with_h) H += cg[HK_TILE];
+        if (with_h) H += cg[HK_WAVE];
     }
-    gsub[r] = G * fc.corr - a[r];
-    if (with_h) hsub[r] = H * fc.corr * fc.corr;
+    part[wq][0][lane] = G;
+    part[wq][1][lane] = H;
+    __syncthreads();
+    const int64_t r = (int64_t)q * HK_WAVE + lane;
+    if (wq != 0 || r >= m) return;
+    double Gs = part[0][0][lane], Hs = part[0][1][lane];
+    for (int k = 1; k < SUB_FIN_WAVES; ++k) {
+        Gs += part[k][0][lane];
+        Hs += part[k][1][lane];
+    }
+    gsub[r] = Gs * fc.corr - a[r];
+    if (with_h) hsub[r] = Hs * fc.corr * fc.corr;
 }
 
 // Scatter the subset results to the caller's slot order.
@@ -600,8 +629,8 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 void hk_subset_free(hawkes_plan p) {
     hk_subset *s = p->sub;
     if (!s) return;
-    void *ptrs[] = {s->pos, s->slot, s->cidx, s->cnt, s->items, s->item0, s->nseg, s->lam_static, s->Lam_static,
-                    s->a, s->theta32, s->xs, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->off, s->vz, s->scal,
+    void *ptrs[] = {s->pos, s->slot, s->cidx, s->ritems, s->ritem0, s->rnseg, s->xpart, s->items, s->item0, s->nseg,
+                    s->lam_static, s->Lam_static, s->a, s->theta32, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->off, s->vz, s->scal,
                     s->grid};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -643,12 +672,9 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     SC(dalloc(&s->pos, s->mpad));
     SC(dalloc(&s->slot, s->mpad));
     SC(dalloc(&s->cidx, m));
-    SC(dalloc(&s->cnt, p->nchunks));
     hipLaunchKernelGGL(k_sub_layout, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, key, slot2, m, s->mpad, s->pos,
                        s->slot, bad);
     SC(hipMemcpyAsync(s->cidx, d_idx, sizeof(int64_t) * m, hipMemcpyDeviceToDevice, stream));
-    hipLaunchKernelGGL(k_sub_count, dim3(nblk(p->nchunks, 256)), dim3(256), 0, stream, s->pos, m, p->nchunks,
-                       s->cnt);
     SC(hipGetLastError());
     std::vector<int> hpos(m);
     int hbad = 0;
@@ -663,32 +689,67 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
         hk_subset_free(p);
         return HAWKES_E_INVALID;
     }
-    // column pass schedule: subset tile T sweeps row chunks from the chunk of its
-    // earliest entry to the end, in segments of S chunks
-    s->ntiles = (int)(s->mpad / HK_TILE);
-    const int S = 16;
-    std::vector<hk_item> items;
-    std::vector<int> item0(s->ntiles), nseg(s->ntiles);
-    for (int T = 0; T < s->ntiles; ++T) {
-        const int first = hpos[(size_t)T * HK_TILE] / HK_WAVE;
-        item0[T] = (int)items.size();
-        int seg = 0;
-        for (int c = first; c < p->nchunks; c += S) items.push_back({T, c, std::min(c + S, p->nchunks), seg++});
-        nseg[T] = seg;
+    // row pass schedule: row chunk b pairs with the subset entries before its end
+    // (cnt_b of them, a prefix in time order), in items of at most BR entries
+    const int nch = p->nchunks;
+    std::vector<int> cnt(nch);
+    {
+        int64_t r = 0;
+        for (int b = 0; b < nch; ++b) {
+            while (r < m && hpos[(size_t)r] < HK_WAVE * (b + 1)) ++r;
+            cnt[b] = (int)r;
+        }
     }
+    int64_t wrow = 0;
+    for (int b = 0; b < nch; ++b) wrow += cnt[b];
+    const int64_t br = std::max<int64_t>(1, (wrow + SUB_ROW_ITEMS * HK_WAVE - 1) / (SUB_ROW_ITEMS * HK_WAVE)) * HK_WAVE;
+    std::vector<hk_item> ritems;
+    std::vector<int> ritem0(nch), rnseg(nch);
+    for (int b = 0; b < nch; ++b) {
+        ritem0[b] = (int)ritems.size();
+        int seg = 0;
+        for (int64_t e = 0; e < cnt[b]; e += br)
+            ritems.push_back({b, (int)e, (int)std::min<int64_t>(e + br, cnt[b]), seg++});
+        rnseg[b] = seg;
+    }
+    // column pass schedule: subset chunk q sweeps the row chunks from the chunk of
+    // its earliest entry to the end, in items of sc chunks
+    s->nq = (int)(s->mpad / HK_WAVE);
+    const int nq_live = (int)((m + HK_WAVE - 1) / HK_WAVE);
+    int64_t wcol = 0;
+    for (int q = 0; q < nq_live; ++q) wcol += nch - hpos[(size_t)q * HK_WAVE] / HK_WAVE;
+    const int sc = (int)std::max<int64_t>(1, (wcol + SUB_COL_ITEMS - 1) / SUB_COL_ITEMS);
+    std::vector<hk_item> items;
+    std::vector<int> item0(s->nq, 0), nseg(s->nq, 0);
+    for (int q = 0; q < nq_live; ++q) {
+        const int first = hpos[(size_t)q * HK_WAVE] / HK_WAVE;
+        item0[q] = (int)items.size();
+        int seg = 0;
+        for (int c = first; c < nch; c += sc) items.push_back({q, c, std::min(c + sc, nch), seg++});
+        nseg[q] = seg;
+    }
+    for (int q = nq_live; q < s->nq; ++q) item0[q] = (int)items.size();
+    s->n_ritems = (int)ritems.size();
     s->n_items = (int)items.size();
+    SC(dalloc(&s->ritems, std::max<size_t>(1, ritems.size())));
+    SC(dalloc(&s->ritem0, nch));
+    SC(dalloc(&s->rnseg, nch));
+    SC(dalloc(&s->xpart, (size_t)std::max(1, s->n_ritems) * HK_WAVE));
+    if (!ritems.empty())
+        SC(hipMemcpy(s->ritems, ritems.data(), sizeof(hk_item) * ritems.size(), hipMemcpyHostToDevice));
+    SC(hipMemcpy(s->ritem0, ritem0.data(), sizeof(int) * nch, hipMemcpyHostToDevice));
+    SC(hipMemcpy(s->rnseg, rnseg.data(), sizeof(int) * nch, hipMemcpyHostToDevice));
     SC(dalloc(&s->items, items.size()));
-    SC(dalloc(&s->item0, s->ntiles));
-    SC(dalloc(&s->nseg, s->ntiles));
+    SC(dalloc(&s->item0, s->nq));
+    SC(dalloc(&s->nseg, s->nq));
     SC(hipMemcpy(s->items, items.data(), sizeof(hk_item) * items.size(), hipMemcpyHostToDevice));
-    SC(hipMemcpy(s->item0, item0.data(), sizeof(int) * s->ntiles, hipMemcpyHostToDevice));
-    SC(hipMemcpy(s->nseg, nseg.data(), sizeof(int) * s->ntiles, hipMemcpyHostToDevice));
+    SC(hipMemcpy(s->item0, item0.data(), sizeof(int) * s->nq, hipMemcpyHostToDevice));
+    SC(hipMemcpy(s->nseg, nseg.data(), sizeof(int) * s->nq, hipMemcpyHostToDevice));
     SC(dalloc(&s->lam_static, p->npad));
     SC(dalloc(&s->Lam_static, 1));
     SC(dalloc(&s->a, s->mpad));
     SC(dalloc(&s->theta32, s->mpad));
-    SC(dalloc(&s->xs, p->npad));
-    SC(dalloc(&s->colG, (size_t)s->n_items * 2 * HK_TILE));
+    SC(dalloc(&s->colG, (size_t)s->n_items * 2 * HK_WAVE));
     SC(dalloc(&s->gsub, s->mpad));
     SC(dalloc(&s->hsub, s->mpad));
     SC(dalloc(&s->sums, 8));
@@ -741,18 +802,19 @@ void sub_eval(hawkes_plan p, const double *z, const double *off, double *theta_f
     p->epoch += 1;  // p->lam and p->w are overwritten below
     hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, off, s->slot, s->cidx, s->m,
                        s->mpad, s->theta32, theta_full);
-    hipLaunchKernelGGL(k_sub_row, dim3(p->nchunks), dim3(SUB_ROW_THREADS), 0, stream, p->ts, p->xi, p->yi, p->g,
-                       s->pos, s->theta32, s->cnt, kc, s->xs);
-    hipLaunchKernelGGL(k_sub_fin, dim3(p->nfin_blocks), dim3(256), 0, stream, s->lam_static, s->xs, p->n,
-                       p->npad, fc,
+    hipLaunchKernelGGL(k_sub_row, dim3(s->n_ritems), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->g, s->pos,
+                       s->theta32, s->ritems, kc, s->xpart);
+    hipLaunchKernelGGL(k_sub_fin, dim3(p->nfin_blocks), dim3(256), 0, stream, s->lam_static, s->ritem0, s->rnseg,
+                       s->xpart, p->n, p->npad, fc,
                        p->lam, p->w, p->wlo, p->blockpart, p->status);
     if (with_h)
-        hipLaunchKernelGGL(k_sub_col<true>, dim3(s->n_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->w,
+        hipLaunchKernelGGL(k_sub_col<true>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->w,
                            p->wlo, p->g, s->pos, s->m, s->items, kc, s->colG);
     else
-        hipLaunchKernelGGL(k_sub_col<false>, dim3(s->n_items), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->w,
+        hipLaunchKernelGGL(k_sub_col<false>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->w,
                            p->wlo, p->g, s->pos, s->m, s->items, kc, s->colG);
-    hipLaunchKernelGGL(k_sub_colfin, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->item0, s->nseg, s->colG, s->a,
+    hipLaunchKernelGGL(k_sub_colfin, dim3(s->nq), dim3(SUB_FIN_WAVES * HK_WAVE), 0, stream, s->item0, s->nseg,
+                       s->colG, s->a,
                        s->m, fc, with_h, s->gsub, s->hsub);
 }
 
