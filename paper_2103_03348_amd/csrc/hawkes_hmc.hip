@@ -58,7 +58,7 @@ struct hk_subset {
     double *hsub;        // [mpad] Eq. 5 on the subset, time order
     double *sums;        // [8] loglik pieces of the last evaluation
     // HMC state
-    double *z0, *p, *gz; // [m] slot order
+    double *z0, *p;      // [m] slot order
     double *off;         // [m] temporal-trend offsets beta t_k, slot order
     double *vz;          // [m] V^{-1} z of the phylogenetic prior, slot order
     double *scal;        // [16] energies and flags
@@ -448,12 +448,30 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
     if (WITH_H) cg[HK_WAVE + lane] = live ? Hd : 0.0;
 }
 
+// A leapfrog update fused into the column finalisation: with g = Eq. 4 at the
+// current z, the log-posterior gradient in z is theta g - P z / sigma^2 (P the
+// prior precision direction, pv = z or V^{-1} z), then p += a_p grad and, when
+// a_z != 0, z += a_z p / M and the subset rates for the next evaluation.
+struct SubUpd {
+    const int *slot;
+    double *z;
+    const double *off;
+    const double *pv;
+    double inv_s2;
+    double *p;
+    const double *mass;
+    double a_p, a_z;
+    float *theta32;
+};
+
 // Per 64-entry subset chunk: the SUB_FIN_WAVES wavefronts split the chunk's
-// items round robin, then the first combines them in a fixed order.
+// items round robin, then the first combines them in a fixed order (and, with
+// UPD, applies the leapfrog update to its entries).
+template <bool UPD>
 __global__ __launch_bounds__(SUB_FIN_WAVES * HK_WAVE) void k_sub_colfin(
     const int *__restrict__ item0, const int *__restrict__ nseg, const double *__restrict__ colG,
     const double *__restrict__ a, int64_t m, const FinConst fc, bool with_h, double *__restrict__ gsub,
-    double *__restrict__ hsub) {
+    double *__restrict__ hsub, const SubUpd u) {
     __shared__ double part[SUB_FIN_WAVES][2][HK_WAVE];
     const int q = blockIdx.x, lane = threadIdx.x & (HK_WAVE - 1), wq = threadIdx.x / HK_WAVE;
     double G = 0.0, H = 0.0;
@@ -474,8 +492,21 @@ __global__ __launch_bounds__(SUB_FIN_WAVES * HK_WAVE) void k_sub_colfin(
         Gs += part[k][0][lane];
         Hs += part[k][1][lane];
     }
-    gsub[r] = Gs * fc.corr - a[r];
+    const double g = Gs * fc.corr - a[r];
+    gsub[r] = g;
     if (with_h) hsub[r] = Hs * fc.corr * fc.corr;
+    if (UPD) {
+        const int k = u.slot[r];
+        const double zk = u.z[k];
+        const double gz = exp(u.off ? zk + u.off[k] : zk) * g - u.pv[k] * u.inv_s2;
+        const double pk = u.p[k] + u.a_p * gz;
+        u.p[k] = pk;
+        if (u.a_z != 0.0) {
+            const double zn = zk + u.a_z * pk / u.mass[k];
+            u.z[k] = zn;
+            u.theta32[r] = (float)exp(u.off ? zn + u.off[k] : zn);
+        }
+    }
 }
 
 // Scatter the subset results to the caller's slot order.
@@ -554,27 +585,6 @@ __global__ void k_hmc_init(int64_t m, uint64_t seed, uint64_t counter, const dou
     z0[k] = z[k];
 }
 
-// grad_z log pi = theta_k g_k - z_k / sigma^2 in slot order
-// prior term: pv = z for the iid prior, V^{-1} z for the phylogenetic one
-__global__ void k_hmc_gradz(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
-                            const double *__restrict__ z, const double *__restrict__ off,
-                            const double *__restrict__ pv, double inv_s2, double *__restrict__ gz) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= m) return;
-    const int k = slot[r];
-    gz[k] = exp(zeff(z, off, k)) * gsub[r] - pv[k] * inv_s2;
-}
-
-// p += a_p * grad; then (if a_z != 0) z += a_z * p / M
-__global__ void k_hmc_kick_drift(int64_t m, double a_p, const double *__restrict__ gz, double a_z,
-                                 const double *__restrict__ mass, double *__restrict__ p, double *__restrict__ z) {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    double pk = p[k] + a_p * gz[k];
-    p[k] = pk;
-    if (a_z != 0.0) z[k] = z[k] + a_z * pk / mass[k];
-}
-
 // Energies: scal[0..3] start sums, scal[4..7] end sums (k_sub_energy layout).
 // H = -(sum log lambda - Lam_static - theta0-part) + sum z^2/(2 s^2) + sum p^2/(2M)
 __global__ void k_hmc_accept(const double *__restrict__ scal, const double *__restrict__ Lam_static,
@@ -630,7 +640,7 @@ void hk_subset_free(hawkes_plan p) {
     hk_subset *s = p->sub;
     if (!s) return;
     void *ptrs[] = {s->pos, s->slot, s->cidx, s->ritems, s->ritem0, s->rnseg, s->xpart, s->items, s->item0, s->nseg,
-                    s->lam_static, s->Lam_static, s->a, s->theta32, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->gz, s->off, s->vz, s->scal,
+                    s->lam_static, s->Lam_static, s->a, s->theta32, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->off, s->vz, s->scal,
                     s->grid};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -755,7 +765,6 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     SC(dalloc(&s->sums, 8));
     SC(dalloc(&s->z0, m));
     SC(dalloc(&s->p, m));
-    SC(dalloc(&s->gz, m));
     SC(dalloc(&s->off, m));
     SC(dalloc(&s->vz, m));
     SC(dalloc(&s->scal, 16));
@@ -794,28 +803,46 @@ hawkes_status ensure_static(hawkes_plan p, const hawkes_hyper *hy, const double 
     return HAWKES_OK;
 }
 
-// One subset evaluation at z (slot order): theta, lambda, w, Eq. 4 (and Eq. 5)
-// on the subset, block partial sums of log lambda in p->blockpart.
-void sub_eval(hawkes_plan p, const double *z, const double *off, double *theta_full, bool with_h,
-              const PairConst &kc, const FinConst &fc, hipStream_t stream) {
+// The row half of a subset evaluation at z (slot order): (theta,) lambda, w and
+// the block partial sums of log lambda in p->blockpart.
+static void sub_rows(hawkes_plan p, const double *z, const double *off, double *theta_full, bool with_theta,
+                     const PairConst &kc, const FinConst &fc, hipStream_t stream) {
     hk_subset *s = p->sub;
     p->epoch += 1;  // p->lam and p->w are overwritten below
-    hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, off, s->slot, s->cidx, s->m,
-                       s->mpad, s->theta32, theta_full);
+    if (with_theta)
+        hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, off, s->slot, s->cidx,
+                           s->m, s->mpad, s->theta32, theta_full);
     hipLaunchKernelGGL(k_sub_row, dim3(s->n_ritems), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->g, s->pos,
                        s->theta32, s->ritems, kc, s->xpart);
     hipLaunchKernelGGL(k_sub_fin, dim3(p->nfin_blocks), dim3(256), 0, stream, s->lam_static, s->ritem0, s->rnseg,
-                       s->xpart, p->n, p->npad, fc,
-                       p->lam, p->w, p->wlo, p->blockpart, p->status);
+                       s->xpart, p->n, p->npad, fc, p->lam, p->w, p->wlo, p->blockpart, p->status);
+}
+
+// The column half: Eq. 4 (and Eq. 5) on the subset, optionally with the fused
+// leapfrog update.
+static void sub_cols(hawkes_plan p, bool with_h, const PairConst &kc, const FinConst &fc, const SubUpd *upd,
+                     hipStream_t stream) {
+    hk_subset *s = p->sub;
     if (with_h)
         hipLaunchKernelGGL(k_sub_col<true>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->w,
                            p->wlo, p->g, s->pos, s->m, s->items, kc, s->colG);
     else
         hipLaunchKernelGGL(k_sub_col<false>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->w,
                            p->wlo, p->g, s->pos, s->m, s->items, kc, s->colG);
-    hipLaunchKernelGGL(k_sub_colfin, dim3(s->nq), dim3(SUB_FIN_WAVES * HK_WAVE), 0, stream, s->item0, s->nseg,
-                       s->colG, s->a,
-                       s->m, fc, with_h, s->gsub, s->hsub);
+    if (upd)
+        hipLaunchKernelGGL(k_sub_colfin<true>, dim3(s->nq), dim3(SUB_FIN_WAVES * HK_WAVE), 0, stream, s->item0,
+                           s->nseg, s->colG, s->a, s->m, fc, with_h, s->gsub, s->hsub, *upd);
+    else
+        hipLaunchKernelGGL(k_sub_colfin<false>, dim3(s->nq), dim3(SUB_FIN_WAVES * HK_WAVE), 0, stream, s->item0,
+                           s->nseg, s->colG, s->a, s->m, fc, with_h, s->gsub, s->hsub, SubUpd{});
+}
+
+// One subset evaluation at z (slot order): theta, lambda, w, Eq. 4 (and Eq. 5)
+// on the subset, block partial sums of log lambda in p->blockpart.
+void sub_eval(hawkes_plan p, const double *z, const double *off, double *theta_full, bool with_h,
+              const PairConst &kc, const FinConst &fc, hipStream_t stream) {
+    sub_rows(p, z, off, theta_full, true, kc, fc, stream);
+    sub_cols(p, with_h, kc, fc, nullptr, stream);
 }
 
 __global__ void k_z_from_theta(const double *__restrict__ theta, const int64_t *__restrict__ cidx, int64_t m,
@@ -910,25 +937,25 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
     }
     hipLaunchKernelGGL(k_hmc_init, dim3(gb), dim3(256), 0, stream, m, a->seed, a->counter, a->d_mass, a->d_z, s->p,
                        s->z0);
-    // start of the trajectory
-    sub_eval(p, a->d_z, off, a->d_theta, false, kc, fc, stream);
+    // start of the trajectory: the energy at z0, then the gradient there and the
+    // first half kick and drift (fused into the column finalisation)
+    sub_rows(p, a->d_z, off, a->d_theta, true, kc, fc, stream);
     hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal);
     // phylogenetic prior: the quadratic form z^T V^{-1} z replaces sum z^2
     if (tree && (st = hk_tree_launch(p, a->d_z, s->vz, s->scal + 2, stream)) != HAWKES_OK) return st;
-    hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, off, pv, inv_s2,
-                       s->gz);
+    SubUpd upd{s->slot, a->d_z, off, pv, inv_s2, s->p, a->d_mass, 0.5 * a->eps, a->eps, s->theta32};
+    sub_cols(p, false, kc, fc, &upd, stream);
     for (int l = 0; l < a->L; ++l) {
-        // half kick at the start, full kicks between drifts
-        hipLaunchKernelGGL(k_hmc_kick_drift, dim3(gb), dim3(256), 0, stream, m, l == 0 ? 0.5 * a->eps : a->eps,
-                           s->gz, a->eps, a->d_mass, s->p, a->d_z);
-        sub_eval(p, a->d_z, off, a->d_theta, false, kc, fc, stream);
+        // evaluation at the drifted position, then a full kick and drift, or the
+        // closing half kick after the last one
+        sub_rows(p, a->d_z, off, a->d_theta, false, kc, fc, stream);
         if (tree && (st = hk_tree_launch(p, a->d_z, s->vz, nullptr, stream)) != HAWKES_OK) return st;
-        hipLaunchKernelGGL(k_hmc_gradz, dim3(gb), dim3(256), 0, stream, s->slot, m, s->gsub, a->d_z, off, pv,
-                           inv_s2, s->gz);
+        const bool last = l == a->L - 1;
+        upd.a_p = last ? 0.5 * a->eps : a->eps;
+        upd.a_z = last ? 0.0 : a->eps;
+        sub_cols(p, false, kc, fc, &upd, stream);
     }
-    hipLaunchKernelGGL(k_hmc_kick_drift, dim3(gb), dim3(256), 0, stream, m, 0.5 * a->eps, s->gz, 0.0, a->d_mass,
-                       s->p, a->d_z);
     hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal + 4);
     if (tree && (st = hk_tree_launch(p, a->d_z, nullptr, s->scal + 6, stream)) != HAWKES_OK) return st;
