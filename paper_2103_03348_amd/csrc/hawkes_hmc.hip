@@ -80,7 +80,10 @@ namespace {
 #endif
 constexpr int64_t SUB_ROW_ITEMS = HK_SUB_ROW_ITEMS;
 constexpr int64_t SUB_COL_ITEMS = HK_SUB_COL_ITEMS;
-constexpr int SUB_FIN_WAVES = 8;
+#ifndef HK_SUB_FIN_WAVES
+#define HK_SUB_FIN_WAVES 16
+#endif
+constexpr int SUB_FIN_WAVES = HK_SUB_FIN_WAVES;
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -332,13 +335,14 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
     xpart[(int64_t)blockIdx.x * HK_WAVE + lane] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_static,
+// One wavefront per 64-row chunk (many blocks in flight for the partial-sum
+// reads); the chunk's sum of log lambda goes to blockpart[chunk].
+__global__ __launch_bounds__(HK_WAVE) void k_sub_fin(const double *__restrict__ lam_static,
                                                  const int *__restrict__ ritem0, const int *__restrict__ rnseg,
                                                  const double *__restrict__ xpart, int64_t n, int64_t npad,
                                                  const FinConst fc,
                                                  double *__restrict__ lam, float *__restrict__ w, float *__restrict__ wlo,
                                                  double *__restrict__ blockpart, int *__restrict__ status) {
-    __shared__ double sh[HK_WAVES];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double v = 0.0;
     if (i < n) {
@@ -362,9 +366,7 @@ __global__ __launch_bounds__(256) void k_sub_fin(const double *__restrict__ lam_
         wlo[i] = 0.0f;
     }
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) blockpart[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    if (threadIdx.x == 0) blockpart[blockIdx.x] = v;
 }
 
 // Column pass on the subset: lanes own subset entries (time order), rows are
@@ -814,7 +816,7 @@ static void sub_rows(hawkes_plan p, const double *z, const double *off, double *
                            s->m, s->mpad, s->theta32, theta_full);
     hipLaunchKernelGGL(k_sub_row, dim3(s->n_ritems), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->g, s->pos,
                        s->theta32, s->ritems, kc, s->xpart);
-    hipLaunchKernelGGL(k_sub_fin, dim3(p->nfin_blocks), dim3(256), 0, stream, s->lam_static, s->ritem0, s->rnseg,
+    hipLaunchKernelGGL(k_sub_fin, dim3(p->nchunks), dim3(HK_WAVE), 0, stream, s->lam_static, s->ritem0, s->rnseg,
                        s->xpart, p->n, p->npad, fc, p->lam, p->w, p->wlo, p->blockpart, p->status);
 }
 
@@ -900,7 +902,7 @@ extern "C" hawkes_status hawkes_subset_grad(hawkes_plan p, const hawkes_hyper *h
     hipLaunchKernelGGL(k_sub_scatter, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->slot, s->m, s->gsub, s->hsub,
                        d_grad_sub, d_negH_sub);
     if (d_loglik) {
-        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, s->z0,
+        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nchunks, s->z0,
                            (const double *)nullptr, (const double *)nullptr, (const double *)nullptr, s->slot, s->a,
                            s->m, s->scal);
         hipLaunchKernelGGL(k_sub_loglik_out, dim3(1), dim3(64), 0, stream, s->scal, s->Lam_static, d_loglik);
@@ -940,7 +942,7 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
     // start of the trajectory: the energy at z0, then the gradient there and the
     // first half kick and drift (fused into the column finalisation)
     sub_rows(p, a->d_z, off, a->d_theta, true, kc, fc, stream);
-    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, off, s->p,
+    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nchunks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal);
     // phylogenetic prior: the quadratic form z^T V^{-1} z replaces sum z^2
     if (tree && (st = hk_tree_launch(p, a->d_z, s->vz, s->scal + 2, stream)) != HAWKES_OK) return st;
@@ -956,7 +958,7 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
         upd.a_z = last ? 0.0 : a->eps;
         sub_cols(p, false, kc, fc, &upd, stream);
     }
-    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, a->d_z, off, s->p,
+    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nchunks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal + 4);
     if (tree && (st = hk_tree_launch(p, a->d_z, nullptr, s->scal + 6, stream)) != HAWKES_OK) return st;
     hipLaunchKernelGGL(k_hmc_accept, dim3(1), dim3(256), 0, stream, s->scal, s->Lam_static, inv_s2, a->seed,
@@ -989,7 +991,7 @@ extern "C" hawkes_status hawkes_subset_trend_grad(hawkes_plan p, const hawkes_hy
         hipLaunchKernelGGL(k_sub_trend_out, dim3(1), dim3(256), 0, stream, s->slot, s->pos, p->ts, s->m, s->gsub, d_z,
                            off, d_grad_z, d_grad_beta);
     if (d_loglik) {
-        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nfin_blocks, d_z, off,
+        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nchunks, d_z, off,
                            (const double *)nullptr, (const double *)nullptr, s->slot, s->a, s->m, s->scal);
         hipLaunchKernelGGL(k_sub_loglik_out, dim3(1), dim3(64), 0, stream, s->scal, s->Lam_static, d_loglik);
     }
