@@ -70,8 +70,10 @@ struct hk_subset {
 namespace {
 
 // The subset passes are split into many one-wavefront items (about this many
-// each) so that the whole chip takes part; partial sums per item are combined
-// in a fixed order afterwards.
+// each, and at most SUB_ITEM_BATCHES 64-wide batches per item, so that the
+// few items that still have work under the underflow cutoff stay short) so
+// that the whole chip takes part; partial sums per item are combined in a
+// fixed order afterwards.
 #ifndef HK_SUB_ROW_ITEMS
 #define HK_SUB_ROW_ITEMS 8192
 #endif
@@ -84,6 +86,7 @@ constexpr int64_t SUB_COL_ITEMS = HK_SUB_COL_ITEMS;
 #define HK_SUB_FIN_WAVES 16
 #endif
 constexpr int SUB_FIN_WAVES = HK_SUB_FIN_WAVES;
+constexpr int64_t SUB_ITEM_BATCHES = 16;
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -714,7 +717,9 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     }
     int64_t wrow = 0;
     for (int b = 0; b < nch; ++b) wrow += cnt[b];
-    const int64_t br = std::max<int64_t>(1, (wrow + SUB_ROW_ITEMS * HK_WAVE - 1) / (SUB_ROW_ITEMS * HK_WAVE)) * HK_WAVE;
+    const int64_t br = std::min<int64_t>(SUB_ITEM_BATCHES, std::max<int64_t>(1, (wrow + SUB_ROW_ITEMS * HK_WAVE - 1) /
+                                                                                   (SUB_ROW_ITEMS * HK_WAVE))) *
+                       HK_WAVE;
     std::vector<hk_item> ritems;
     std::vector<int> ritem0(nch), rnseg(nch);
     for (int b = 0; b < nch; ++b) {
@@ -730,7 +735,8 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     const int nq_live = (int)((m + HK_WAVE - 1) / HK_WAVE);
     int64_t wcol = 0;
     for (int q = 0; q < nq_live; ++q) wcol += nch - hpos[(size_t)q * HK_WAVE] / HK_WAVE;
-    const int sc = (int)std::max<int64_t>(1, (wcol + SUB_COL_ITEMS - 1) / SUB_COL_ITEMS);
+    const int sc = (int)std::min<int64_t>(SUB_ITEM_BATCHES,
+                                          std::max<int64_t>(1, (wcol + SUB_COL_ITEMS - 1) / SUB_COL_ITEMS));
     std::vector<hk_item> items;
     std::vector<int> item0(s->nq, 0), nseg(s->nq, 0);
     for (int q = 0; q < nq_live; ++q) {
