@@ -44,14 +44,14 @@ PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # HBM traffic of one k_row launch at N = 23,422, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a device-to-device copy of known size (summary and
-# commands in profiles/k_row_k_col_N23422_counters.md): 5.7 MB read + 64.7 MB
+# commands in profiles/k_row_k_col_N23422_counters.md): 5.9 MB read + 64.7 MB
 # written.  It holds only for the kernel sources it was measured on, so it is
 # reported only while their hashes match.
-K_ROW_TRAFFIC_BYTES = (2785.4375 * 2.0 + 63220.0 * 1.0) * 1024
+K_ROW_TRAFFIC_BYTES = (2888.6 * 2.0 + 63220.0 * 1.0) * 1024
 K_ROW_TRAFFIC_SOURCES = {
-    "paper_2103_03348_amd/csrc/hawkes_eval.hip": "ef2d723cbad81c2a047decda5b1cc69fab0ec953019971dd5f7c498c9dc7e9ab",
-    "paper_2103_03348_amd/csrc/hawkes_internal.h": "b066e375ca0fc397ce3a61c740c56e4fe75a8bdd95087b693c8102053deea3ec",
-    "paper_2103_03348_amd/csrc/hawkes_plan.hip": "0208d7a9d4e83b6b866ab7c7bdab277e8cfbac6d97f6dd6358b782f8d07b32d5",
+    "paper_2103_03348_amd/csrc/hawkes_eval.hip": "790d20c48b24235990a4f574ecc01823693ca6687128aac22b48c4dd17f90694",
+    "paper_2103_03348_amd/csrc/hawkes_internal.h": "87941fd2565bde9c31e173b9e269086fb2a2c9a2b97a02768144f89f590d465e",
+    "paper_2103_03348_amd/csrc/hawkes_plan.hip": "d09328f4ad5bc41692f117f65d65eb772d159051bc3ad97ba456a2be80497745",
 }
 
 
@@ -88,7 +88,7 @@ def cpu_baseline(es, budget_s=12.0):
                       f"derivatives) of the N={n} workload, {el:.1f} s"}
 
 
-def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_states=200, seed=7, n_chains=4):
+def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_states=200, seed=7, n_chains=8):
     """HMC ESS/s on the free log-rates with the exact and the learned diagonal
     preconditioner (and, for reference, none), each chain adapting its step size
     by dual averaging during its own warm-up, then `n_iter` timed iterations;
@@ -157,10 +157,36 @@ def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_
         agg["chains"] = runs
         out[mode] = agg
     out["learned_over_exact"] = {k: out["learned"][k] / out["exact"][k] for k in ("ess_per_s_min", "ess_per_s_median")}
+    # paired by seed (the chains of both modes draw the same random numbers)
+    for k in ("ess_per_s_min", "ess_per_s_median"):
+        rr = np.array([a[k] / b[k] for a, b in zip(out["learned"]["chains"], out["exact"]["chains"])])
+        out["learned_over_exact"][k + "_paired_mean"] = float(rr.mean())
+        out["learned_over_exact"][k + "_paired_sem"] = float(rr.std(ddof=1) / np.sqrt(len(rr))) if len(rr) > 1 else None
     out["config"] = {"n_events": es.n, "free_rates": int(es.subset.shape[0]), "leapfrog": L, "iterations": n_iter,
                      "warmup": warmup, "mass_refresh": refresh, "exact_refresh_in_learned": exact_every,
                      "chains_per_mode": n_chains}
     return out
+
+
+def hmc_trace(es, iters, L=20, seed=3):
+    """K exact-mass HMC iterations (after 5 warm-up ones) on the free rates of
+    `es`: the time per iteration, for a kernel-trace profile of hmc_step."""
+    import numpy as np
+    import torch
+
+    from paper_2103_03348_amd.hawkes import Plan
+    from paper_2103_03348_amd.sampler import HmcSampler
+
+    dev = torch.device("cuda:0")
+    t = torch.as_tensor(es.t, device=dev)
+    xy = torch.as_tensor(np.stack([es.x, es.y], 1), device=dev).contiguous()
+    plan = Plan(t, xy, es.t0)
+    smp = HmcSampler(plan, torch.as_tensor(es.theta, device=dev), torch.as_tensor(es.subset, device=dev), es.hyper,
+                     sigma_z=0.5, L=L, seed=seed)
+    r = smp.run(iters, 5, eps0=0.2, mass="exact", refresh=50)
+    plan.close()
+    return {"hmc_trace": {"n_events": es.n, "free_rates": int(es.subset.shape[0]), "leapfrog": L, "iterations": iters,
+                          "ms_per_iteration": 1e3 * r["seconds"] / iters, "accept": r["accept"]}}
 
 
 def bench_hmc_large(es, iters=10, L=20, learned_every=50, exact_every=500, seed=11):
@@ -273,6 +299,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (HBM counter calibration)")
     ap.add_argument("--hmc-iters", type=int, default=2000)
+    ap.add_argument("--hmc-trace", type=int, default=0, metavar="K",
+                    help="only run K exact-mass HMC iterations on the N=23,422 workload (for a kernel trace)")
     ap.add_argument("--no-larger", action="store_true", help="skip the N=100,000 and 250,000 evaluations")
     ap.add_argument("--no-hmc-large", action="store_true",
                     help="skip the HMC iteration timing on the N=250,000 workload")
@@ -293,9 +321,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_per_launch": {"read": src.numel() * 4, "write": dst.numel() * 4}}))
         return
-
     from paper_2103_03348_amd import _lib, synth
     from paper_2103_03348_amd.hawkes import Plan
+
+    if args.hmc_trace > 0:
+        print(json.dumps(hmc_trace(synth.config(3), args.hmc_trace)))
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
