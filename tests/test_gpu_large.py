@@ -46,6 +46,48 @@ def test_n100k_parity(gpu, n100k):
     assert np.all(e["Hh_abs"] / np.maximum(np.abs(ref["negH_hyper"]), es.n / hy ** 2) < 1e-6)
 
 
+def test_subset_path_n100k(gpu, n100k):
+    """The O(N M) free-rate path at N = 100,000 (6,874 free rates): here its
+    schedules split the subset passes into multi-batch items (column items of
+    the maximum 16 row chunks, row items of several 64-entry batches); Eq. 1,
+    4 and 5 on the subset against the oracle's full evaluation."""
+    import ctypes
+
+    import torch
+
+    from paper_2103_03348_amd import _lib
+    from paper_2103_03348_amd.hawkes import Plan
+
+    es, ref = n100k
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
+    idx = torch.as_tensor(es.subset, dtype=torch.int64, device="cuda:0")
+    _lib.check(_lib.lib().hawkes_plan_set_subset(plan.handle, idx.numel(), _lib.ptr(idx), _lib.stream_handle()),
+               "set_subset")
+    m = es.subset.shape[0]
+    th = torch.as_tensor(es.theta, device="cuda:0")
+    ll = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    g = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+    h = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+    hy = _lib.Hyper.of(es.hyper)
+    _lib.check(_lib.lib().hawkes_subset_grad(plan.handle, ctypes.byref(hy), _lib.ptr(th), 0, _lib.ptr(ll),
+                                             _lib.ptr(g), _lib.ptr(h), _lib.stream_handle()), "subset_grad")
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    g, h = g.cpu().numpy(), h.cpu().numpy()
+    gi = ref["grad_theta"][es.subset]
+    hi = ref["negH_theta"][es.subset]
+    a = es.hyper[3] * (1.0 - np.exp(-es.hyper[4] * (es.t.max() - es.t[es.subset])))
+    rel_l = abs(float(ll.item()) - ref["loglik"]) / abs(ref["loglik"])
+    rel_g = np.max(np.abs(g - gi) / np.maximum(gi + 2 * a, 1e-300))
+    sig = hi >= 1e-4 * hi.max()
+    rel_h = np.max(np.abs(h - hi)[sig] / hi[sig])
+    print(f"\n[subset N=100,000 m={m}] loglik {rel_l:.2e} g {rel_g:.2e} H {rel_h:.2e}", flush=True)
+    assert rel_l < 1e-9
+    assert rel_g < 1e-6
+    assert rel_h < 1e-6
+    plan.close()
+
+
 def _fd_rate(es, lam, m, step=1e-6):
     """Central difference of f(s) above at s = theta_m, term by term."""
     mu0, tau_x, tau_t, theta0, omega, h = es.hyper
