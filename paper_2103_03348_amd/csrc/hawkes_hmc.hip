@@ -52,7 +52,16 @@ struct hk_subset {
     double *Lam_static;  // [1] integral term of the fixed-rate events + background
     double *a;           // [mpad] theta0 (1 - exp(-omega (T1 - t_k))) per subset entry r
     // per-evaluation buffers
-    float *theta32;      // [mpad] subset rates, time order
+    // staged subset entries (time order), written once per evaluation
+    float *tv;           // [mpad] theta_r exp(omega (t_r - T_q)) (theta_r on wide chunks), 0 on padding
+    double2 *sxy;        // [mpad] coordinates pre-scaled by sqrt(-kex)
+    double *sts;         // [mpad] times
+    int *qwide;          // [nq] 1 where the 64-entry chunk q spans more than HK_SUB_FACT_SPAN / omega
+    double *qstep;       // [nq] exp(-omega (T_{q+1} - T_q)), T_q the time of chunk q's first entry
+    // row-chunk staging of the subset column pass, written by k_sub_fin
+    float *wv;           // [npad] c_e / lambda_i times exp(-omega (t_i - T_c)) on split chunks
+    int *cwide;          // [nchunks] 1 where the row chunk takes the direct exponent
+    double *cstep;       // [nchunks] exp(-omega (T_{c+1} - T_c))
     double *colG;        // [n_items][2][HK_WAVE]
     double *gsub;        // [mpad] Eq. 4 on the subset, time order
     double *hsub;        // [mpad] Eq. 5 on the subset, time order
@@ -87,6 +96,9 @@ constexpr int64_t SUB_COL_ITEMS = HK_SUB_COL_ITEMS;
 #endif
 constexpr int SUB_FIN_WAVES = HK_SUB_FIN_WAVES;
 constexpr int64_t SUB_ITEM_BATCHES = 16;
+// a 64-entry (or 64-event) chunk whose times span more than this over omega
+// takes the direct exponent instead of the split time factor
+#define HK_SUB_FACT_SPAN 40.0
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -243,19 +255,41 @@ __global__ void k_sub_offset(const double *__restrict__ ts, const int *__restric
     if (r < m) off[slot[r]] = beta * ts[pos[r]];
 }
 
-// theta_k = exp(z_k): FP32 copy in time order, FP64 into the caller's full rate vector
-__global__ void k_sub_theta(const double *__restrict__ z, const double *__restrict__ off,
-                            const int *__restrict__ slot, const int64_t *__restrict__ cidx, int64_t m, int64_t mpad,
-                            float *__restrict__ theta32, double *__restrict__ theta_full) {
-    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= mpad) return;
-    if (r < m) {
+// theta_k = exp(z_k) into the caller's full rate vector, and the staged subset
+// entries of this evaluation in time order: pre-scaled coordinates, times, the
+// rate with the split time factor of its 64-entry chunk, the chunk's split flag
+// and step factor.  One wavefront per chunk (the grid covers mpad exactly).
+__global__ __launch_bounds__(256) void k_sub_theta(
+    const double *__restrict__ z, const double *__restrict__ off, const int *__restrict__ slot,
+    const int64_t *__restrict__ cidx, int64_t m, const int *__restrict__ pos, const double *__restrict__ ts,
+    const int *__restrict__ xi, const int *__restrict__ yi, const PairConst kc, float *__restrict__ tv,
+    double2 *__restrict__ sxy, double *__restrict__ sts, int *__restrict__ qwide, double *__restrict__ qstep,
+    double *__restrict__ theta_full) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (HK_WAVE - 1);
+    const int64_t r0 = r - lane;  // the chunk's first entry
+    const bool valid = r < m;
+    const int pj = valid ? pos[r] : 0;
+    const double t = ts[pj];
+    const double Tq = r0 < m ? ts[pos[r0]] : 0.0;  // chunks past m hold padding only
+    const double dt = valid ? t - Tq : 0.0;
+    const bool wide = __any(valid && kc.omega * dt > HK_SUB_FACT_SPAN);
+    if (valid) {
         const int k = slot[r];
-        const double th = exp(zeff(z, off, k));
-        theta32[r] = (float)th;
-        if (theta_full) theta_full[cidx[k]] = th;
+        const double ze = zeff(z, off, k);
+        if (theta_full) theta_full[cidx[k]] = exp(ze);
+        tv[r] = (float)exp(wide ? ze : ze + kc.omega * dt);
+        sxy[r] = make_double2((double)xi[pj] * kc.sx, (double)yi[pj] * kc.sx);
+        sts[r] = t;
     } else {
-        theta32[r] = 0.0f;
+        tv[r] = 0.0f;
+        sxy[r] = make_double2(0.0, 0.0);
+        sts[r] = 0.0;
+    }
+    if (lane == 0) {
+        const int64_t q = r0 / HK_WAVE;
+        qwide[q] = wide;
+        qstep[q] = r0 + HK_WAVE < m ? exp(-kc.omega * (ts[pos[r0 + HK_WAVE]] - Tq)) : 0.0;
     }
 }
 
@@ -266,7 +300,6 @@ __global__ void k_sub_theta(const double *__restrict__ z, const double *__restri
 // span more than HK_SUB_FACT_SPAN / omega in time.  The exponent is formed in
 // FP64 from coordinates pre-scaled by sqrt(-kex) (and, unsplit, the FP64 time
 // term) and rounded once, so it carries no rounded FP32 constant.
-#define HK_SUB_FACT_SPAN 40.0
 
 template <bool FACT>
 __device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
@@ -289,8 +322,9 @@ __device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, c
 // to the item's slot.
 __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
     const double *__restrict__ ts, const int *__restrict__ xi, const int *__restrict__ yi, const int *__restrict__ g,
-    const int *__restrict__ pos, const float *__restrict__ theta32, const hk_item *__restrict__ ritems,
-    const PairConst kc, double *__restrict__ xpart) {
+    const int *__restrict__ pos, const float *__restrict__ tv, const double2 *__restrict__ sxy,
+    const double *__restrict__ sts, const int *__restrict__ qwide, const double *__restrict__ qstep,
+    const hk_item *__restrict__ ritems, const PairConst kc, double *__restrict__ xpart) {
     __shared__ double2 rxy[HK_WAVE];
     __shared__ float rv[HK_WAVE];
     __shared__ double rtd[HK_WAVE];
@@ -306,32 +340,41 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
     // under the cutoff, batches whose last entry precedes the chunk's first row
     // by more than dt_cut_ex are skipped (entries are in time order)
     const double chunk_tmin = ts[(int64_t)b * HK_WAVE];
-    for (int c0 = it.c_begin; c0 < it.c_end; c0 += HK_WAVE) {
+    // batches are the 64-entry subset chunks (items start on chunk boundaries),
+    // walked from late to early: the row's split factor exp(-omega (t_i - T_q)) is
+    // evaluated at the first batch that has a causal pair (where it is at most 1)
+    // and carried down by the chunks' step factors
+    double ui = 0.0;
+    bool have_ui = false;
+    const int c_last = it.c_begin + (it.c_end - 1 - it.c_begin) / HK_WAVE * HK_WAVE;
+    for (int c0 = c_last; c0 >= it.c_begin; c0 -= HK_WAVE) {
+        const int q = c0 / HK_WAVE;
+        if (have_ui) ui *= qstep[q];
         const int cend = min(c0 + HK_WAVE, it.c_end);
-        if (chunk_tmin - ts[pos[cend - 1]] > kc.dt_cut_ex) continue;
-        const double Tr = ts[pos[c0]];
-        bool fact;
+        if (chunk_tmin - sts[cend - 1] > kc.dt_cut_ex) continue;
+        const bool fact = qwide[q] == 0;
         {
             const int r = c0 + lane;
             const bool valid = r < cend;
-            const int pj = valid ? pos[r] : 0;
-            const double dtk = valid ? ts[pj] - Tr : 0.0;
-            const float th = valid ? theta32[r] : 0.0f;
-            fact = !__any(th > 0.0f && kc.omega * dtk > HK_SUB_FACT_SPAN);
-            rxy[lane] = valid ? make_double2((double)xi[pj] * kc.sx, (double)yi[pj] * kc.sx)
-                              : make_double2(0.0, 0.0);
-            rv[lane] = (fact && th > 0.0f) ? (float)((double)th * exp(kc.omega * dtk)) : th;
-            rtd[lane] = valid ? ts[pj] : 0.0;
-            rpos[lane] = valid ? pj : 0x7fffffff;
+            rxy[lane] = sxy[r];
+            rv[lane] = valid ? tv[r] : 0.0f;
+            rtd[lane] = sts[r];
+            rpos[lane] = valid ? pos[r] : 0x7fffffff;
         }
         __syncthreads();
         double accb = 0.0;
         if (fact) sub_row_sweep<true>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
         else sub_row_sweep<false>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
-        // a row with a causal pair here has t_i > t_k >= T_r: its factor is at most 1
         if (accb != 0.0) {
-            const double ui = fact ? exp(-kc.omega * (tsi - Tr)) : 1.0;
-            acc += ui * accb;
+            if (fact) {
+                if (!have_ui) {
+                    ui = exp(-kc.omega * (tsi - sts[c0]));
+                    have_ui = true;
+                }
+                acc += ui * accb;
+            } else {
+                acc += accb;
+            }
         }
         __syncthreads();
     }
@@ -339,14 +382,24 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
 }
 
 // One wavefront per 64-row chunk (many blocks in flight for the partial-sum
-// reads); the chunk's sum of log lambda goes to blockpart[chunk].
+// reads); the chunk's sum of log lambda goes to blockpart[chunk].  It also stages
+// the chunk for the subset column pass: w_i = c_e / lambda_i times the split
+// factor exp(-omega (t_i - T_c)), the chunk's split flag and its step factor.
 __global__ __launch_bounds__(HK_WAVE) void k_sub_fin(const double *__restrict__ lam_static,
                                                  const int *__restrict__ ritem0, const int *__restrict__ rnseg,
-                                                 const double *__restrict__ xpart, int64_t n, int64_t npad,
-                                                 const FinConst fc,
-                                                 double *__restrict__ lam, float *__restrict__ w, float *__restrict__ wlo,
+                                                 const double *__restrict__ xpart, const double *__restrict__ ts,
+                                                 int64_t n, int64_t npad, const FinConst fc,
+                                                 double *__restrict__ lam, float *__restrict__ wv,
+                                                 int *__restrict__ cwide, double *__restrict__ cstep,
                                                  double *__restrict__ blockpart, int *__restrict__ status) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i0 = i - threadIdx.x;  // the chunk's first event
+    const double dti = ts[i] - ts[i0];
+    const bool wide = __any(i < n && fc.omega * dti > HK_SUB_FACT_SPAN);
+    if (threadIdx.x == 0) {
+        cwide[blockIdx.x] = wide;
+        cstep[blockIdx.x] = i0 + HK_WAVE < npad ? exp(-fc.omega * (ts[i0 + HK_WAVE] - ts[i0])) : 0.0;
+    }
     double v = 0.0;
     if (i < n) {
         // the row items of this chunk, in order
@@ -360,13 +413,11 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_fin(const double *__restrict__ 
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
         const double wd = l > 0.0 ? fc.c_e / l : 0.0;
-        w[i] = (float)wd;
-        wlo[i] = (float)(wd - (double)(float)wd);
+        wv[i] = (float)(wide ? wd : wd * exp(-fc.omega * dti));
         v = log(l);
-    } else if (i < npad) {
+    } else {
         lam[i] = 1.0;
-        w[i] = 0.0f;
-        wlo[i] = 0.0f;
+        wv[i] = 0.0f;
     }
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (threadIdx.x == 0) blockpart[blockIdx.x] = v;
@@ -377,7 +428,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_fin(const double *__restrict__ 
 // column pass: time factors in FP64, spatial exponent from pre-scaled FP64
 // coordinates, rounded once.
 template <bool WITH_H, bool FACT>
-__device__ __forceinline__ void sub_col_sweep(const double2 *__restrict__ rxy, const float2 *__restrict__ rv,
+__device__ __forceinline__ void sub_col_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
                                               const double *__restrict__ rtd, const int *__restrict__ rg, int pj,
                                               double tsj, double xj, double yj, const PairConst kc, float &G,
                                               float &H) {
@@ -388,8 +439,7 @@ __device__ __forceinline__ void sub_col_sweep(const double2 *__restrict__ rxy, c
         const double aed = -fma(dx, dx, dy * dy);
         float E = fexp2(FACT ? (float)aed : (float)fma(rtd[s] - tsj, kc.kw_d, aed));
         if (!(pj < rg[s])) E = 0.0f;
-        const float2 v = rv[s];
-        const float ew = fmaf(E, v.y, E * v.x);
+        const float ew = E * rv[s];
         G += ew;
         if (WITH_H) H = fmaf(ew, ew, H);
     }
@@ -399,13 +449,14 @@ __device__ __forceinline__ void sub_col_sweep(const double2 *__restrict__ rxy, c
 // chunks after them; the entries' partial sums go to the item's slot.
 template <bool WITH_H>
 __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ ts, const int *__restrict__ xi,
-                                                      const int *__restrict__ yi, const float *__restrict__ w,
-                                                      const float *__restrict__ wlo, const int *__restrict__ g,
-                                                      const int *__restrict__ pos, int64_t m,
-                                                      const hk_item *__restrict__ items, const PairConst kc,
-                                                      double *__restrict__ colG) {
+                                                      const int *__restrict__ yi, const float *__restrict__ wv,
+                                                      const int *__restrict__ cwide, const double *__restrict__ cstep,
+                                                      const int *__restrict__ g, const int *__restrict__ pos,
+                                                      const double2 *__restrict__ sxy, const double *__restrict__ sts,
+                                                      int64_t m, const hk_item *__restrict__ items,
+                                                      const PairConst kc, double *__restrict__ colG) {
     __shared__ double2 rxy[HK_WAVE];
-    __shared__ float2 rv[HK_WAVE];
+    __shared__ float rv[HK_WAVE];
     __shared__ double rtd[HK_WAVE];
     __shared__ int rg[HK_WAVE];
     const hk_item it = items[blockIdx.x];
@@ -413,38 +464,45 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
     const int64_t r = (int64_t)it.tile * HK_WAVE + lane;
     const bool live = r < m;
     const int pj = live ? pos[r] : 0;
-    const double tsj = ts[pj];
-    const double xj = (double)xi[pj] * kc.sx, yj = (double)yi[pj] * kc.sx;
-    // the chunk's latest entry (entries are in time order; padding entries
-    // repeat position 0 and do not raise it)
+    const double tsj = sts[r];
+    const double2 pxy = sxy[r];
+    // the chunk's latest entry (entries are in time order)
     const int64_t r_last = min((int64_t)it.tile * HK_WAVE + HK_WAVE, m) - 1;
-    const double q_tmax = ts[pos[r_last]];
+    const double q_tmax = sts[r_last];
     double Gd = 0.0, Hd = 0.0;
+    // the entry's split factor exp(omega (t_j - T_c)), evaluated at the first
+    // split chunk with a causal pair (at most exp(HK_SUB_FACT_SPAN)) and carried
+    // to later chunks by their step factors
+    double uj = 0.0;
+    bool have_uj = false;
     for (int c = it.c_begin; c < it.c_end; ++c) {
+        if (have_uj) uj *= cstep[c - 1];
         const double Tc = ts[(int64_t)c * HK_WAVE];
         if (Tc - q_tmax > kc.dt_cut_ex) break;  // cutoff: all later rows too far
-        bool fact;
+        const bool fact = cwide[c] == 0;
         {
             const int64_t i = (int64_t)c * HK_WAVE + lane;
-            const double ti = ts[i];
-            const double dti = ti - Tc;
-            const double wd = (double)w[i] + (double)wlo[i];
-            fact = !__any(wd > 0.0 && kc.omega * dti > HK_SUB_FACT_SPAN);
-            const double vv = fact ? wd * exp(-kc.omega * dti) : wd;
-            const float vhi = (float)vv;
             rxy[lane] = make_double2((double)xi[i] * kc.sx, (double)yi[i] * kc.sx);
-            rv[lane] = make_float2(vhi, (float)(vv - (double)vhi));
-            rtd[lane] = ti;
+            rv[lane] = wv[i];
+            rtd[lane] = ts[i];
             rg[lane] = g[i];
         }
         __syncthreads();
         float G = 0.0f, H = 0.0f;
-        if (fact) sub_col_sweep<WITH_H, true>(rxy, rv, rtd, rg, pj, tsj, xj, yj, kc, G, H);
-        else sub_col_sweep<WITH_H, false>(rxy, rv, rtd, rg, pj, tsj, xj, yj, kc, G, H);
+        if (fact) sub_col_sweep<WITH_H, true>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
+        else sub_col_sweep<WITH_H, false>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
         if (G != 0.0f) {
-            const double uj = fact ? exp(kc.omega * (tsj - Tc)) : 1.0;
-            Gd += uj * (double)G;
-            if (WITH_H) Hd += (uj * uj) * (double)H;
+            if (fact) {
+                if (!have_uj) {
+                    uj = exp(kc.omega * (tsj - Tc));
+                    have_uj = true;
+                }
+                Gd += uj * (double)G;
+                if (WITH_H) Hd += (uj * uj) * (double)H;
+            } else {
+                Gd += (double)G;
+                if (WITH_H) Hd += (double)H;
+            }
         }
         __syncthreads();
     }
@@ -466,7 +524,10 @@ struct SubUpd {
     double *p;
     const double *mass;
     double a_p, a_z;
-    float *theta32;
+    float *tv;            // staged subset rates (k_sub_theta's layout)
+    const double *sts;
+    const int *qwide;
+    double omega;
 };
 
 // Per 64-entry subset chunk: the SUB_FIN_WAVES wavefronts split the chunk's
@@ -509,7 +570,9 @@ __global__ __launch_bounds__(SUB_FIN_WAVES * HK_WAVE) void k_sub_colfin(
         if (u.a_z != 0.0) {
             const double zn = zk + u.a_z * pk / u.mass[k];
             u.z[k] = zn;
-            u.theta32[r] = (float)exp(u.off ? zn + u.off[k] : zn);
+            const double ze = u.off ? zn + u.off[k] : zn;
+            const int64_t r0 = (int64_t)q * HK_WAVE;
+            u.tv[r] = (float)exp(u.qwide[q] ? ze : ze + u.omega * (u.sts[r] - u.sts[r0]));
         }
     }
 }
@@ -645,7 +708,7 @@ void hk_subset_free(hawkes_plan p) {
     hk_subset *s = p->sub;
     if (!s) return;
     void *ptrs[] = {s->pos, s->slot, s->cidx, s->ritems, s->ritem0, s->rnseg, s->xpart, s->items, s->item0, s->nseg,
-                    s->lam_static, s->Lam_static, s->a, s->theta32, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->off, s->vz, s->scal,
+                    s->lam_static, s->Lam_static, s->a, s->tv, s->sxy, s->sts, s->qwide, s->qstep, s->wv, s->cwide, s->cstep, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->off, s->vz, s->scal,
                     s->grid};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -766,7 +829,14 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     SC(dalloc(&s->lam_static, p->npad));
     SC(dalloc(&s->Lam_static, 1));
     SC(dalloc(&s->a, s->mpad));
-    SC(dalloc(&s->theta32, s->mpad));
+    SC(dalloc(&s->tv, s->mpad));
+    SC(dalloc(&s->sxy, s->mpad));
+    SC(dalloc(&s->sts, s->mpad));
+    SC(dalloc(&s->qwide, s->nq));
+    SC(dalloc(&s->qstep, s->nq));
+    SC(dalloc(&s->wv, p->npad));
+    SC(dalloc(&s->cwide, p->nchunks));
+    SC(dalloc(&s->cstep, p->nchunks));
     SC(dalloc(&s->colG, (size_t)s->n_items * 2 * HK_WAVE));
     SC(dalloc(&s->gsub, s->mpad));
     SC(dalloc(&s->hsub, s->mpad));
@@ -816,14 +886,16 @@ hawkes_status ensure_static(hawkes_plan p, const hawkes_hyper *hy, const double 
 static void sub_rows(hawkes_plan p, const double *z, const double *off, double *theta_full, bool with_theta,
                      const PairConst &kc, const FinConst &fc, hipStream_t stream) {
     hk_subset *s = p->sub;
-    p->epoch += 1;  // p->lam and p->w are overwritten below
+    p->epoch += 1;  // p->lam is overwritten below
     if (with_theta)
-        hipLaunchKernelGGL(k_sub_theta, dim3(nblk(s->mpad, 256)), dim3(256), 0, stream, z, off, s->slot, s->cidx,
-                           s->m, s->mpad, s->theta32, theta_full);
+        hipLaunchKernelGGL(k_sub_theta, dim3((unsigned)(s->mpad / 256)), dim3(256), 0, stream, z, off, s->slot,
+                           s->cidx, s->m, s->pos, p->ts, p->xi, p->yi, kc, s->tv, s->sxy, s->sts, s->qwide, s->qstep,
+                           theta_full);
     hipLaunchKernelGGL(k_sub_row, dim3(s->n_ritems), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->g, s->pos,
-                       s->theta32, s->ritems, kc, s->xpart);
+                       s->tv, s->sxy, s->sts, s->qwide, s->qstep, s->ritems, kc, s->xpart);
     hipLaunchKernelGGL(k_sub_fin, dim3(p->nchunks), dim3(HK_WAVE), 0, stream, s->lam_static, s->ritem0, s->rnseg,
-                       s->xpart, p->n, p->npad, fc, p->lam, p->w, p->wlo, p->blockpart, p->status);
+                       s->xpart, p->ts, p->n, p->npad, fc, p->lam, s->wv, s->cwide, s->cstep, p->blockpart,
+                       p->status);
 }
 
 // The column half: Eq. 4 (and Eq. 5) on the subset, optionally with the fused
@@ -832,11 +904,11 @@ static void sub_cols(hawkes_plan p, bool with_h, const PairConst &kc, const FinC
                      hipStream_t stream) {
     hk_subset *s = p->sub;
     if (with_h)
-        hipLaunchKernelGGL(k_sub_col<true>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->w,
-                           p->wlo, p->g, s->pos, s->m, s->items, kc, s->colG);
+        hipLaunchKernelGGL(k_sub_col<true>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, s->wv,
+                           s->cwide, s->cstep, p->g, s->pos, s->sxy, s->sts, s->m, s->items, kc, s->colG);
     else
-        hipLaunchKernelGGL(k_sub_col<false>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->w,
-                           p->wlo, p->g, s->pos, s->m, s->items, kc, s->colG);
+        hipLaunchKernelGGL(k_sub_col<false>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, s->wv,
+                           s->cwide, s->cstep, p->g, s->pos, s->sxy, s->sts, s->m, s->items, kc, s->colG);
     if (upd)
         hipLaunchKernelGGL(k_sub_colfin<true>, dim3(s->nq), dim3(SUB_FIN_WAVES * HK_WAVE), 0, stream, s->item0,
                            s->nseg, s->colG, s->a, s->m, fc, with_h, s->gsub, s->hsub, *upd);
@@ -952,7 +1024,8 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
                        a->d_mass, s->slot, s->a, m, s->scal);
     // phylogenetic prior: the quadratic form z^T V^{-1} z replaces sum z^2
     if (tree && (st = hk_tree_launch(p, a->d_z, s->vz, s->scal + 2, stream)) != HAWKES_OK) return st;
-    SubUpd upd{s->slot, a->d_z, off, pv, inv_s2, s->p, a->d_mass, 0.5 * a->eps, a->eps, s->theta32};
+    SubUpd upd{s->slot, a->d_z, off, pv, inv_s2, s->p, a->d_mass, 0.5 * a->eps, a->eps, s->tv, s->sts, s->qwide,
+               kc.omega};
     sub_cols(p, false, kc, fc, &upd, stream);
     for (int l = 0; l < a->L; ++l) {
         // evaluation at the drifted position, then a full kick and drift, or the

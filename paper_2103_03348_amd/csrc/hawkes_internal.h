@@ -90,8 +90,6 @@ struct hawkes_plan_s {
     float *rowpart;           // [n_row_items][HK_NROW][HK_TILE] row partial sums of each piece
     float *colpart;           // triangular [tile][HK_NCOL][(tile+1)*HK_TILE]: background column partials
     double *lam;              // [npad] lambda_i, sorted
-    float *w;                 // [npad] c_e / lambda_i of the subset path (FP32 high part), 0 on padding
-    float *wlo;               // [npad] FP32 remainder of that c_e / lambda_i
     double *a;                // [npad] theta0 (1 - exp(-omega (T1 - t_i)))
     double *colG;             // [n_col_items][2][HK_TILE]: G and H of each column piece
     int nfin_blocks;          // npad / 256 (subset-path reductions)

@@ -152,7 +152,7 @@ void free_plan(hawkes_plan p) {
     hk_tree_free(p);
     void *ptrs[] = {p->ts, p->xi, p->yi, p->perm, p->g, p->row_items, p->row_block0, p->row_item0, p->row_nseg,
                     p->colpart_off, p->col_items, p->col_block0, p->col_item0, p->col_nseg, p->theta_s, p->theta_v, p->chunk_wide, p->tstep, p->wv, p->rowpart,
-                    p->colpart, p->lam, p->w, p->wlo, p->a, p->colG, p->blockpart, p->status};
+                    p->colpart, p->lam, p->a, p->colG, p->blockpart, p->status};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -366,8 +366,6 @@ extern "C" hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const d
     PC(dalloc(&p->rowpart, (size_t)p->n_row_items * HK_NROW * HK_TILE));
     PC(dalloc(&p->colpart, (size_t)cpl));
     PC(dalloc(&p->lam, npad));
-    PC(dalloc(&p->w, npad));
-    PC(dalloc(&p->wlo, npad));
     PC(dalloc(&p->a, npad));
     PC(dalloc(&p->colG, (size_t)p->n_col_items * 2 * HK_TILE));
     p->nfin_blocks = (int)(npad / 256);
