@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_sub_theta(
 // FP64 from coordinates pre-scaled by sqrt(-kex) (and, unsplit, the FP64 time
 // term) and rounded once, so it carries no rounded FP32 constant.
 
-template <bool FACT>
+template <bool MASKED, bool FACT>
 __device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
                                               const double *__restrict__ rtd, const int *__restrict__ rpos,
                                               double tsi, double xr, double yr, int gr, const PairConst kc,
@@ -312,7 +312,7 @@ __device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, c
         const double dx = xr - pk.x, dy = yr - pk.y;
         const double aed = -fma(dx, dx, dy * dy);
         float E = fexp2(FACT ? (float)aed : (float)fma(tsi - rtd[s], kc.kw_d, aed));
-        if (!(rpos[s] < gr)) E = 0.0f;
+        if (MASKED && !(rpos[s] < gr)) E = 0.0f;
         acc += (double)(E * rv[s]);
     }
 }
@@ -340,6 +340,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
     // under the cutoff, batches whose last entry precedes the chunk's first row
     // by more than dt_cut_ex are skipped (entries are in time order)
     const double chunk_tmin = ts[(int64_t)b * HK_WAVE];
+    const int g_first = g[(int64_t)b * HK_WAVE];  // g is non-decreasing
     // batches are the 64-entry subset chunks (items start on chunk boundaries),
     // walked from late to early: the row's split factor exp(-omega (t_i - T_q)) is
     // evaluated at the first batch that has a causal pair (where it is at most 1)
@@ -363,8 +364,15 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
         }
         __syncthreads();
         double accb = 0.0;
-        if (fact) sub_row_sweep<true>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
-        else sub_row_sweep<false>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
+        // a batch whose entries all precede the chunk's first tie group needs no
+        // causality mask (padding entries carry rate 0)
+        if (pos[cend - 1] < g_first) {
+            if (fact) sub_row_sweep<false, true>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
+            else sub_row_sweep<false, false>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
+        } else {
+            if (fact) sub_row_sweep<true, true>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
+            else sub_row_sweep<true, false>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
+        }
         if (accb != 0.0) {
             if (fact) {
                 if (!have_ui) {
@@ -427,7 +435,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_fin(const double *__restrict__ 
 // all events after them, broadcast from LDS.  Same arithmetic as the full
 // column pass: time factors in FP64, spatial exponent from pre-scaled FP64
 // coordinates, rounded once.
-template <bool WITH_H, bool FACT>
+template <bool WITH_H, bool MASKED, bool FACT>
 __device__ __forceinline__ void sub_col_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
                                               const double *__restrict__ rtd, const int *__restrict__ rg, int pj,
                                               double tsj, double xj, double yj, const PairConst kc, float &G,
@@ -438,7 +446,7 @@ __device__ __forceinline__ void sub_col_sweep(const double2 *__restrict__ rxy, c
         const double dx = p.x - xj, dy = p.y - yj;
         const double aed = -fma(dx, dx, dy * dy);
         float E = fexp2(FACT ? (float)aed : (float)fma(rtd[s] - tsj, kc.kw_d, aed));
-        if (!(pj < rg[s])) E = 0.0f;
+        if (MASKED && !(pj < rg[s])) E = 0.0f;
         const float ew = E * rv[s];
         G += ew;
         if (WITH_H) H = fmaf(ew, ew, H);
@@ -469,6 +477,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
     // the chunk's latest entry (entries are in time order)
     const int64_t r_last = min((int64_t)it.tile * HK_WAVE + HK_WAVE, m) - 1;
     const double q_tmax = sts[r_last];
+    const int pos_last = pos[r_last];
     double Gd = 0.0, Hd = 0.0;
     // the entry's split factor exp(omega (t_j - T_c)), evaluated at the first
     // split chunk with a causal pair (at most exp(HK_SUB_FACT_SPAN)) and carried
@@ -489,8 +498,14 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
         }
         __syncthreads();
         float G = 0.0f, H = 0.0f;
-        if (fact) sub_col_sweep<WITH_H, true>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
-        else sub_col_sweep<WITH_H, false>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
+        // rows whose tie groups all start after the chunk's last entry need no mask
+        if (pos_last < g[(int64_t)c * HK_WAVE]) {
+            if (fact) sub_col_sweep<WITH_H, false, true>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
+            else sub_col_sweep<WITH_H, false, false>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
+        } else {
+            if (fact) sub_col_sweep<WITH_H, true, true>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
+            else sub_col_sweep<WITH_H, true, false>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
+        }
         if (G != 0.0f) {
             if (fact) {
                 if (!have_uj) {
