@@ -600,6 +600,7 @@ __global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__
 #pragma unroll
         for (int k = 0; k < HK_NROW; ++k) acc[k] = 0.0;
         const int it0 = row_item0[I], ns = row_nseg[I];
+        #pragma unroll 2
         for (int sg = wq; sg < ns; sg += HK_FIN_WAVES) {
             const float *rp = rowpart + (int64_t)(it0 + sg) * HK_NROW * HK_TILE + r;
             acc[0] += rp[0];
@@ -619,6 +620,7 @@ __global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__
         }
         // background from later events: the column partials of row tiles J >= I
         // (region J starts at HK_NCOL HK_TILE J (J + 1) / 2)
+        #pragma unroll 2
         for (int J = I + wq; J < ntiles; J += HK_FIN_WAVES) {
             const int64_t stride = (int64_t)(J + 1) * HK_TILE;
             const float *cp = colpart + (int64_t)HK_NCOL * HK_TILE * J * (J + 1) / 2 + i;
@@ -805,6 +807,7 @@ __global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_colfin(const int *__
     const int J = (int)(j / HK_TILE), r = (int)(j % HK_TILE);
     const int it0 = col_item0[J], ns = col_nseg[J];
     double G = 0.0, H = 0.0;
+    #pragma unroll 2
     for (int sg = wv; sg < ns; sg += HK_FIN_WAVES) {
         const double *cg = colG + (int64_t)(it0 + sg) * 2 * HK_TILE + r;
         G += cg[0];

@@ -41,10 +41,16 @@ def _subset_grad(plan, es, theta, refresh=0):
     return float(ll.item()), g.cpu().numpy(), h.cpu().numpy()
 
 
-@pytest.mark.parametrize("cfg", ["small", "n23422"])
+@pytest.mark.parametrize("cfg", ["small", "allfree", "n23422"])
 def test_subset_grad_matches_oracle(gpu, cfg):
-    """Eq. 1, 4, 5 restricted to the free rates, by the cached-static O(N M) path."""
-    es = synth.small(1500, seed=21, ties=6, all_free=False) if cfg == "small" else synth.config(1)
+    """Eq. 1, 4, 5 restricted to the free rates, by the cached-static O(N M) path
+    (allfree: every rate free, so the static part holds the background only)."""
+    if cfg == "small":
+        es = synth.small(1500, seed=21, ties=6, all_free=False)
+    elif cfg == "allfree":
+        es = synth.small(333, seed=22, ties=5, all_free=True)
+    else:
+        es = synth.config(1)
     plan, idx = _setup(es)
     ll, g, h = _subset_grad(plan, es, es.theta)
     assert plan.status() == 0
