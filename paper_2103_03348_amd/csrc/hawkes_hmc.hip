@@ -300,13 +300,14 @@ __global__ __launch_bounds__(256) void k_sub_theta(
     }
 }
 
-// Subset excitation per event: one wavefront owns 64 rows and sweeps the subset
-// entries that precede them (cnt[b]), staged 64 at a time through LDS.  The
-// time factor of E is split at the first staged entry's time as in the full row
-// pass (FP64 factors, spatial exponent in the loop) unless the staged entries
-// span more than HK_SUB_FACT_SPAN / omega in time.  The exponent is formed in
-// FP64 from coordinates pre-scaled by sqrt(-kex) (and, unsplit, the FP64 time
-// term) and rounded once, so it carries no rounded FP32 constant.
+// Subset excitation per event: a wavefront owns the 64 rows of a chunk and
+// sweeps subset entries that precede the chunk's end, staged 64 at a time (one
+// 64-entry subset chunk) through LDS.  The time factor of E is split at the
+// chunk's first entry time as in the full row pass (FP64 factors, spatial
+// exponent in the loop) unless the chunk spans more than HK_SUB_FACT_SPAN /
+// omega in time.  The exponent is formed in FP64 from coordinates pre-scaled by
+// sqrt(-kex) (and, unsplit, the FP64 time term) and rounded once, so it carries
+// no rounded FP32 constant.
 
 template <bool MASKED, bool FACT>
 __device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
