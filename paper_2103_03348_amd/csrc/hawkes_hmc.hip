@@ -154,8 +154,6 @@ __global__ void k_sub_layout(const double *__restrict__ key, const int *__restri
     }
 }
 
-// cnt[b] = number of subset entries with pos < 64 (b + 1) (binary search).
-
 // ---- static part ---------------------------------------------------------------------
 // theta with the subset entries zeroed, sorted, FP32
 __global__ void k_sub_static_theta(const double *__restrict__ theta, const int *__restrict__ perm,

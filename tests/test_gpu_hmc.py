@@ -77,6 +77,29 @@ def test_subset_grad_matches_oracle(gpu, cfg):
     assert np.max(np.abs(g2 - gi2) / np.maximum(np.abs(gi2) + 2 * a, 1e-300)) < 1e-6
 
 
+def test_subset_rejects_bad_indices(gpu):
+    """A repeated or out-of-range free-rate index is an argument error, and the
+    plan keeps working for a valid subset afterwards."""
+    import torch
+
+    from paper_2103_03348_amd import _lib
+    from paper_2103_03348_amd.hawkes import Plan
+
+    es = synth.small(300, seed=23, ties=4, all_free=False)
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
+    for bad in ([3, 7, 3], [0, 299, 300], [-1, 5]):
+        idx = torch.as_tensor(bad, dtype=torch.int64, device="cuda:0")
+        code = _lib.lib().hawkes_plan_set_subset(plan.handle, idx.numel(), _lib.ptr(idx), _lib.stream_handle())
+        assert code == _lib.E_INVALID, (bad, code)
+    idx = torch.as_tensor(es.subset, dtype=torch.int64, device="cuda:0")
+    _lib.check(_lib.lib().hawkes_plan_set_subset(plan.handle, idx.numel(), _lib.ptr(idx), _lib.stream_handle()),
+               "set_subset")
+    ll, g, _ = _subset_grad(plan, es, es.theta)
+    ref = oracle.evaluate_es(es, want=("loglik", "grad_theta"))
+    assert abs(ll - ref["loglik"]) / abs(ref["loglik"]) < 1e-6
+    plan.close()
+
+
 def _hmc_gpu(plan, es, z0, mass, eps, L, sigma, seed, counter, theta=None):
     import torch
 
