@@ -32,9 +32,12 @@
  *    status word that hawkes_plan_status returns and clears.
  *  - A plan is not thread-safe; calls on one plan must be ordered by the
  *    caller (one stream, or explicit events).  Separate plans are independent.
- *  - Precision: inputs and outputs are FP64.  The O(N^2) pair sums run in FP32
- *    with compensated accumulation; log-intensities, the integral term, the
- *    final reductions and the HMC energy run in FP64.
+ *  - Precision: inputs and outputs are FP64.  The O(N^2) pair terms are FP32
+ *    (their exponents formed in FP64 and rounded once where that decides the
+ *    accuracy); the sums that build lambda accumulate every term in FP64, the
+ *    derivative moments in FP32 per 64-term chunk and FP64 beyond.
+ *    Log-intensities, the integral term, the final reductions (in a fixed
+ *    order, so results are bit-reproducible) and the HMC energy run in FP64.
  */
 #ifndef HAWKES_H_
 #define HAWKES_H_
