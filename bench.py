@@ -49,7 +49,7 @@ PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # reported only while their hashes match.
 K_ROW_TRAFFIC_BYTES = (2887.8 * 2.0 + 63220.0 * 1.0) * 1024
 K_ROW_TRAFFIC_SOURCES = {
-    "paper_2103_03348_amd/csrc/hawkes_eval.hip": "60f33ac5849835b76575433ffd39ce7391fdf97de5e9fa338e7e374fb2f5b457",
+    "paper_2103_03348_amd/csrc/hawkes_eval.hip": "93ca0aa3a215c8166a06069dcc777e947d683e95156121b47b47486192d0dbe7",
     "paper_2103_03348_amd/csrc/hawkes_internal.h": "270f6159affbf2d887bf23a0521c214907fbb9b853a5737e6cf7fea68cf636b6",
     "paper_2103_03348_amd/csrc/hawkes_plan.hip": "443f7d95179df2b68273428f576385264811fe54713bfd8ae3d0b8a02ea0fecf",
 }

@@ -3,15 +3,16 @@
 //
 // Kernels, in launch order:
 //   k_tfac     theta to sorted order (FP32), validity check, staged rates of
-//              the split excitation time factor and the per-chunk split flags
+//              the split excitation time factor, the per-chunk split flags and
+//              step factors
 //   k_row      row pass over causal tile pairs: for each row i the background
 //              moments over j < i and the excitation moments over t_j < t_i;
 //              the background is symmetric, so each pair also adds its
 //              background moments to column j through accumulators that rotate
 //              one lane per step around the wavefront (DPP wave_rol)
 //   k_fin      per event: partial sums -> lambda_i (FP64), log lambda_i,
-//              w_i = c_e / lambda_i, integral term (App. A), hyperparameter
-//              terms; fixed-order block reduction (DPP within the wavefront)
+//              w_i = c_e / lambda_i staged for the column pass, integral term
+//              (App. A), hyperparameter terms; fixed-order block reduction
 //   k_fin2     one block: block partials -> loglik, grad/negH of hyperparameters
 //   k_col      column pass: G_j = sum_{t_i > t_j} E_ij w_i, H_j = sum (E_ij w_i)^2
 //   k_colfin   G_j, H_j -> Eq. 4 / Eq. 5 in the caller's order

@@ -14,12 +14,16 @@
 // Kernels:
 //   k_sub_static   partial sums of the static row pass -> lambda_static_i
 //   k_sub_offset   temporal-trend offsets beta t_k (Sec. 2.2)
-//   k_sub_theta    theta_k = exp(z_k + beta t_k) into FP32 subset order and the caller's theta
-//   k_sub_row      X_i = sum_{k in M, t_k < t_i} theta_k E_ik (rows = all events)
-//   k_sub_fin      lambda_i, w_i = c_e / lambda_i, block sums of log lambda_i
-//   k_sub_col      G_k = sum_{t_i > t_k} E_ik w_i, H_k = sum (E_ik w_i)^2
-//   k_sub_colfin   Eq. 4 / Eq. 5 on the subset; gradient in z with the prior
-//   k_hmc_*        momenta (Philox-4x32-10 + Box-Muller), leapfrog, energy, accept
+//   k_sub_theta    theta_k = exp(z_k + beta t_k) into the caller's theta, and the
+//                  subset entries staged in time order for the subset passes
+//   k_sub_row      X_i = sum_{k in M, t_k < t_i} theta_k E_ik (rows = all events),
+//                  one-wavefront items with partial sums
+//   k_sub_fin      lambda_i, block sums of log lambda_i, and the row chunks
+//                  staged for the column pass (w_i = c_e / lambda_i)
+//   k_sub_col      G_k = sum_{t_i > t_k} E_ik w_i, H_k = sum (E_ik w_i)^2, items
+//   k_sub_colfin   Eq. 4 / Eq. 5 on the subset; inside hmc_step also the
+//                  leapfrog's gradient in z, kick and drift
+//   k_hmc_*        momenta (Philox-4x32-10 + Box-Muller), energy, accept
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
