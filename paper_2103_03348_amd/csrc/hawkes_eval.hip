@@ -480,7 +480,7 @@ constexpr int HK_FIN_WAVES = 8;
 template <int MODE>
 __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const double *__restrict__ theta,
                                            const int *__restrict__ perm, int64_t n, const FinConst &fc,
-                                           const int *__restrict__ chunk_wide,
+                                           int *__restrict__ chunk_wide_col,
                                            const double (*part)[HK_NROW][HK_WAVE], int lane, int64_t i,
                                            double *__restrict__ lam, float *__restrict__ wv,
                                            double *__restrict__ a_out, double *__restrict__ blockpart,
@@ -488,6 +488,9 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
     double s[HK_NSUM];
 #pragma unroll
     for (int k = 0; k < HK_NSUM; ++k) s[k] = 0.0;
+    // the column pass's split flag of this chunk (HK_COL_SPAN)
+    const bool wide_col = __any(i < n && fc.omega * (ts[i] - ts[i - lane]) > HK_COL_SPAN);
+    if (lane == 0) chunk_wide_col[blockIdx.x] = wide_col;
     if (i < n) {
         double acc[HK_NROW];
 #pragma unroll
@@ -512,9 +515,9 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
         }
         {
             // w_i = c_e / lambda_i, staged for the column pass as w_i exp(-omega (t_i - T_c))
-            // on split chunks, rounded once to FP32
+            // on its split chunks, rounded once to FP32
             const double wd = lamv > 0.0 ? fc.c_e / lamv : 0.0;
-            wv[i] = (float)(chunk_wide[blockIdx.x] ? wd : wd * exp(-fc.omega * (ts[i] - ts[i - lane])));
+            wv[i] = (float)(wide_col ? wd : wd * exp(-fc.omega * (ts[i] - ts[i - lane])));
         }
         s[0] = log(lamv);
         const double inv = 1.0 / lamv;
@@ -588,7 +591,7 @@ __global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__
                                              const int *__restrict__ perm, int64_t n, int ntiles,
                                              const int *__restrict__ row_item0, const int *__restrict__ row_nseg,
                                              const float *__restrict__ rowpart, const float *__restrict__ colpart,
-                                             const FinConst fc, const int *__restrict__ chunk_wide,
+                                             const FinConst fc, int *__restrict__ chunk_wide_col,
                                              double *__restrict__ lam, float *__restrict__ wv,
                                              double *__restrict__ a_out,
                                              double *__restrict__ blockpart, int *__restrict__ status) {
@@ -639,7 +642,7 @@ __global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__
         for (int k = 0; k < HK_NROW; ++k) part[wq][k][lane] = acc[k];
     }
     __syncthreads();
-    if (wq == 0) fin_events<MODE>(ts, theta, perm, n, fc, chunk_wide, part, lane, i, lam, wv, a_out, blockpart,
+    if (wq == 0) fin_events<MODE>(ts, theta, perm, n, fc, chunk_wide_col, part, lane, i, lam, wv, a_out, blockpart,
                                   status);
 }
 
@@ -714,7 +717,7 @@ __device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const
 template <bool WITH_H>
 __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, const int *__restrict__ xi,
                                                   const int *__restrict__ yi, const float *__restrict__ wv,
-                                                  const int *__restrict__ chunk_wide,
+                                                  const int *__restrict__ chunk_wide_col,
                                                   const double *__restrict__ tstep, const int *__restrict__ g,
                                                   const hk_item *__restrict__ items, const int *__restrict__ block0,
                                                   double *__restrict__ colG, const PairConst kc) {
@@ -739,7 +742,7 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
         double Gd = 0.0, Hd = 0.0;
         // the column's split factor exp(omega (t_j - T_c)), evaluated at the first
         // split chunk with a causal pair and carried to later chunks by their step
-        // factors (decreasing from at most exp(HK_FACT_SPAN)); a wide chunk breaks
+        // factors (decreasing from at most exp(HK_COL_SPAN)); a wide chunk breaks
         // the chain
         double uj = 0.0;
         bool have_uj = false;
@@ -761,7 +764,7 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
             // optional underflow cutoff: rows that all start more than dt_cut_ex
             // after the wave's latest column give excitation terms below 2^-160
             if (gmax > wave_first && !(Tc - wave_tmax > kc.dt_cut_ex)) {
-                const bool fact = chunk_wide[c] == 0;
+                const bool fact = chunk_wide_col[c] == 0;
                 float G = 0.0f, H = 0.0f;
                 const bool masked = gmin <= wave_first + HK_WAVE - 1;
                 if (fact) {
@@ -894,10 +897,10 @@ static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, d
     hk_prof_mark(p, HK_PROF_COL, true, stream);
     if (d_negH_theta)
         hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->wv,
-                           p->chunk_wide, p->tstep, p->g, p->col_items, p->col_block0, p->colG, kc);
+                           p->chunk_wide_col, p->tstep, p->g, p->col_items, p->col_block0, p->colG, kc);
     else
         hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                           p->wv, p->chunk_wide, p->tstep, p->g, p->col_items, p->col_block0, p->colG, kc);
+                           p->wv, p->chunk_wide_col, p->tstep, p->g, p->col_items, p->col_block0, p->colG, kc);
     hk_prof_mark(p, HK_PROF_COL, false, stream);
     hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->perm, p->n, p->col_item0, p->col_nseg,
                        p->colG, p->a, fc, d_grad_theta, d_negH_theta);
@@ -952,7 +955,7 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 #define HK_FIN(M)                                                                                              \
     hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->ts, d_theta,       \
                        p->perm, p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, fc,             \
-                       p->chunk_wide, p->lam, p->wv, p->a, p->blockpart, p->status)
+                       p->chunk_wide_col, p->lam, p->wv, p->a, p->blockpart, p->status)
     if (mode == HK_MODE_GRAD) HK_ROW(HK_MODE_GRAD);
     else HK_ROW(HK_MODE_HESS);
     hk_prof_mark(p, HK_PROF_ROW, false, stream);

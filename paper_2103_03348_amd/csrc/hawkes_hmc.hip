@@ -413,7 +413,8 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_fin(const double *__restrict__ 
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t i0 = i - threadIdx.x;  // the chunk's first event
     const double dti = ts[i] - ts[i0];
-    const bool wide = __any(i < n && fc.omega * dti > HK_SUB_FACT_SPAN);
+    // the column pass squares its terms: its split limit is HK_COL_SPAN
+    const bool wide = __any(i < n && fc.omega * dti > HK_COL_SPAN);
     if (threadIdx.x == 0) {
         cwide[blockIdx.x] = wide;
         cstep[blockIdx.x] = i0 + HK_WAVE < npad ? exp(-fc.omega * (ts[i0 + HK_WAVE] - ts[i0])) : 0.0;
@@ -490,7 +491,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
     const int pos_last = pos[r_last];
     double Gd = 0.0, Hd = 0.0;
     // the entry's split factor exp(omega (t_j - T_c)), evaluated at the first
-    // split chunk with a causal pair (at most exp(HK_SUB_FACT_SPAN)) and carried
+    // split chunk with a causal pair (at most exp(HK_COL_SPAN)) and carried
     // to later chunks by their step factors
     double uj = 0.0;
     bool have_uj = false;

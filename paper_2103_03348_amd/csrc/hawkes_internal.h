@@ -26,6 +26,13 @@
 // FP32 range.
 #define HK_FACT_SPAN 40.0
 
+// The column pass splits the same factor only for chunks of span at most this
+// over omega.  Its staged weight w_i exp(-omega (t_i - T_c)) is small by up to
+// exp(-span) and Eq. 5 squares it, so a wide split would push the squared
+// terms of small H_j towards FP32 underflow (by up to exp(-2 span) before the
+// column factor restores them); at 8 the loss stays below exp(-16).
+#define HK_COL_SPAN 8.0
+
 // Time offset given to padding events: their pair terms underflow to exactly
 // zero while every square stays finite in FP32.
 #define HK_PAD_DT 1.0e15
@@ -85,6 +92,7 @@ struct hawkes_plan_s {
     float *theta_s;           // [npad] rates in sorted order (FP32), 0 on padding
     float *theta_v;           // [npad] staged rates of the row pass (split time factor applied)
     int *chunk_wide;          // [nchunks] 1 where the chunk takes the direct exponent
+    int *chunk_wide_col;      // [nchunks] the same for the column pass (HK_COL_SPAN)
     double *tstep;            // [nchunks] exp(-omega (T_{c+1} - T_c)) of the last k_tfac
     float *wv;                // [npad] staged column-pass weights w_i exp(-omega (t_i - T_c))
     float *rowpart;           // [n_row_items][HK_NROW][HK_TILE] row partial sums of each piece

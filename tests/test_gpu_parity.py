@@ -73,9 +73,12 @@ def test_small_ragged(gpu, n, seed, ties, dup):
     _check(es, gpu_r, ref, tiny=True)
 
 
-@pytest.mark.parametrize("n,seed", [(300, 31), (700, 32)])
-def test_sparse_fallback(gpu, n, seed):
-    es = synth.small(n, seed=seed, t_end=3.0 * n, ties=2)
+@pytest.mark.parametrize("n,seed,per_event", [(300, 31, 3.0), (700, 32, 3.0), (2000, 33, 1.2)])
+def test_sparse_fallback(gpu, n, seed, per_event):
+    """Chunks that span more than the split's limit take the direct exponent:
+    all of them at 3 time units per event, about half of them at 1.2, where
+    the split factors carried by step factors restart after every such chunk."""
+    es = synth.small(n, seed=seed, t_end=per_event * n, ties=2)
     g = run_gpu(es)
     ref = oracle.evaluate_es(es)
     e = errors(es, g, ref)
@@ -86,6 +89,10 @@ def test_sparse_fallback(gpu, n, seed):
     assert e["g_rel"] < 1e-6
     assert e["h_rel"] < 5e-6
     assert e["h_rel_norm"] < 1e-6
+    # every entry, also the tiny ones of events whose later events are all far:
+    # the column pass must not split the time factor so widely that the squared
+    # terms of Eq. 5 approach FP32 underflow
+    assert e["h_rel_all"] < 3e-5
 
 
 def test_workload_n1000(gpu):
