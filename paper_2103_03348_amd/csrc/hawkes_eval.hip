@@ -253,7 +253,10 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
     __shared__ float colbuf[HK_WAVES][HK_NCOL][HK_WAVE];
     __shared__ double colbuf0[HK_WAVES][HK_WAVE];
     constexpr int NC = MODE == HK_MODE_LOGLIK ? 1 : (MODE == HK_MODE_GRAD ? 3 : 5);
-    const int tid = threadIdx.x, lane = tid & (HK_WAVE - 1), wv = tid / HK_WAVE;
+    // the wavefront index is made visibly uniform, so that the per-wave chunk
+    // bounds below live in scalar registers and select the sweep variant with
+    // scalar branches
+    const int tid = threadIdx.x, lane = tid & (HK_WAVE - 1), wv = __builtin_amdgcn_readfirstlane(tid / HK_WAVE);
     const int q_end = block0[blockIdx.x + 1];
 
     for (int q = block0[blockIdx.x]; q < q_end; ++q) {
@@ -285,19 +288,18 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         for (int c = it.c_end - 1; c >= it.c_begin; --c) {
             if (have_ui) ui *= tstep[c];
             // under the cutoff a chunk that ends more than dt_cut before the
-            // tile's first row is skipped by the whole block: its column
-            // partials are zero
-            if (tile_tmin - ts[(int64_t)c * HK_WAVE + HK_WAVE - 1] > kc.dt_cut) {
-                for (int e = tid; e < NC * HK_WAVE; e += HK_TILE)
-                    cp[(e / HK_WAVE) * stride + (int64_t)c * HK_WAVE + e % HK_WAVE] = 0.0f;
-                continue;
-            }
+            // tile's first row is skipped by the whole block (nothing is staged
+            // and no wave sweeps it): its column partials come out zero.  It
+            // takes the same path as a swept chunk otherwise, which keeps the
+            // accumulators in place across chunks.
+            const double Tlast = ts[(int64_t)c * HK_WAVE + HK_WAVE - 1];
+            const bool block_live = !(tile_tmin - Tlast > kc.dt_cut);
             // times relative to the chunk's first event: for the pairs that carry
             // the sums (close in time) both operands of dt are then small and
             // exact to FP32
             const double Tc = ts[(int64_t)c * HK_WAVE];
             const float ti = (float)(tsi - Tc);
-            if (tid < HK_WAVE) {
+            if (block_live && tid < HK_WAVE) {
                 const int64_t j = (int64_t)c * HK_WAVE + tid;
                 const double tj = ts[j];
                 float2 r;
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
             for (int a = 0; a < HK_NCOL; ++a) C[a] = 0.0f;
             // optional underflow cutoff: a chunk that ends more than dt_cut before
             // the wave's earliest row contributes only terms below 2^-160
-            const bool live = c <= wave_chunk && !(wave_tmin - ts[(int64_t)c * HK_WAVE + HK_WAVE - 1] > kc.dt_cut);
+            const bool live = block_live && c <= wave_chunk && !(wave_tmin - Tlast > kc.dt_cut);
             if (live) {
                 if (fact)
                     row_sweep_masked<MODE, true>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
@@ -725,7 +727,8 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
     __shared__ float rv[HK_WAVE];
     __shared__ double rtd[HK_WAVE];
     __shared__ int rg[HK_WAVE];
-    const int tid = threadIdx.x, wvi = tid / HK_WAVE;
+    // uniform wavefront index: the per-wave bounds select the sweep with scalar branches
+    const int tid = threadIdx.x, wvi = __builtin_amdgcn_readfirstlane(tid / HK_WAVE);
     const int q_end = block0[blockIdx.x + 1];
 
     for (int q = block0[blockIdx.x]; q < q_end; ++q) {
