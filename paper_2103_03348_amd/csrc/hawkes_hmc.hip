@@ -99,6 +99,11 @@ constexpr int64_t SUB_COL_ITEMS = HK_SUB_COL_ITEMS;
 #define HK_SUB_FIN_WAVES 16
 #endif
 constexpr int SUB_FIN_WAVES = HK_SUB_FIN_WAVES;
+// wavefronts per row chunk in the subset row finalisation
+#ifndef HK_SUB_ROWFIN_WAVES
+#define HK_SUB_ROWFIN_WAVES 4
+#endif
+constexpr int SUB_ROWFIN_WAVES = HK_SUB_ROWFIN_WAVES;
 constexpr int64_t SUB_ITEM_BATCHES = 16;
 // unroll of the subset sweeps: 8 measured fastest (104 VGPRs, 4 wavefronts per
 // SIMD); shorter loops fit more wavefronts but lose more instruction-level
@@ -399,35 +404,49 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
     xpart[(int64_t)blockIdx.x * HK_WAVE + lane] = acc;
 }
 
-// One wavefront per 64-row chunk (many blocks in flight for the partial-sum
-// reads); the chunk's sum of log lambda goes to blockpart[chunk].  It also stages
-// the chunk for the subset column pass: w_i = c_e / lambda_i times the split
-// factor exp(-omega (t_i - T_c)), the chunk's split flag and its step factor.
-__global__ __launch_bounds__(HK_WAVE) void k_sub_fin(const double *__restrict__ lam_static,
+// One block per 64-row chunk.  Its SUB_ROWFIN_WAVES wavefronts split the
+// chunk's row items (late chunks have the most, one per run of subset sources
+// before them) and combine their partial sums in a fixed order, so that the
+// partial-sum reads are in flight together; wavefront 0 then finalises the
+// rows.  The chunk's sum of log lambda goes to blockpart[chunk].  It also
+// stages the chunk for the subset column pass: w_i = c_e / lambda_i times the
+// split factor exp(-omega (t_i - T_c)), the chunk's split flag and its step
+// factor.
+__global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const double *__restrict__ lam_static,
                                                  const int *__restrict__ ritem0, const int *__restrict__ rnseg,
                                                  const double *__restrict__ xpart, const double *__restrict__ ts,
                                                  int64_t n, int64_t npad, const FinConst fc,
                                                  double *__restrict__ lam, float *__restrict__ wv,
                                                  int *__restrict__ cwide, double *__restrict__ cstep,
                                                  double *__restrict__ blockpart, int *__restrict__ status) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t i0 = i - threadIdx.x;  // the chunk's first event
+    __shared__ double part[SUB_ROWFIN_WAVES][HK_WAVE];
+    const int b = blockIdx.x, lane = threadIdx.x & (HK_WAVE - 1), wq = threadIdx.x / HK_WAVE;
+    const int64_t i0 = (int64_t)b * HK_WAVE;  // the chunk's first event
+    const int64_t i = i0 + lane;
+    {
+        double x = 0.0;
+        if (i < n) {
+            const double *xp = xpart + (int64_t)ritem0[b] * HK_WAVE + lane;
+            const int ns = rnseg[b];
+#pragma unroll 4
+            for (int sg = wq; sg < ns; sg += SUB_ROWFIN_WAVES) x += xp[(int64_t)sg * HK_WAVE];
+        }
+        part[wq][lane] = x;
+    }
+    __syncthreads();
+    if (wq != 0) return;
     const double dti = ts[i] - ts[i0];
     // the column pass squares its terms: its split limit is HK_COL_SPAN
     const bool wide = __any(i < n && fc.omega * dti > HK_COL_SPAN);
-    if (threadIdx.x == 0) {
-        cwide[blockIdx.x] = wide;
-        cstep[blockIdx.x] = i0 + HK_WAVE < npad ? exp(-fc.omega * (ts[i0 + HK_WAVE] - ts[i0])) : 0.0;
+    if (lane == 0) {
+        cwide[b] = wide;
+        cstep[b] = i0 + HK_WAVE < npad ? exp(-fc.omega * (ts[i0 + HK_WAVE] - ts[i0])) : 0.0;
     }
     double v = 0.0;
     if (i < n) {
-        // the row items of this chunk, in order
-        const int b = (int)(i / HK_WAVE), lane = (int)(i % HK_WAVE);
-        const double *xp = xpart + (int64_t)ritem0[b] * HK_WAVE + lane;
-        double x = 0.0;
-        const int ns = rnseg[b];
-#pragma unroll 4
-        for (int sg = 0; sg < ns; ++sg) x += xp[(int64_t)sg * HK_WAVE];
+        double x = part[0][lane];
+#pragma unroll
+        for (int k = 1; k < SUB_ROWFIN_WAVES; ++k) x += part[k][lane];
         const double l = lam_static[i] + fc.c_e * fc.corr * x;
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
@@ -439,7 +458,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_fin(const double *__restrict__ 
         wv[i] = 0.0f;
     }
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (threadIdx.x == 0) blockpart[blockIdx.x] = v;
+    if (lane == 0) blockpart[b] = v;
 }
 
 // Column pass on the subset: lanes own subset entries (time order), rows are
@@ -919,7 +938,8 @@ static void sub_rows(hawkes_plan p, const double *z, const double *off, double *
                            theta_full);
     hipLaunchKernelGGL(k_sub_row, dim3(s->n_ritems), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->g, s->pos,
                        s->tv, s->sxy, s->sts, s->qwide, s->qstep, s->ritems, kc, s->xpart);
-    hipLaunchKernelGGL(k_sub_fin, dim3(p->nchunks), dim3(HK_WAVE), 0, stream, s->lam_static, s->ritem0, s->rnseg,
+    hipLaunchKernelGGL(k_sub_fin, dim3(p->nchunks), dim3(SUB_ROWFIN_WAVES * HK_WAVE), 0, stream, s->lam_static,
+                       s->ritem0, s->rnseg,
                        s->xpart, p->ts, p->n, p->npad, fc, p->lam, s->wv, s->cwide, s->cstep, p->blockpart,
                        p->status);
 }
