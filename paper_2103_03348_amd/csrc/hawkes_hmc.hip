@@ -99,6 +99,8 @@ constexpr int64_t SUB_COL_ITEMS = HK_SUB_COL_ITEMS;
 #define HK_SUB_FIN_WAVES 16
 #endif
 constexpr int SUB_FIN_WAVES = HK_SUB_FIN_WAVES;
+// partial-sum loads a finalisation wavefront keeps in flight
+constexpr int SUB_FIN_BATCH = 8;
 // wavefronts per row chunk in the subset row finalisation
 #ifndef HK_SUB_ROWFIN_WAVES
 #define HK_SUB_ROWFIN_WAVES 4
@@ -420,34 +422,54 @@ __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const do
                                                  int *__restrict__ cwide, double *__restrict__ cstep,
                                                  double *__restrict__ blockpart, int *__restrict__ status) {
     __shared__ double part[SUB_ROWFIN_WAVES][HK_WAVE];
-    const int b = blockIdx.x, lane = threadIdx.x & (HK_WAVE - 1), wq = threadIdx.x / HK_WAVE;
+    const int b = blockIdx.x, lane = threadIdx.x & (HK_WAVE - 1);
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / HK_WAVE);
     const int64_t i0 = (int64_t)b * HK_WAVE;  // the chunk's first event
     const int64_t i = i0 + lane;
+    // wavefront 0's own operands are fetched before the reduction, so that their
+    // latency overlaps the partial-sum reads
+    double tsi = 0.0, tsc = 0.0, tsnext = 0.0, lst = 0.0;
+    if (wq == 0) {
+        tsi = ts[i];
+        tsc = ts[i0];
+        if (i0 + HK_WAVE < npad) tsnext = ts[i0 + HK_WAVE];
+        if (i < n) lst = lam_static[i];
+    }
     {
         double x = 0.0;
         if (i < n) {
             const double *xp = xpart + (int64_t)ritem0[b] * HK_WAVE + lane;
             const int ns = rnseg[b];
-#pragma unroll 4
-            for (int sg = wq; sg < ns; sg += SUB_ROWFIN_WAVES) x += xp[(int64_t)sg * HK_WAVE];
+            // batches of SUB_FIN_BATCH loads issue together (absent ones read as
+            // zero, which adds exactly); the adds keep the items' order
+            for (int base = wq; base < ns; base += SUB_FIN_BATCH * SUB_ROWFIN_WAVES) {
+                double v[SUB_FIN_BATCH];
+#pragma unroll
+                for (int k = 0; k < SUB_FIN_BATCH; ++k) {
+                    const int sg = base + k * SUB_ROWFIN_WAVES;
+                    v[k] = sg < ns ? xp[(int64_t)sg * HK_WAVE] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < SUB_FIN_BATCH; ++k) x += v[k];
+            }
         }
         part[wq][lane] = x;
     }
     __syncthreads();
     if (wq != 0) return;
-    const double dti = ts[i] - ts[i0];
+    const double dti = tsi - tsc;
     // the column pass squares its terms: its split limit is HK_COL_SPAN
     const bool wide = __any(i < n && fc.omega * dti > HK_COL_SPAN);
     if (lane == 0) {
         cwide[b] = wide;
-        cstep[b] = i0 + HK_WAVE < npad ? exp(-fc.omega * (ts[i0 + HK_WAVE] - ts[i0])) : 0.0;
+        cstep[b] = i0 + HK_WAVE < npad ? exp(-fc.omega * (tsnext - tsc)) : 0.0;
     }
     double v = 0.0;
     if (i < n) {
         double x = part[0][lane];
 #pragma unroll
         for (int k = 1; k < SUB_ROWFIN_WAVES; ++k) x += part[k][lane];
-        const double l = lam_static[i] + fc.c_e * fc.corr * x;
+        const double l = lst + fc.c_e * fc.corr * x;
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
         const double wd = l > 0.0 ? fc.c_e / l : 0.0;
@@ -584,40 +606,71 @@ __global__ __launch_bounds__(SUB_FIN_WAVES * HK_WAVE) void k_sub_colfin(
     const double *__restrict__ a, int64_t m, const FinConst fc, bool with_h, double *__restrict__ gsub,
     double *__restrict__ hsub, const SubUpd u) {
     __shared__ double part[SUB_FIN_WAVES][2][HK_WAVE];
-    const int q = blockIdx.x, lane = threadIdx.x & (HK_WAVE - 1), wq = threadIdx.x / HK_WAVE;
+    const int q = blockIdx.x, lane = threadIdx.x & (HK_WAVE - 1);
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / HK_WAVE);
+    const int64_t r = (int64_t)q * HK_WAVE + lane;
+    const bool fin = wq == 0 && r < m;
+    // the operands of the finalisation and of the update are fetched before the
+    // reduction, so that their latency (a gather through the slot) overlaps the
+    // partial-sum reads; each slot belongs to one entry, so no other thread
+    // writes them in between
+    double ar = 0.0, zk = 0.0, offk = 0.0, pvk = 0.0, pk0 = 0.0, massk = 1.0, dts = 0.0;
+    int k = 0, wide = 1;
+    if (fin) {
+        ar = a[r];
+        if (UPD) {
+            k = u.slot[r];
+            zk = u.z[k];
+            if (u.off) offk = u.off[k];
+            pvk = u.pv[k];
+            pk0 = u.p[k];
+            if (u.a_z != 0.0) {
+                massk = u.mass[k];
+                wide = u.qwide[q];
+                dts = u.sts[r] - u.sts[(int64_t)q * HK_WAVE];
+            }
+        }
+    }
     double G = 0.0, H = 0.0;
     const int ns = nseg[q], i0 = item0[q];
-#pragma unroll 4
-    for (int sg = wq; sg < ns; sg += SUB_FIN_WAVES) {
-        const double *cg = colG + (int64_t)(i0 + sg) * 2 * HK_WAVE + lane;
-        G += cg[0];
-        if (with_h) H += cg[HK_WAVE];
+    // batches of SUB_FIN_BATCH loads issue together (absent ones read as zero,
+    // which adds exactly); the adds keep the items' order
+    for (int base = wq; base < ns; base += SUB_FIN_BATCH * SUB_FIN_WAVES) {
+        double vg[SUB_FIN_BATCH], vh[SUB_FIN_BATCH];
+#pragma unroll
+        for (int k = 0; k < SUB_FIN_BATCH; ++k) {
+            const int sg = base + k * SUB_FIN_WAVES;
+            const double *cg = colG + (int64_t)(i0 + sg) * 2 * HK_WAVE + lane;
+            vg[k] = sg < ns ? cg[0] : 0.0;
+            vh[k] = with_h && sg < ns ? cg[HK_WAVE] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < SUB_FIN_BATCH; ++k) {
+            G += vg[k];
+            H += vh[k];
+        }
     }
     part[wq][0][lane] = G;
     part[wq][1][lane] = H;
     __syncthreads();
-    const int64_t r = (int64_t)q * HK_WAVE + lane;
-    if (wq != 0 || r >= m) return;
+    if (!fin) return;
     double Gs = part[0][0][lane], Hs = part[0][1][lane];
-    for (int k = 1; k < SUB_FIN_WAVES; ++k) {
-        Gs += part[k][0][lane];
-        Hs += part[k][1][lane];
+    for (int w = 1; w < SUB_FIN_WAVES; ++w) {
+        Gs += part[w][0][lane];
+        Hs += part[w][1][lane];
     }
-    const double g = Gs * fc.corr - a[r];
+    const double g = Gs * fc.corr - ar;
     gsub[r] = g;
     if (with_h) hsub[r] = Hs * fc.corr * fc.corr;
     if (UPD) {
-        const int k = u.slot[r];
-        const double zk = u.z[k];
-        const double gz = exp(u.off ? zk + u.off[k] : zk) * g - u.pv[k] * u.inv_s2;
-        const double pk = u.p[k] + u.a_p * gz;
+        const double gz = exp(u.off ? zk + offk : zk) * g - pvk * u.inv_s2;
+        const double pk = pk0 + u.a_p * gz;
         u.p[k] = pk;
         if (u.a_z != 0.0) {
-            const double zn = zk + u.a_z * pk / u.mass[k];
+            const double zn = zk + u.a_z * pk / massk;
             u.z[k] = zn;
-            const double ze = u.off ? zn + u.off[k] : zn;
-            const int64_t r0 = (int64_t)q * HK_WAVE;
-            u.tv[r] = (float)exp(u.qwide[q] ? ze : ze + u.omega * (u.sts[r] - u.sts[r0]));
+            const double ze = u.off ? zn + offk : zn;
+            u.tv[r] = (float)exp(wide ? ze : ze + u.omega * dts);
         }
     }
 }
