@@ -365,25 +365,42 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
     double ui = 0.0;
     bool have_ui = false;
     const int c_last = it.c_begin + (it.c_end - 1 - it.c_begin) / HK_WAVE * HK_WAVE;
+    // a batch's entries are loaded into registers one batch ahead, so that the
+    // loads of the next batch are in flight during this one's sweep (the subset
+    // arrays are padded to whole 256-entry tiles: every lane's load is in bounds)
+    double2 nxy = sxy[c_last + lane];
+    float nv = tv[c_last + lane];
+    double nt = sts[c_last + lane];
+    int np = pos[c_last + lane];
     for (int c0 = c_last; c0 >= it.c_begin; c0 -= HK_WAVE) {
         const int q = c0 / HK_WAVE;
         if (have_ui) ui *= qstep[q];
         const int cend = min(c0 + HK_WAVE, it.c_end);
+        const double2 pxy = nxy;
+        const float pv = nv;
+        const double pt = nt;
+        const int pp = np;
+        if (c0 - HK_WAVE >= it.c_begin) {
+            const int rn = c0 - HK_WAVE + lane;
+            nxy = sxy[rn];
+            nv = tv[rn];
+            nt = sts[rn];
+            np = pos[rn];
+        }
         if (chunk_tmin - sts[cend - 1] > kc.dt_cut_ex) continue;
         const bool fact = qwide[q] == 0;
         {
-            const int r = c0 + lane;
-            const bool valid = r < cend;
-            rxy[lane] = sxy[r];
-            rv[lane] = valid ? tv[r] : 0.0f;
-            rtd[lane] = sts[r];
-            rpos[lane] = valid ? pos[r] : 0x7fffffff;
+            const bool valid = c0 + lane < cend;
+            rxy[lane] = pxy;
+            rv[lane] = valid ? pv : 0.0f;
+            rtd[lane] = pt;
+            rpos[lane] = valid ? pp : 0x7fffffff;
         }
         __syncthreads();
         double accb = 0.0;
         // a batch whose entries all precede the chunk's first tie group needs no
         // causality mask (padding entries carry rate 0)
-        if (pos[cend - 1] < g_first) {
+        if (rpos[cend - 1 - c0] < g_first) {
             if (fact) sub_row_sweep<false, true>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
             else sub_row_sweep<false, false>(rxy, rv, rtd, rpos, tsi, xr, yr, gr, kc, accb);
         } else {
@@ -393,7 +410,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
         if (accb != 0.0) {
             if (fact) {
                 if (!have_ui) {
-                    ui = exp(-kc.omega * (tsi - sts[c0]));
+                    ui = exp(-kc.omega * (tsi - rtd[0]));
                     have_ui = true;
                 }
                 acc += ui * accb;
@@ -536,22 +553,43 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
     // to later chunks by their step factors
     double uj = 0.0;
     bool have_uj = false;
+    // a row chunk is loaded into registers one chunk ahead, so that the loads of
+    // the next chunk are in flight during this one's sweep (items are never empty)
+    int nx, ny, ng;
+    float nw;
+    double nt;
+    {
+        const int64_t i = (int64_t)it.c_begin * HK_WAVE + lane;
+        nx = xi[i];
+        ny = yi[i];
+        nw = wv[i];
+        nt = ts[i];
+        ng = g[i];
+    }
     for (int c = it.c_begin; c < it.c_end; ++c) {
         if (have_uj) uj *= cstep[c - 1];
+        const int px = nx, py = ny, pg = ng;
+        const float pw = nw;
+        const double pt = nt;
+        if (c + 1 < it.c_end) {
+            const int64_t i = (int64_t)(c + 1) * HK_WAVE + lane;
+            nx = xi[i];
+            ny = yi[i];
+            nw = wv[i];
+            nt = ts[i];
+            ng = g[i];
+        }
         const double Tc = ts[(int64_t)c * HK_WAVE];
         if (Tc - q_tmax > kc.dt_cut_ex) break;  // cutoff: all later rows too far
         const bool fact = cwide[c] == 0;
-        {
-            const int64_t i = (int64_t)c * HK_WAVE + lane;
-            rxy[lane] = make_double2((double)xi[i] * kc.sx, (double)yi[i] * kc.sx);
-            rv[lane] = wv[i];
-            rtd[lane] = ts[i];
-            rg[lane] = g[i];
-        }
+        rxy[lane] = make_double2((double)px * kc.sx, (double)py * kc.sx);
+        rv[lane] = pw;
+        rtd[lane] = pt;
+        rg[lane] = pg;
         __syncthreads();
         float G = 0.0f, H = 0.0f;
         // rows whose tie groups all start after the chunk's last entry need no mask
-        if (pos_last < g[(int64_t)c * HK_WAVE]) {
+        if (pos_last < rg[0]) {
             if (fact) sub_col_sweep<WITH_H, false, true>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
             else sub_col_sweep<WITH_H, false, false>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
         } else {
