@@ -86,12 +86,15 @@ namespace {
 // each, and at most SUB_ITEM_BATCHES 64-wide batches per item, so that the
 // few items that still have work under the underflow cutoff stay short) so
 // that the whole chip takes part; partial sums per item are combined in a
-// fixed order afterwards.
+// fixed order afterwards.  Measured on the N = 23,422 HMC iteration (M = 1,610):
+// column items 4096 -> 8192 (one row chunk per item there) 0.616 -> 0.607 ms,
+// 2048 0.623 ms; row items 4096 0.639 ms, 16384 no change (one batch per item
+// already).
 #ifndef HK_SUB_ROW_ITEMS
 #define HK_SUB_ROW_ITEMS 8192
 #endif
 #ifndef HK_SUB_COL_ITEMS
-#define HK_SUB_COL_ITEMS 4096
+#define HK_SUB_COL_ITEMS 8192
 #endif
 constexpr int64_t SUB_ROW_ITEMS = HK_SUB_ROW_ITEMS;
 constexpr int64_t SUB_COL_ITEMS = HK_SUB_COL_ITEMS;
@@ -99,7 +102,8 @@ constexpr int64_t SUB_COL_ITEMS = HK_SUB_COL_ITEMS;
 #define HK_SUB_FIN_WAVES 16
 #endif
 constexpr int SUB_FIN_WAVES = HK_SUB_FIN_WAVES;
-// partial-sum loads a finalisation wavefront keeps in flight
+// partial-sum loads a finalisation wavefront keeps in flight (16 in the
+// column finalisation measured slower: 4.95 -> 5.7 us at N = 23,422)
 constexpr int SUB_FIN_BATCH = 8;
 // wavefronts per row chunk in the subset row finalisation
 #ifndef HK_SUB_ROWFIN_WAVES
@@ -727,29 +731,53 @@ __global__ void k_sub_scatter(const int *__restrict__ slot, int64_t m, const dou
 // Deterministic single-block sums over the subset (m is at most a few 1e4).
 // out[0] = sum log lambda (from block partials), out[1] = sum theta_k a_k,
 // out[2] = sum z_k^2, out[3] = sum p_k^2 / M_k
-__global__ __launch_bounds__(256) void k_sub_energy(const double *__restrict__ loglam_part, int nb,
+constexpr int ENERGY_THREADS = 1024;
+constexpr int ENERGY_BATCH = 4;
+__global__ __launch_bounds__(ENERGY_THREADS) void k_sub_energy(const double *__restrict__ loglam_part, int nb,
                                                     const double *__restrict__ z, const double *__restrict__ off,
                                                     const double *__restrict__ p,
                                                     const double *__restrict__ mass, const int *__restrict__ slot,
                                                     const double *__restrict__ a, int64_t m,
                                                     double *__restrict__ out) {
-    __shared__ double sh[4][256];
+    __shared__ double sh[4][ENERGY_THREADS];
+    const int t = threadIdx.x;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nb; b += 256) s[0] += loglam_part[b];
-    for (int64_t r = threadIdx.x; r < m; r += 256) {
-        const int k = slot[r];
-        s[1] += exp(zeff(z, off, k)) * a[r];
-        s[2] += z[k] * z[k];
-        if (p) s[3] += p[k] * p[k] / mass[k];
+    for (int b = t; b < nb; b += ENERGY_THREADS) s[0] += loglam_part[b];
+    // a thread's entries are gathered ENERGY_BATCH at a time (the loads through
+    // the slot issue together), then summed in entry order
+    for (int64_t base = t; base < m; base += (int64_t)ENERGY_BATCH * ENERGY_THREADS) {
+        int k[ENERGY_BATCH];
+        double zk[ENERGY_BATCH], ok[ENERGY_BATCH], pk[ENERGY_BATCH], mk[ENERGY_BATCH], ak[ENERGY_BATCH];
+#pragma unroll
+        for (int e = 0; e < ENERGY_BATCH; ++e) {
+            const int64_t r = base + (int64_t)e * ENERGY_THREADS;
+            k[e] = r < m ? slot[r] : 0;
+            ak[e] = r < m ? a[r] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < ENERGY_BATCH; ++e) {
+            const bool in = base + (int64_t)e * ENERGY_THREADS < m;
+            zk[e] = in ? z[k[e]] : 0.0;
+            ok[e] = in && off ? off[k[e]] : 0.0;
+            pk[e] = in && p ? p[k[e]] : 0.0;
+            mk[e] = in && p ? mass[k[e]] : 1.0;
+        }
+#pragma unroll
+        for (int e = 0; e < ENERGY_BATCH; ++e) {
+            if (base + (int64_t)e * ENERGY_THREADS >= m) break;
+            s[1] += exp(off ? zk[e] + ok[e] : zk[e]) * ak[e];
+            s[2] += zk[e] * zk[e];
+            if (p) s[3] += pk[e] * pk[e] / mk[e];
+        }
     }
-    for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = s[q];
+    for (int q = 0; q < 4; ++q) sh[q][t] = s[q];
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
-            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + h];
+    for (int h = ENERGY_THREADS / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int q = 0; q < 4; ++q) sh[q][t] += sh[q][t + h];
         __syncthreads();
     }
-    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+    if (t < 4) out[t] = sh[t][0];
 }
 
 // ---- Philox-4x32-10 (Salmon et al. 2011) ------------------------------------------------
@@ -1117,7 +1145,7 @@ extern "C" hawkes_status hawkes_subset_grad(hawkes_plan p, const hawkes_hyper *h
     hipLaunchKernelGGL(k_sub_scatter, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->slot, s->m, s->gsub, s->hsub,
                        d_grad_sub, d_negH_sub);
     if (d_loglik) {
-        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nchunks, s->z0,
+        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(ENERGY_THREADS), 0, stream, p->blockpart, p->nchunks, s->z0,
                            (const double *)nullptr, (const double *)nullptr, (const double *)nullptr, s->slot, s->a,
                            s->m, s->scal);
         hipLaunchKernelGGL(k_sub_loglik_out, dim3(1), dim3(64), 0, stream, s->scal, s->Lam_static, d_loglik);
@@ -1157,7 +1185,7 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
     // start of the trajectory: the energy at z0, then the gradient there and the
     // first half kick and drift (fused into the column finalisation)
     sub_rows(p, a->d_z, off, a->d_theta, true, kc, fc, stream);
-    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nchunks, a->d_z, off, s->p,
+    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(ENERGY_THREADS), 0, stream, p->blockpart, p->nchunks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal);
     // phylogenetic prior: the quadratic form z^T V^{-1} z replaces sum z^2
     if (tree && (st = hk_tree_launch(p, a->d_z, s->vz, s->scal + 2, stream)) != HAWKES_OK) return st;
@@ -1174,7 +1202,7 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
         upd.a_z = last ? 0.0 : a->eps;
         sub_cols(p, false, kc, fc, &upd, stream);
     }
-    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nchunks, a->d_z, off, s->p,
+    hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(ENERGY_THREADS), 0, stream, p->blockpart, p->nchunks, a->d_z, off, s->p,
                        a->d_mass, s->slot, s->a, m, s->scal + 4);
     if (tree && (st = hk_tree_launch(p, a->d_z, nullptr, s->scal + 6, stream)) != HAWKES_OK) return st;
     hipLaunchKernelGGL(k_hmc_accept, dim3(1), dim3(256), 0, stream, s->scal, s->Lam_static, inv_s2, a->seed,
@@ -1207,7 +1235,7 @@ extern "C" hawkes_status hawkes_subset_trend_grad(hawkes_plan p, const hawkes_hy
         hipLaunchKernelGGL(k_sub_trend_out, dim3(1), dim3(256), 0, stream, s->slot, s->pos, p->ts, s->m, s->gsub, d_z,
                            off, d_grad_z, d_grad_beta);
     if (d_loglik) {
-        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(256), 0, stream, p->blockpart, p->nchunks, d_z, off,
+        hipLaunchKernelGGL(k_sub_energy, dim3(1), dim3(ENERGY_THREADS), 0, stream, p->blockpart, p->nchunks, d_z, off,
                            (const double *)nullptr, (const double *)nullptr, s->slot, s->a, s->m, s->scal);
         hipLaunchKernelGGL(k_sub_loglik_out, dim3(1), dim3(64), 0, stream, s->scal, s->Lam_static, d_loglik);
     }
