@@ -41,14 +41,23 @@ def _subset_grad(plan, es, theta, refresh=0):
     return float(ll.item()), g.cpu().numpy(), h.cpu().numpy()
 
 
-@pytest.mark.parametrize("cfg", ["small", "allfree", "n23422"])
+@pytest.mark.parametrize("cfg", ["small", "allfree", "dense", "n23422"])
 def test_subset_grad_matches_oracle(gpu, cfg):
     """Eq. 1, 4, 5 restricted to the free rates, by the cached-static O(N M) path
-    (allfree: every rate free, so the static part holds the background only)."""
+    (allfree: every rate free, so the static part holds the background only;
+    dense: the latest 2,500 of 3,000 events free, so that late row chunks have
+    up to 40 row items each and their finalisation takes more than one round of
+    batched reads)."""
     if cfg == "small":
         es = synth.small(1500, seed=21, ties=6, all_free=False)
     elif cfg == "allfree":
         es = synth.small(333, seed=22, ties=5, all_free=True)
+    elif cfg == "dense":
+        import dataclasses
+
+        es = synth.small(3000, seed=23, ties=4, all_free=False)
+        sub = np.sort(np.argsort(es.t, kind="stable")[500:]).astype(np.int64)
+        es = dataclasses.replace(es, subset=sub, z=np.log(es.theta[sub]))
     else:
         es = synth.config(1)
     plan, idx = _setup(es)
