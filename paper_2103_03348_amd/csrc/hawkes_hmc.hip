@@ -111,9 +111,10 @@ constexpr int SUB_FIN_BATCH = 8;
 #endif
 constexpr int SUB_ROWFIN_WAVES = HK_SUB_ROWFIN_WAVES;
 constexpr int64_t SUB_ITEM_BATCHES = 16;
-// unroll of the subset sweeps: 8 measured fastest (104 VGPRs, 4 wavefronts per
+// unroll of the subset sweeps: 8 measured fastest (114 VGPRs, 4 wavefronts per
 // SIMD); shorter loops fit more wavefronts but lose more instruction-level
-// parallelism than that hides (N = 23,422 HMC iteration: 4 -> +2%, 1 -> +20%)
+// parallelism than that hides (N = 23,422 HMC iteration, 0.603 ms at 8: 4 ->
+// +1.5%, 6 -> +5%, 16 -> +8%, 1 -> +20%)
 #ifndef HK_SUB_UNROLL
 #define HK_SUB_UNROLL 8
 #endif
