@@ -681,16 +681,16 @@ __global__ __launch_bounds__(SUB_FIN_WAVES * HK_WAVE) void k_sub_colfin(
     for (int base = wq; base < ns; base += SUB_FIN_BATCH * SUB_FIN_WAVES) {
         double vg[SUB_FIN_BATCH], vh[SUB_FIN_BATCH];
 #pragma unroll
-        for (int k = 0; k < SUB_FIN_BATCH; ++k) {
-            const int sg = base + k * SUB_FIN_WAVES;
+        for (int e = 0; e < SUB_FIN_BATCH; ++e) {
+            const int sg = base + e * SUB_FIN_WAVES;
             const double *cg = colG + (int64_t)(i0 + sg) * 2 * HK_WAVE + lane;
-            vg[k] = sg < ns ? cg[0] : 0.0;
-            vh[k] = with_h && sg < ns ? cg[HK_WAVE] : 0.0;
+            vg[e] = sg < ns ? cg[0] : 0.0;
+            vh[e] = with_h && sg < ns ? cg[HK_WAVE] : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < SUB_FIN_BATCH; ++k) {
-            G += vg[k];
-            H += vh[k];
+        for (int e = 0; e < SUB_FIN_BATCH; ++e) {
+            G += vg[e];
+            H += vh[e];
         }
     }
     part[wq][0][lane] = G;
