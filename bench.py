@@ -403,7 +403,7 @@ def main():
             "n_free_rates": int(es.subset.shape[0]),
             "pairs_per_step": pairs,
             "outputs": "loglik, grad_theta[N], grad_hyper[6], negH_theta[N], negH_hyper[6]",
-            "precision": "FP32 pair terms, compensated sums, FP64 finals",
+            "precision": "FP32 pair terms; FP64 per-term sums for lambda, FP32 per chunk and FP64 across chunks for the moments; FP64 finals",
         },
         "roofline": {
             "bound": "alu",
