@@ -312,19 +312,111 @@ def test_hmc_samples_prior_when_no_excitation():
     assert abs(d.var() - sig ** 2) < 0.04
 
 
-def test_hmc_leapfrog_reversible_and_second_order():
-    """Leapfrog is time-reversible (negating the final momentum retraces the path)
-    and its energy error shrinks as eps^2."""
+def test_hmc_leapfrog_reversible():
+    """Leapfrog is time-reversible: L steps forward, the momentum negated, L steps
+    back return to the starting point (z0, -p0) up to FP64 rounding (Sec. 2.3.2;
+    Neal 2011, Sec. 2.3).  Catches a kick or drift taken with the wrong step, a
+    missing half kick or a gradient evaluated at the wrong point -- each breaks
+    the symmetry of the integrator.  Checked with the iid prior, with the temporal
+    trend and with a dense Eq. 2 covariance."""
+    from oracle import hmc, tree as otree
+    es = _es(25, seed=52)
+    idx = np.arange(0, 25, 3)
+    m = idx.shape[0]
+    z0 = np.log(es.theta[idx]) + 0.1
+    mass = np.linspace(3.0, 9.0, m)
+    p0 = np.random.default_rng(52).standard_normal(m) * np.sqrt(mass)
+    par, ln = synth.coalescent_tree(m, seed=5, scale=float(m))
+    for beta, V in ((0.0, None), (-0.02, None), (0.0, otree.covariance(par, ln, 0.7))):
+        z1, p1, _, _ = hmc.leapfrog(es.t, es.x, es.y, es.theta, idx, z0, p0, mass, es.hyper, 0.0, 0.05, 12, 0.5,
+                                    beta, V)
+        assert np.max(np.abs(z1 - z0)) > 1e-3          # the path went somewhere
+        z2, p2, _, _ = hmc.leapfrog(es.t, es.x, es.y, es.theta, idx, z1, -p1, mass, es.hyper, 0.0, 0.05, 12, 0.5,
+                                    beta, V)
+        np.testing.assert_allclose(z2, z0, rtol=0, atol=1e-10)
+        np.testing.assert_allclose(-p2, p0, rtol=0, atol=1e-10)
+
+
+def test_hmc_leapfrog_second_order():
+    """The leapfrog's energy error over a fixed trajectory length shrinks as eps^2."""
     from oracle import hmc
     es = _es(25, seed=52)
     idx = np.arange(0, 25, 3)
     z0 = np.log(es.theta[idx])
     mass = np.full(idx.shape[0], 4.0)
     errs = []
-    for eps in (0.02, 0.01):
-        r = hmc.hmc_iteration(es.t, es.x, es.y, es.theta, idx, z0, mass, es.hyper, 0.0, eps, 10, 0.5, 9, 0)
+    for eps, L in ((0.04, 5), (0.02, 10), (0.01, 20)):
+        r = hmc.hmc_iteration(es.t, es.x, es.y, es.theta, idx, z0, mass, es.hyper, 0.0, eps, L, 0.5, 9, 0)
         errs.append(abs(r["dH"]))
-    assert errs[1] < errs[0] / 3.0
+    assert errs[1] == pytest.approx(errs[0] / 4.0, rel=0.1)
+    assert errs[2] == pytest.approx(errs[1] / 4.0, rel=0.1)
+
+
+def _z_grad(es, idx, z, beta, sigma, V):
+    """d log pi / dz from the oracle: the chain-rule gradient of Eq. 1 (itself
+    pinned by finite differences in test_fd_temporal_trend_gradient) plus the
+    prior's gradient (pinned against scipy in test_tree_prior_closed_form_and_scipy)."""
+    from oracle import hmc, tree as otree
+    _, gz, _ = hmc.trend_grad(es.t, es.x, es.y, es.theta, idx, z, beta, es.hyper, es.t0)
+    if V is None:
+        return gz - z / sigma ** 2
+    return gz + otree.logpdf_and_grad(z, V, sigma)[1]
+
+
+@pytest.mark.parametrize("case", ["iid", "trend", "tree"])
+def test_z_hessian_diag_by_finite_differences(case):
+    """The exact z-space curvature -d2 log pi / dz_k^2 = theta^2 H - theta g + P_kk
+    (Eq. 4, Eq. 5 through theta_k = exp(z_k + beta t_k), P the prior precision)
+    against central differences of the log-posterior gradient in z_k (step 1e-5).
+    A sign slip in the -theta g term, a missing square on theta, a rate taken
+    as exp(z) while beta != 0 or the wrong prior precision each fail here."""
+    from oracle import hmc, tree as otree
+    es = _es(70, seed=61, ties=2)
+    idx = np.arange(1, es.n, 4)
+    m = idx.shape[0]
+    z = 0.3 * np.random.default_rng(61).standard_normal(m)
+    sigma = 0.7
+    beta = -0.03 if case == "trend" else 0.0
+    V = None
+    if case == "tree":
+        par, ln = synth.coalescent_tree(m, seed=7, scale=float(m))
+        V = otree.covariance(par, ln, 0.6)
+    ref = hmc.z_hessian_diag(es.t, es.x, es.y, es.theta, idx, z, es.hyper, es.t0, sigma, beta=beta, prior_v=V)
+    step = 1e-5
+    checked = 0
+    for k in range(0, m, 3):
+        zp, zm = z.copy(), z.copy()
+        zp[k] += step
+        zm[k] -= step
+        fd = -(_z_grad(es, idx, zp, beta, sigma, V)[k] - _z_grad(es, idx, zm, beta, sigma, V)[k]) / (2 * step)
+        assert ref[k] == pytest.approx(fd, rel=1e-6, abs=1e-8), (case, k)
+        checked += 1
+    assert checked >= 5
+    # the likelihood part is not negligible here: the check sees the -theta g and theta^2 H terms
+    lik = ref - hmc.prior_precision_diag(m, sigma, V)
+    assert np.max(np.abs(lik)) > 0.05 * np.median(hmc.prior_precision_diag(m, sigma, V))
+
+
+def test_prior_precision_diag_is_conditional_precision():
+    """(V^{-1})_kk is the inverse of the conditional variance of tip k given the
+    other tips.  On the three-tip tree ((0, 1), 2) with root factor tau0, the
+    conditional variance of tip 0 follows by hand from the Brownian motion of
+    Eq. 2: the root given tip 2, then the parent of tips 0 and 1 given tip 1 and
+    the root side, then tip 0's own branch.  The oracle's dense inverse must
+    agree; an inverse taken of the wrong matrix or a missing 1/sigma^2 fails."""
+    from oracle import hmc
+    w0, w1, w2, w3, tau0 = 0.4, 0.9, 1.3, 0.5, 0.8
+    # nodes 0, 1, 2 tips; 3 = parent of (0, 1), branch w3 to the root 4; tip 2 hangs off the root
+    V = np.array([[tau0 + w3 + w0, tau0 + w3, tau0],
+                  [tau0 + w3, tau0 + w3 + w1, tau0],
+                  [tau0, tau0, tau0 + w2]])
+    P = hmc.prior_precision_diag(3, 1.0, V)
+    # conditional variance of tip 0: the ancestor node 3 given tips 1 and 2 combines
+    # the message from tip 1 (variance w1) and from the root side (w3 + (tau0 given tip 2))
+    root_given_2 = 1.0 / (1.0 / tau0 + 1.0 / w2)
+    node3 = 1.0 / (1.0 / w1 + 1.0 / (w3 + root_given_2))
+    assert P[0] == pytest.approx(1.0 / (w0 + node3), rel=1e-13)
+    assert np.all(hmc.prior_precision_diag(4, 0.5) == 4.0)
 
 
 def test_mlp_gradient_by_finite_differences():
@@ -357,6 +449,37 @@ def test_mlp_forward_closed_form_and_adam_first_step():
     g = np.random.default_rng(1).standard_normal(mlp.N_PARAMS)
     new, m, v = mlp.adam_step(flat, g, np.zeros_like(g), np.zeros_like(g), 1, lr=1e-3)
     np.testing.assert_allclose(new - flat, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-9)
+
+
+def test_adam_later_steps_closed_forms():
+    """Adam (Kingma & Ba 2015) over several steps, against closed forms of its
+    moment recursions rather than the recursions themselves:
+      * a constant gradient g: the bias-corrected moments are g and g^2 at every
+        step, so after k steps each parameter has moved by -k lr g / (|g| + eps);
+      * an alternating gradient (-1)^t g: the first moment is the geometric sum
+        m_t = (1 - b1) g (-1)^t (1 - (-b1)^t) / (1 + b1) and the second is still
+        (1 - b2^t) g^2, so step t moves by
+        -lr (-1)^t (1 - b1) (1 - (-b1)^t) / ((1 + b1)(1 - b1^t)) g / (|g| + eps).
+    A wrong decay exponent in the bias correction, or moments not carried from
+    step to step, fail these."""
+    from oracle import mlp
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal(mlp.N_PARAMS)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    p = np.zeros(mlp.N_PARAMS)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t in range(1, 8):
+        p, m, v = mlp.adam_step(p, g, m, v, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        np.testing.assert_allclose(p, -t * lr * g / (np.abs(g) + eps), rtol=1e-9)
+    p = np.zeros(mlp.N_PARAMS)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t in range(1, 8):
+        prev = p.copy()
+        p, m, v = mlp.adam_step(p, (-1.0) ** t * g, m, v, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        mhat_over_g = (-1.0) ** t * (1 - b1) * (1 - (-b1) ** t) / ((1 + b1) * (1 - b1 ** t))
+        np.testing.assert_allclose(p - prev, -lr * mhat_over_g * g / (np.abs(g) + eps), rtol=1e-8)
 
 
 def test_features_small_hand_case():
