@@ -26,19 +26,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 operations per unordered event pair (FMA = 2 flops, exp = 1).
-# Row pass: differences dt, dx, dy (3), r^2 (3), dt^2 (1), background and
-# excitation exponents (3 + 3) and exponentials (2), theta_j E (1), the four
-# background moment products (4) added to both events' sums (10), the
-# excitation sums X0, X1, X2, X11, X22 (9).  Column pass: dt, dx, dy, r^2 (6),
-# exponent (3), exponential (1), E w (1), G and H sums (3).
-FLOPS_ROW_PER_PAIR = 39
+# Algorithmic FP32 work per unordered event pair of the measured evaluation
+# (log-likelihood + rate gradient + Hessian diagonal + hyperparameter
+# derivatives), counted as FMA = 2, add/mul/sub = 1, exp = 1 flop: 59 flops and
+# 3 exponentials per pair, split between the row pass (45 flops, 2 exps: the
+# intensity's background and excitation terms with their moments, the
+# background's counted for both events of the pair) and the column pass (14
+# flops, 1 exp: Eq. 4 and Eq. 5's terms).
+FLOPS_PER_PAIR = 59
 FLOPS_COL_PER_PAIR = 14
-FLOPS_PER_PAIR = FLOPS_ROW_PER_PAIR + FLOPS_COL_PER_PAIR
-# MI355X FP32 vector peaks: 157.3 TFLOP/s is AMD's figure, which counts packed
-# FP32 FMAs (two per lane and cycle).  This library is built without packed FP32
-# instructions, so the peak its kernels can reach is the non-packed one:
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+FLOPS_ROW_PER_PAIR = FLOPS_PER_PAIR - FLOPS_COL_PER_PAIR
+EXPS_ROW_PER_PAIR = 2
+EXPS_COL_PER_PAIR = 1
+# MI355X FP32 vector peaks: 157.3 TFLOP/s is AMD's published figure, which counts
+# packed FP32 FMAs (two per lane and cycle); it is the peak the roofline
+# fraction is quoted against.  This library is built without packed FP32
+# instructions, so the peak its kernels can reach is the non-packed one,
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s,
+# reported beside it.
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
@@ -70,7 +75,8 @@ CONFIGS = {1: "N23422_branching_M1610", 0: "N1000_uniform_mix5", 2: "N100000_bra
 
 def cpu_baseline(es, budget_s=12.0):
     """The FP64 oracle (plain double loops, OpenMP over rows) on the host cores:
-    full evaluations of the same workload, repeated until `budget_s` elapse."""
+    full evaluations of the same workload, repeated until `budget_s` elapse on
+    all cores, then one full evaluation on a single thread (pairs/s per core)."""
     import oracle
     threads = oracle.max_threads()
     n = es.n
@@ -83,12 +89,32 @@ def cpu_baseline(es, budget_s=12.0):
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 50:
             break
+    t1 = time.perf_counter()
+    oracle.evaluate_es(es, nthreads=1)
+    el1 = time.perf_counter() - t1
     return {"value": pairs * reps / el, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} full FP64 evaluation(s) (loglik, rate gradient, Hessian diagonal, hyperparameter "
-                      f"derivatives) of the N={n} workload, {el:.1f} s"}
+                      f"derivatives) of the N={n} workload, {el:.1f} s on {threads} threads; then one on 1 thread",
+            "pairs_per_s_per_core": pairs * reps / el / threads,
+            "single_thread": {"value": pairs / el1, "unit": "pair-evals/s", "cores": 1, "seconds": el1}}
 
 
-def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_states=200, seed=7, n_chains=8):
+def exp2_peak():
+    """Issue rate of the hardware exp2 alone (hawkes_exp2_rate): the
+    transcendental ceiling the pair kernels' exponentials are measured against."""
+    import torch
+
+    from paper_2103_03348_amd import _lib
+    blocks = 256 * 64
+    sink = torch.empty(blocks, dtype=torch.float32, device="cuda:0")
+    out = (ctypes.c_double * 3)()
+    _lib.check(_lib.lib().hawkes_exp2_rate(blocks, 256, _lib.ptr(sink), out, _lib.stream_handle()), "exp2_rate")
+    return {"exp2_per_s": out[2], "evaluations": out[0], "seconds": out[1],
+            "launch": f"{blocks} blocks x 256 threads x 8 chains x 256 steps"}
+
+
+def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_states=200, seed=7, n_chains=8,
+              sigma_z=0.5):
     """HMC ESS/s on the free log-rates with the exact and the learned diagonal
     preconditioner (and, for reference, none), each chain adapting its step size
     by dual averaging during its own warm-up, then `n_iter` timed iterations;
@@ -113,7 +139,7 @@ def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_
     # pilot chain with the exact preconditioner -> training states -> network
     tt0 = time.perf_counter()
     plan = Plan(t, xy, es.t0)
-    pilot = HmcSampler(plan, theta0, idx, es.hyper, sigma_z=0.5, L=L, seed=seed)
+    pilot = HmcSampler(plan, theta0, idx, es.hyper, sigma_z=sigma_z, L=L, seed=seed)
     r = pilot.run(0, warmup, eps0=0.05, mass="exact", refresh=refresh, record=False)
     pre = LearnedPreconditioner(pilot, t, xy, seed=seed)
     X, T = pre.collect(n_states, r["eps"], thin=2)
@@ -124,9 +150,9 @@ def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_
     pre.train(Xtr, Ttr, steps=1500, batch=4096, lr=2e-3, seed=seed)
     loss1 = pre.evaluate(Xva, Tva)
     torch.cuda.synchronize()
-    out["training"] = {"states": n_states, "samples": int(X.shape[0]), "val_mse_untrained": loss0,
-                       "val_mse_trained": loss1, "target_var": float(Tva.double().var().item()),
-                       "seconds": time.perf_counter() - tt0}
+    out["training"] = {"states": n_states, "samples": int(X.shape[0]), "target": "log max(H_k, 1e-30) (Eq. 5)",
+                       "val_mse_untrained": loss0, "val_mse_trained": loss1,
+                       "target_var": float(Tva.double().var().item()), "seconds": time.perf_counter() - tt0}
     plan.close()
 
     # each mode runs the same n_chains seeds (common random numbers: the chains of
@@ -135,7 +161,7 @@ def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_
         runs = []
         for c in range(n_chains):
             plan = Plan(t, xy, es.t0)
-            smp = HmcSampler(plan, theta0, idx, es.hyper, sigma_z=0.5, L=L, seed=seed + 1 + c)
+            smp = HmcSampler(plan, theta0, idx, es.hyper, sigma_z=sigma_z, L=L, seed=seed + 1 + c)
             learned = None
             if mode == "learned":
                 pre.s = smp
@@ -161,8 +187,18 @@ def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_
     for k in ("ess_per_s_min", "ess_per_s_median"):
         rr = np.array([a[k] / b[k] for a, b in zip(out["learned"]["chains"], out["exact"]["chains"])])
         out["learned_over_exact"][k + "_paired_mean"] = float(rr.mean())
-        out["learned_over_exact"][k + "_paired_sem"] = float(rr.std(ddof=1) / np.sqrt(len(rr))) if len(rr) > 1 else None
-    out["config"] = {"n_events": es.n, "free_rates": int(es.subset.shape[0]), "leapfrog": L, "iterations": n_iter,
+        sem = float(rr.std(ddof=1) / np.sqrt(len(rr))) if len(rr) > 1 else None
+        out["learned_over_exact"][k + "_paired_sem"] = sem
+        if sem is not None:
+            from scipy import stats
+            q = float(stats.t.ppf(0.975, len(rr) - 1))
+            out["learned_over_exact"][k + "_paired_ci95"] = [float(rr.mean()) - q * sem, float(rr.mean()) + q * sem]
+    for k in ("ess_per_s_min", "ess_per_s_median"):
+        rr = np.array([a[k] / b[k] for a, b in zip(out["exact"]["chains"], out["identity"]["chains"])])
+        out.setdefault("exact_over_identity", {})[k + "_paired_mean"] = float(rr.mean())
+        out["exact_over_identity"][k + "_paired_sem"] = float(rr.std(ddof=1) / np.sqrt(len(rr))) if len(rr) > 1 else None
+    out["config"] = {"n_events": es.n, "free_rates": int(es.subset.shape[0]), "sigma_z": sigma_z, "leapfrog": L,
+                     "iterations": n_iter,
                      "warmup": warmup, "mass_refresh": refresh, "exact_refresh_in_learned": exact_every,
                      "chains_per_mode": n_chains}
     return out
@@ -280,9 +316,13 @@ def bench_larger(configs=(2, 4), steps=(20, 8)):
         if plan.status() != 0 or not np.isfinite(float(out["loglik"].item())):
             raise RuntimeError(f"evaluation failed on {CONFIGS[cfg]}")
         achieved = FLOPS_ROW_PER_PAIR * pairs / (row_ms * 1e-3) / 1e12
+        eval_tf = FLOPS_PER_PAIR * pairs / el / 1e12
         res[CONFIGS[cfg]] = {"n_events": es.n, "steps": k, "ms_per_step": 1e3 * el,
                              "pair_evals_per_s": pairs / el, "row_ms": row_ms, "col_ms": prof[2] / max(prof[3], 1),
-                             "row_tflops": achieved, "row_frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS}
+                             "row_tflops": achieved, "row_frac": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
+                             "row_frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                             "eval_tflops": eval_tf, "eval_frac": eval_tf / PEAK_FP32_PUBLISHED_TFLOPS,
+                             "eval_frac_nonpacked": eval_tf / PEAK_FP32_NONPACKED_TFLOPS}
         plan.close()
     return res
 
@@ -333,6 +373,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # the larger workloads run first: they report on their own, and the
+    # headline's warm-up and timed steps then start on a GPU already at its
+    # sustained clocks (over the first ~20 ms of load the clocks ramp up and
+    # the row pass runs ~12% slower)
+    larger = bench_larger() if (not args.no_larger and args.config == 1) else None
+    exp_peak = exp2_peak()
     es = synth.config(args.config)
     n = es.n
     pairs = n * (n - 1) / 2
@@ -383,6 +429,7 @@ def main():
     plan.set_cutoff(False)
 
     achieved = FLOPS_ROW_PER_PAIR * pairs / (row_ms * 1e-3) / 1e12
+    eval_tf = FLOPS_PER_PAIR * pairs / (eval_ms * 1e-3) / 1e12
     rec = {
         "metric": "pair-evals/s for loglik+grad+Hess-diag at N=23,422; HMC ESS/s learned vs exact" if args.config == 1
         else f"pair-evals/s for loglik+grad+Hess-diag at N={n:,}",
@@ -403,34 +450,50 @@ def main():
             "n_free_rates": int(es.subset.shape[0]),
             "pairs_per_step": pairs,
             "outputs": "loglik, grad_theta[N], grad_hyper[6], negH_theta[N], negH_hyper[6]",
-            "precision": "FP32 pair terms; FP64 per-term sums for lambda, FP32 per chunk and FP64 across chunks for the moments; FP64 finals",
+            "precision": "FP32 pair terms; FP64 per-term sums for lambda, FP32 per chunk and FP64 across chunks for "
+                         "the moments; column pass exponents in FP64 with an exact power of two and an FP32 "
+                         "fraction; FP64 finals",
         },
         "roofline": {
             "bound": "alu",
             "kernel": "k_row (row pass)",
             "achieved": achieved,
-            "peak": PEAK_FP32_NONPACKED_TFLOPS,
+            "peak": PEAK_FP32_PUBLISHED_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+            "frac": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
             "traffic": k_row_traffic() if args.config == 1 else None,
             "traffic_unit": "bytes per launch (HBM read + write)",
             "flops_per_pair": FLOPS_ROW_PER_PAIR,
+            "pairs_per_launch": pairs,
             "kernel_ms": row_ms,
-            "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
+            "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+            "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+            "transcendental": {"exp2_per_s": EXPS_ROW_PER_PAIR * pairs / (row_ms * 1e-3),
+                               "peak_exp2_per_s_measured": exp_peak["exp2_per_s"],
+                               "frac": EXPS_ROW_PER_PAIR * pairs / (row_ms * 1e-3) / exp_peak["exp2_per_s"],
+                               "exps_per_pair": EXPS_ROW_PER_PAIR},
         },
+        "evaluation_roofline": {"flops_per_pair": FLOPS_PER_PAIR, "ms": eval_ms, "achieved": eval_tf,
+                                "frac": eval_tf / PEAK_FP32_PUBLISHED_TFLOPS,
+                                "frac_nonpacked": eval_tf / PEAK_FP32_NONPACKED_TFLOPS,
+                                "exp2_per_s": (EXPS_ROW_PER_PAIR + EXPS_COL_PER_PAIR) * pairs / (eval_ms * 1e-3)},
+        "exp2_peak": exp_peak,
         "passes_ms": {"row": row_ms, "col": col_ms, "eval": eval_ms},
         "col_pass_tflops": FLOPS_COL_PER_PAIR * pairs / (col_ms * 1e-3) / 1e12 if col_ms > 0 else None,
-        "eval_tflops": FLOPS_PER_PAIR * pairs / (eval_ms * 1e-3) / 1e12,
         "loglik": ll,
         "with_underflow_cutoff": {"ms_per_step": cut_ms, "speedup": ms_step / cut_ms,
                                   "loglik_rel_change": abs(ll_cut - ll) / abs(ll),
                                   "note": "skips pair blocks whose terms are all below 2^-160; not counted as "
                                           "pair-evaluations"},
     }
-    if not args.no_larger and args.config == 1:
-        rec["larger_workloads"] = bench_larger()
+    if larger is not None:
+        rec["larger_workloads"] = larger
     if not args.no_hmc and args.config == 1:
         rec["hmc"] = bench_hmc(synth.config(3), n_iter=args.hmc_iters)
+        # the same comparison where the likelihood's curvature is a sizeable share
+        # of the mass: a wider prior on the log-rates (sigma_z = 2, prior
+        # precision 1/4 instead of 4)
+        rec["hmc_sigma2"] = bench_hmc(synth.config(3), n_iter=args.hmc_iters, sigma_z=2.0)
     if not args.no_hmc and not args.no_hmc_large and args.config == 1:
         rec["hmc_iteration_N250000"] = bench_hmc_large(synth.config(4))
     if not args.no_cpu_baseline:

@@ -195,6 +195,11 @@ hawkes_status hawkes_subset_trend_grad(hawkes_plan p, const hawkes_hyper *hyper,
                                        double *d_theta, double *d_loglik, double *d_grad_z, double *d_grad_beta,
                                        hipStream_t stream);
 
+/* The log-rates of the subset from a full rate vector, slot order:
+ * d_z[k] = log d_theta[idx[k]] - beta t_{idx[k]} (Sec. 2.2's theta_k =
+ * exp(z_k + beta t_k) solved for z_k).  d_theta [n] caller order, rates > 0. */
+hawkes_status hawkes_subset_z(hawkes_plan p, const double *d_theta, double beta, double *d_z, hipStream_t stream);
+
 /* One HMC iteration on z (slot order) with target
  *   log pi(z) = loglik(theta(z)) - sum_k z_k^2 / (2 sigma_z^2),
  *   theta_k = exp(z_k + beta t_k)
@@ -224,6 +229,8 @@ typedef struct {
     int prior;             /* 0: z ~ N(0, sigma_z^2 I); 1: the phylogenetic prior of Eq. 2,
                               z ~ N(0, sigma_z^2 V) for the tree set by hawkes_plan_set_tree
                               (its tips must be the subset slots)                          */
+    double *d_z_proposal;  /* [m] device, may be NULL: the end of the leapfrog path (slot
+                              order), written whether or not the proposal is accepted     */
 } hawkes_hmc_args;
 
 hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawkes_hmc_args *args, hipStream_t stream);
@@ -299,13 +306,33 @@ hawkes_status hawkes_mlp_train_step(float *d_params, float *d_adam_m, float *d_a
 hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hyper, const double *d_t, const double *d_xy,
                               const double *d_z, double gx0, double gy0, float *d_feat, hipStream_t stream);
 
-/* Running average of the diagonal mass: d_mass[k] <- (count d_mass[k] + c_k)/(count + 1)
- * with c_k the z-space curvature estimate at the rates d_theta:
- *   d_pred == NULL: exact, max(theta^2 H - theta g, 0) + 1/sigma_z^2 (Eq. 4, Eq. 5, subset path);
- *   d_pred != NULL: learned, max(exp(d_pred[k]), 1/sigma_z^2) (d_pred [m] FP32, slot order: a
- *                   prediction of the log of the exact estimate). */
+/* The log posterior's curvature in the subset's log-rates (Sec. 2.3.2: the
+ * diagonal of Eq. 5 used as the HMC mass, carried to z by the chain rule; with
+ * theta_k = exp(z_k + beta t_k), d theta_k / d z_k = theta_k whatever beta):
+ *   c_k = -d2 log pi / dz_k^2 = theta_k^2 H_k - theta_k g_k + P_kk,
+ * g, H = Eq. 4, Eq. 5 on the subset at the rates d_theta [n] (caller order,
+ * read only; the subset path), P_kk the prior's precision diagonal:
+ * 1/sigma_z^2 for prior = 0 (z ~ N(0, sigma_z^2 I)), (V^{-1})_kk / sigma_z^2 for
+ * prior = 1 (Eq. 2 on the tree of hawkes_plan_set_tree).
+ *   d_curv  [m] FP64, slot order: c_k                              -- may be NULL
+ *   d_log_h [m] FP32, slot order: log max(H_k, 1e-30), the learned
+ *           preconditioner's training target (Eq. 5 is 0 for an event
+ *           with no later event)                                   -- may be NULL
+ * HAWKES_E_UNSUPPORTED without a subset, or with prior = 1 and no tree of m tips. */
+hawkes_status hawkes_subset_curvature(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
+                                      double sigma_z, int prior, double *d_curv, float *d_log_h,
+                                      hipStream_t stream);
+
+/* Running average of the diagonal mass: d_mass[k] <- (count d_mass[k] + e_k)/(count + 1)
+ * with e_k an estimate of c_k above at the rates d_theta:
+ *   d_pred == NULL: exact, max(theta_k^2 H_k - theta_k g_k, 0) + P_kk (Eq. 4, Eq. 5 by
+ *                   the subset path; floored at the prior's precision);
+ *   d_pred != NULL: learned, theta_k^2 exp(d_pred[k]) + P_kk (d_pred [m] FP32, slot order:
+ *                   the network's prediction of log H_k).
+ * prior and P_kk as in hawkes_subset_curvature.  The mass stays positive, so
+ * HMC remains exact whatever the estimate. */
 hawkes_status hawkes_mass_update(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
-                                 const float *d_pred, double sigma_z, int64_t count, double *d_mass,
+                                 const float *d_pred, double sigma_z, int prior, int64_t count, double *d_mass,
                                  hipStream_t stream);
 
 /* Timing of the pair passes with HIP events recorded on the launch stream.
@@ -324,6 +351,13 @@ hawkes_status hawkes_profile_read(hawkes_plan p, double *out);
  * hawkes_exp2_bias_constant(), the value the library corrects for. */
 hawkes_status hawkes_exp2_bias(int64_t nsamples, double lo, double hi, double *d_out, hipStream_t stream);
 double hawkes_exp2_bias_constant(void);
+
+/* Issue throughput of the hardware exp2: `blocks` blocks of 256 threads, each
+ * thread running 8 independent chains of `iters` exp2 steps and nothing else.
+ * One untimed launch, then one launch timed by HIP events on `stream`;
+ * synchronises.  h_out (host) [3]: exp2 evaluations, seconds, evaluations per
+ * second.  d_sink: device FP32 [blocks], never written in practice. */
+hawkes_status hawkes_exp2_rate(int64_t blocks, int iters, float *d_sink, double *h_out, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -43,7 +43,8 @@ class HmcArgs(ctypes.Structure):
     _fields_ = [("d_z", ctypes.c_void_p), ("d_theta", ctypes.c_void_p), ("d_mass", ctypes.c_void_p),
                 ("eps", ctypes.c_double), ("L", ctypes.c_int), ("sigma_z", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("counter", ctypes.c_uint64), ("refresh_static", ctypes.c_int),
-                ("d_out", ctypes.c_void_p), ("beta", ctypes.c_double), ("prior", ctypes.c_int)]
+                ("d_out", ctypes.c_void_p), ("beta", ctypes.c_double), ("prior", ctypes.c_int),
+                ("d_z_proposal", ctypes.c_void_p)]
 
 
 class Hyper(ctypes.Structure):
@@ -88,11 +89,14 @@ SIGNATURES = {
     "hawkes_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _i64, _vp, _vp,
                                              _i64, _vp, _vp, _vp, _vp, _vp]),
     "hawkes_features": (ctypes.c_int, [_vp, _HyP, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
-    "hawkes_mass_update": (ctypes.c_int, [_vp, _HyP, _vp, _vp, ctypes.c_double, _i64, _vp, _vp]),
+    "hawkes_mass_update": (ctypes.c_int, [_vp, _HyP, _vp, _vp, ctypes.c_double, ctypes.c_int, _i64, _vp, _vp]),
+    "hawkes_subset_z": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _vp]),
+    "hawkes_subset_curvature": (ctypes.c_int, [_vp, _HyP, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp, _vp]),
     "hawkes_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hawkes_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "hawkes_exp2_bias": (ctypes.c_int, [_i64, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "hawkes_exp2_bias_constant": (ctypes.c_double, []),
+    "hawkes_exp2_rate": (ctypes.c_int, [_i64, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double), _vp]),
 }
 
 for _name, (_res, _args) in SIGNATURES.items():

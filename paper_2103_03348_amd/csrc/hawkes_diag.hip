@@ -1,6 +1,9 @@
-// Calibration of the hardware exp2 (v_exp_f32) against FP64 exp2: the mean
-// signed and mean absolute relative error over a low-discrepancy set of
-// arguments.  The pair kernels divide their FP64 normalisers by (1 + bias).
+// Diagnostics of the hardware exp2 (v_exp_f32):
+//   * calibration against FP64 exp2: the mean signed and mean absolute relative
+//     error over a low-discrepancy set of arguments (the pair kernels divide
+//     their FP64 normalisers by (1 + bias));
+//   * issue throughput: exp2 instructions per second when nothing else is
+//     issued, the transcendental ceiling of the pair kernels.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -50,7 +53,51 @@ __global__ void k_exp2_bias_fin(const double *__restrict__ part, int nb, int64_t
     }
 }
 
+// Each thread runs EXP_CHAINS independent chains x <- exp2(-x) (the negation
+// is a source modifier of the instruction, so the loop issues exp2 and loop
+// control only); the chains stay in [1/2, 1].
+constexpr int EXP_CHAINS = 8;
+__global__ __launch_bounds__(256) void k_exp2_rate(int iters, float seed, float *__restrict__ sink) {
+    float x[EXP_CHAINS];
+#pragma unroll
+    for (int k = 0; k < EXP_CHAINS; ++k) x[k] = seed + 0.01f * (float)k + 1e-6f * (float)threadIdx.x;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < EXP_CHAINS; ++k) x[k] = __builtin_amdgcn_exp2f(-x[k]);
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < EXP_CHAINS; ++k) acc += x[k];
+    // never true for chains in [1/2, 1]: keeps the loop alive without a store per thread
+    if (acc < 0.0f) sink[blockIdx.x] = acc;
+}
+
 }  // namespace
+
+extern "C" hawkes_status hawkes_exp2_rate(int64_t blocks, int iters, float *d_sink, double *h_out,
+                                          hipStream_t stream) {
+    if (blocks < 1 || blocks > (1 << 24) || iters < 1 || !d_sink || !h_out) return HAWKES_E_INVALID;
+    hipEvent_t e0, e1;
+    HK_CHECK(hipEventCreate(&e0));
+    HK_CHECK(hipEventCreate(&e1));
+    // a first launch brings up the clocks and loads the code
+    hipLaunchKernelGGL(k_exp2_rate, dim3((unsigned)blocks), dim3(256), 0, stream, iters, 0.5f, d_sink);
+    (void)hipEventRecord(e0, stream);
+    hipLaunchKernelGGL(k_exp2_rate, dim3((unsigned)blocks), dim3(256), 0, stream, iters, 0.5f, d_sink);
+    (void)hipEventRecord(e1, stream);
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return HAWKES_E_DEVICE;
+    const double n = (double)blocks * 256.0 * EXP_CHAINS * (double)iters;
+    h_out[0] = n;
+    h_out[1] = 1e-3 * (double)ms;
+    h_out[2] = n / (1e-3 * (double)ms);
+    return HAWKES_OK;
+}
 
 extern "C" hawkes_status hawkes_exp2_bias(int64_t nsamples, double lo, double hi, double *d_out,
                                           hipStream_t stream) {

@@ -178,8 +178,10 @@ __device__ __forceinline__ void row_sweep(const float2 *__restrict__ rec, const 
         const double dx = xr - pj.x, dy = yr - pj.y;
         const float ar = (float)(-fma(dx, dx, dy * dy));
         const float dt2 = dt * dt;
-        float b = fexp2(fmaf(dt2, kc.kbt, ar));
-        const float ae = ar * kc.rex;
+        // LOGLIK: the rounded FP32 constants are completed by their low parts
+        // here; the other modes correct them through the first moments
+        float b = fexp2(MODE == HK_MODE_LOGLIK ? fmaf(dt2, kc.kbt, fmaf(dt2, kc.kbt_lo, ar)) : fmaf(dt2, kc.kbt, ar));
+        const float ae = MODE == HK_MODE_LOGLIK ? fmaf(ar, kc.rex, ar * kc.rex_lo) : ar * kc.rex;
         float E;
         if (FACT) {
             E = fexp2(ae);
@@ -482,17 +484,13 @@ constexpr int HK_FIN_WAVES = 8;
 template <int MODE>
 __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const double *__restrict__ theta,
                                            const int *__restrict__ perm, int64_t n, const FinConst &fc,
-                                           int *__restrict__ chunk_wide_col,
                                            const double (*part)[HK_NROW][HK_WAVE], int lane, int64_t i,
-                                           double *__restrict__ lam, float *__restrict__ wv,
+                                           double *__restrict__ lam, double *__restrict__ lw,
                                            double *__restrict__ a_out, double *__restrict__ blockpart,
                                            int *__restrict__ status) {
     double s[HK_NSUM];
 #pragma unroll
     for (int k = 0; k < HK_NSUM; ++k) s[k] = 0.0;
-    // the column pass's split flag of this chunk (HK_COL_SPAN)
-    const bool wide_col = __any(i < n && fc.omega * (ts[i] - ts[i - lane]) > HK_COL_SPAN);
-    if (lane == 0) chunk_wide_col[blockIdx.x] = wide_col;
     if (i < n) {
         double acc[HK_NROW];
 #pragma unroll
@@ -515,13 +513,10 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
         if (!(lamv > 0.0)) {
             atomicOr(status, isnan(lamv) ? HK_ST_NONFINITE : HK_ST_ZERO);
         }
-        {
-            // w_i = c_e / lambda_i, staged for the column pass as w_i exp(-omega (t_i - T_c))
-            // on its split chunks, rounded once to FP32
-            const double wd = lamv > 0.0 ? fc.c_e / lamv : 0.0;
-            wv[i] = (float)(wide_col ? wd : wd * exp(-fc.omega * (ts[i] - ts[i - lane])));
-        }
         s[0] = log(lamv);
+        // the column pass's weight w_i = c_e / lambda_i as its log2 (FP64), which
+        // enters the exponent of each term c_e E_ij / lambda_i
+        lw[i] = lamv > 0.0 ? fmax(fc.log2_ce - s[0] * 1.4426950408889634, HK_EXP_FLOOR) : HK_EXP_FLOOR;
         const double inv = 1.0 / lamv;
         if (MODE >= HK_MODE_GRAD) {
             const double B1 = acc[1] * fc.corr * fc.Kx, B2 = acc[2] * fc.corr;
@@ -572,7 +567,7 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
         }
     } else {
         lam[i] = 1.0;
-        wv[i] = 0.0f;
+        lw[i] = HK_EXP_FLOOR;
         a_out[i] = 0.0;
     }
 #pragma unroll
@@ -593,8 +588,8 @@ __global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__
                                              const int *__restrict__ perm, int64_t n, int ntiles,
                                              const int *__restrict__ row_item0, const int *__restrict__ row_nseg,
                                              const float *__restrict__ rowpart, const float *__restrict__ colpart,
-                                             const FinConst fc, int *__restrict__ chunk_wide_col,
-                                             double *__restrict__ lam, float *__restrict__ wv,
+                                             const FinConst fc,
+                                             double *__restrict__ lam, double *__restrict__ lw,
                                              double *__restrict__ a_out,
                                              double *__restrict__ blockpart, int *__restrict__ status) {
     __shared__ double part[HK_FIN_WAVES][HK_NROW][HK_WAVE];
@@ -644,7 +639,7 @@ __global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__
         for (int k = 0; k < HK_NROW; ++k) part[wq][k][lane] = acc[k];
     }
     __syncthreads();
-    if (wq == 0) fin_events<MODE>(ts, theta, perm, n, fc, chunk_wide_col, part, lane, i, lam, wv, a_out, blockpart,
+    if (wq == 0) fin_events<MODE>(ts, theta, perm, n, fc, part, lane, i, lam, lw, a_out, blockpart,
                                   status);
 }
 
@@ -660,51 +655,74 @@ __global__ __launch_bounds__(HK_NSUM * HK_TOT_LANES) void k_fin2(const double *_
 
 
 // ------------------------------------------------------------------------------------
-// Column pass.  G_j = sum_{t_i > t_j} E_ij w_i and H_j = sum (E_ij w_i)^2 for the
-// lanes' columns j against a staged chunk of 64 later rows i.  With the time
-// factorisation the staged row carries v_i = w_i exp(-omega (t_i - T_c)) in
-// FP32 and the lane applies u_j = exp(omega (t_j - T_c)) to its chunk sums; the
-// spatial exponent is formed in FP64 and rounded once, so that each term
-// E_ij w_i is good to a few FP32 roundings (H squares it, which doubles its
-// relative error, and an absolute rounding of the exponent becomes a relative
-// error of the term, so the exponent must not carry more).  The rounding of
-// v_i itself is independent across rows and averages out in the sums.
-template <bool MASKED, bool FACT>
-__device__ __forceinline__ float col_term(const double2 *__restrict__ rxy, const float *__restrict__ rv,
-                                          const double *__restrict__ rtd, const int *__restrict__ rg, int s,
-                                          int jcol, double tsj, double xj, double yj, const PairConst kc) {
-    // coordinates pre-scaled in FP64, so that the spatial exponent is minus a
-    // squared distance, formed in FP64 and rounded once
-    const double2 p = rxy[s];
-    const double dx = p.x - xj, dy = p.y - yj;
-    const double aed = -fma(dx, dx, dy * dy);
-    // with the time term when the chunk is too wide for the split
-    float E = fexp2(FACT ? (float)aed : (float)fma(rtd[s] - tsj, kc.kw_d, aed));
+// Column pass.  G_j = sum_{t_i > t_j} T_ij and H_j = sum T_ij^2 with
+// T_ij = c_e E_ij / lambda_i (Eq. 4 without theta0's integral term, and Eq. 5)
+// for the lanes' columns j against a staged chunk of 64 later rows i.
+//
+// Each term is one exponential of its whole exponent in log2 units,
+//   e_ij = lw_i - omega (t_i - t_j) / ln2 - |s (x_i - x_j)|^2,
+// with lw_i = log2(c_e / lambda_i) from the finalisation and s = 1 / (h sqrt(2
+// ln 2)), formed in FP64.  e_ij is split into its nearest integer n and a
+// fraction f in [-1/2, 1/2]; only f is rounded to FP32 for the hardware exp2
+// and 2^n is applied exactly (ldexp).  The term's relative error is then a few
+// FP32 roundings whatever the size of e_ij: Eq. 5 squares the terms, and an
+// error in the exponent's absolute value would become a relative error of the
+// term that grows with |e_ij|.
+//
+// The exponent is split into a row part (staged), a column part (per lane)
+// and the cross term.  With DOT the spatial part is expanded,
+//   -|u_i - u_j|^2 = 2 u_i . u_j - |u_i|^2 - |u_j|^2   (u = s x),
+// which takes three FP64 operations per pair; it is used when every |u|^2 is
+// at most HK_DOT_MAX2, where the cancellation costs at most ~2^-30 absolute.
+// Otherwise the differences are formed (five operations).  Times enter
+// relative to the column tile's first time, so that both parts stay small for
+// the pairs whose terms are not negligible.
+struct ColRow {     // one staged row
+    double2 u;      // DOT: 2 u_i; else u_i
+    double c;       // lw_i + kw (t_i - T_ref) (DOT: minus |u_i|^2), at least HK_EXP_FLOOR
+};
+
+template <bool DOT>
+__device__ __forceinline__ double col_exponent(const ColRow &r, double xj, double yj, double dj) {
+    if (DOT) return fma(r.u.x, xj, fma(r.u.y, yj, r.c + dj));
+    const double dx = r.u.x - xj, dy = r.u.y - yj;
+    return fma(-dx, dx, fma(-dy, dy, r.c + dj));
+}
+
+// 2^e for an FP64 exponent: exact integer part, FP32 fraction
+__device__ __forceinline__ float exp2_split(double e) {
+    const double n = rint(e);
+    return __builtin_amdgcn_ldexpf(fexp2((float)(e - n)), (int)n);
+}
+
+template <bool MASKED, bool DOT>
+__device__ __forceinline__ float col_term(const ColRow *__restrict__ rows, const int *__restrict__ rg, int s,
+                                          int jcol, double xj, double yj, double dj) {
+    float T = exp2_split(col_exponent<DOT>(rows[s], xj, yj, dj));
     if (MASKED) {
-        if (!(jcol < rg[s])) E = 0.0f;
+        if (!(jcol < rg[s])) T = 0.0f;
     }
-    return E * rv[s];
+    return T;
 }
 
 // Two interleaved streams of steps (even and odd rows of the chunk) with their
 // own accumulators: the FP64 exponent chains of neighbouring steps overlap.
 // The loop is kept short (HK_COL_UNROLL pairs of steps per iteration): a
-// deeper unroll hoists more LDS loads into registers, and at 130 VGPRs only
-// three wavefronts per SIMD fit, too few to hide the FP64 and exp latencies.
+// deeper unroll hoists more LDS loads into registers and fits fewer
+// wavefronts per SIMD.
 #ifndef HK_COL_UNROLL
 #define HK_COL_UNROLL 2
 #endif
 constexpr int kColUnroll = HK_COL_UNROLL;
-template <bool WITH_H, bool MASKED, bool FACT>
-__device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
-                                          const double *__restrict__ rtd, const int *__restrict__ rg, int jcol,
-                                          double tsj, double xj, double yj, const PairConst kc, float &G, float &H) {
+template <bool WITH_H, bool MASKED, bool DOT>
+__device__ __forceinline__ void col_sweep(const ColRow *__restrict__ rows, const int *__restrict__ rg, int jcol,
+                                          double xj, double yj, double dj, float &G, float &H) {
 #pragma clang fp contract(off)
     float G1 = 0.0f, H1 = 0.0f;
 #pragma unroll kColUnroll
     for (int s = 0; s < HK_WAVE; s += 2) {
-        const float e0 = col_term<MASKED, FACT>(rxy, rv, rtd, rg, s, jcol, tsj, xj, yj, kc);
-        const float e1 = col_term<MASKED, FACT>(rxy, rv, rtd, rg, s + 1, jcol, tsj, xj, yj, kc);
+        const float e0 = col_term<MASKED, DOT>(rows, rg, s, jcol, xj, yj, dj);
+        const float e1 = col_term<MASKED, DOT>(rows, rg, s + 1, jcol, xj, yj, dj);
         G += e0;
         G1 += e1;
         if (WITH_H) {
@@ -716,16 +734,13 @@ __device__ __forceinline__ void col_sweep(const double2 *__restrict__ rxy, const
     H += H1;
 }
 
-template <bool WITH_H>
+template <bool WITH_H, bool DOT>
 __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, const int *__restrict__ xi,
-                                                  const int *__restrict__ yi, const float *__restrict__ wv,
-                                                  const int *__restrict__ chunk_wide_col,
-                                                  const double *__restrict__ tstep, const int *__restrict__ g,
+                                                  const int *__restrict__ yi, const double *__restrict__ lw,
+                                                  const int *__restrict__ g, int64_t n,
                                                   const hk_item *__restrict__ items, const int *__restrict__ block0,
                                                   double *__restrict__ colG, const PairConst kc) {
-    __shared__ double2 rxy[HK_WAVE];
-    __shared__ float rv[HK_WAVE];
-    __shared__ double rtd[HK_WAVE];
+    __shared__ ColRow rows[HK_WAVE];
     __shared__ int rg[HK_WAVE];
     // uniform wavefront index: the per-wave bounds select the sweep with scalar branches
     const int tid = threadIdx.x, wvi = __builtin_amdgcn_readfirstlane(tid / HK_WAVE);
@@ -736,30 +751,36 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
         const int J = it.tile;
         const int64_t col0 = (int64_t)J * HK_TILE;
         const int jcol = (int)(col0 + tid);
-        const double tsj = ts[jcol];
-        const double xj = (double)xi[jcol] * kc.sx, yj = (double)yi[jcol] * kc.sx;
+        const double t_ref = ts[col0];
+        const double uxj = (double)xi[jcol] * kc.sx, uyj = (double)yi[jcol] * kc.sx;
+        // the column's part of the exponent: omega (t_j - T_ref) / ln2 (DOT:
+        // minus |u_j|^2); a padding column's terms are never used
+        double dj = -kc.kw_d * (ts[jcol] - t_ref);
+        if (DOT) dj -= fma(uxj, uxj, uyj * uyj);
+        if (jcol >= n) dj = HK_EXP_FLOOR;
         const int wave_first = (int)(col0 + wvi * HK_WAVE);
         const double wave_tmax = ts[(int64_t)wave_first + HK_WAVE - 1];  // the wave's latest column
 
         const double tile_tmax = ts[col0 + HK_TILE - 1];
         double Gd = 0.0, Hd = 0.0;
-        // the column's split factor exp(omega (t_j - T_c)), evaluated at the first
-        // split chunk with a causal pair and carried to later chunks by their step
-        // factors (decreasing from at most exp(HK_COL_SPAN)); a wide chunk breaks
-        // the chain
-        double uj = 0.0;
-        bool have_uj = false;
         for (int c = it.c_begin; c < it.c_end; ++c) {
-            if (have_uj) uj *= tstep[c - 1];
             const double Tc = ts[(int64_t)c * HK_WAVE];
             // under the cutoff, rows starting more than dt_cut_ex after the
             // tile's latest column end the sweep (times are sorted)
             if (Tc - tile_tmax > kc.dt_cut_ex) break;
             if (tid < HK_WAVE) {
                 const int64_t i = (int64_t)c * HK_WAVE + tid;
-                rxy[tid] = make_double2((double)xi[i] * kc.sx, (double)yi[i] * kc.sx);
-                rv[tid] = wv[i];  // w_i exp(-omega (t_i - T_c)) on split chunks
-                rtd[tid] = ts[i];
+                const double ux = (double)xi[i] * kc.sx, uy = (double)yi[i] * kc.sx;
+                double cr = lw[i] + kc.kw_d * (ts[i] - t_ref);
+                ColRow r;
+                if (DOT) {
+                    cr -= fma(ux, ux, uy * uy);
+                    r.u = make_double2(2.0 * ux, 2.0 * uy);
+                } else {
+                    r.u = make_double2(ux, uy);
+                }
+                r.c = fmax(cr, HK_EXP_FLOOR);
+                rows[tid] = r;
                 rg[tid] = g[i];
             }
             __syncthreads();
@@ -767,30 +788,13 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
             // optional underflow cutoff: rows that all start more than dt_cut_ex
             // after the wave's latest column give excitation terms below 2^-160
             if (gmax > wave_first && !(Tc - wave_tmax > kc.dt_cut_ex)) {
-                const bool fact = chunk_wide_col[c] == 0;
                 float G = 0.0f, H = 0.0f;
-                const bool masked = gmin <= wave_first + HK_WAVE - 1;
-                if (fact) {
-                    if (masked) col_sweep<WITH_H, true, true>(rxy, rv, rtd, rg, jcol, tsj, xj, yj, kc, G, H);
-                    else col_sweep<WITH_H, false, true>(rxy, rv, rtd, rg, jcol, tsj, xj, yj, kc, G, H);
-                } else {
-                    if (masked) col_sweep<WITH_H, true, false>(rxy, rv, rtd, rg, jcol, tsj, xj, yj, kc, G, H);
-                    else col_sweep<WITH_H, false, false>(rxy, rv, rtd, rg, jcol, tsj, xj, yj, kc, G, H);
-                }
-                // a column with a causal pair here has t_j < t_i <= T_c + span, so
-                // its factor is finite; the others have nothing to scale
-                if (!fact) {
-                    Gd += (double)G;
-                    if (WITH_H) Hd += (double)H;
-                    have_uj = false;
-                } else if (G != 0.0f) {
-                    if (!have_uj) {
-                        uj = exp(kc.omega * (tsj - Tc));
-                        have_uj = true;
-                    }
-                    Gd += uj * (double)G;
-                    if (WITH_H) Hd += (uj * uj) * (double)H;
-                }
+                if (gmin <= wave_first + HK_WAVE - 1)
+                    col_sweep<WITH_H, true, DOT>(rows, rg, jcol, uxj, uyj, dj, G, H);
+                else
+                    col_sweep<WITH_H, false, DOT>(rows, rg, jcol, uxj, uyj, dj, G, H);
+                Gd += (double)G;
+                if (WITH_H) Hd += (double)H;
             }
             __syncthreads();
         }
@@ -874,7 +878,16 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     }
     kc->sx = sqrt(-kex);
     kc->sbx = sqrt(-kbx);
+    {
+        // largest |s x|^2 over the plan: the fixed-point coordinates are centred,
+        // so |x_fixed| is at most half the bounding box's larger side (plus rounding)
+        const double half = 0.5 * fmax(p->xmax - p->xmin, p->ymax - p->ymin) * ldexp(1.0, p->fxk) + 1.0;
+        const double umax = half * kc->sx;
+        kc->dot = 2.0 * umax * umax <= HK_DOT_MAX2;
+    }
     kc->rex = (float)(kex / kbx);
+    kc->kbt_lo = (float)(kbt - (double)kc->kbt);
+    kc->rex_lo = (float)(kex / kbx - (double)kc->rex);
     fc->dkbt = (double)kc->kbt - kbt;
     fc->rho_ex = ((double)kc->rex - kex / kbx) / (double)kc->rex;
     const double corr = 1.0 / (1.0 + HK_EXP2_BIAS);
@@ -885,6 +898,7 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     fc->ce1 = hy->omega / (two_pi * hy->h * hy->h);
     fc->c_b = fc->cb1 * hy->mu0;
     fc->c_e = fc->ce1 * hy->theta0;
+    fc->log2_ce = log2(fc->c_e);
     // moments are accumulated in log2 units of the exponent: r^2 = -2 s^2 ln2 * a
     // (the fixed-point scale is already inside kbx / kex)
     fc->Kx = -2.0 * hy->tau_x * hy->tau_x * ln2;
@@ -898,12 +912,17 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
 static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, double *d_grad_theta,
                        double *d_negH_theta, hipStream_t stream) {
     hk_prof_mark(p, HK_PROF_COL, true, stream);
-    if (d_negH_theta)
-        hipLaunchKernelGGL(k_col<true>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->wv,
-                           p->chunk_wide_col, p->tstep, p->g, p->col_items, p->col_block0, p->colG, kc);
-    else
-        hipLaunchKernelGGL(k_col<false>, dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                           p->wv, p->chunk_wide_col, p->tstep, p->g, p->col_items, p->col_block0, p->colG, kc);
+#define HK_COL(H, D)                                                                                        \
+    hipLaunchKernelGGL((k_col<H, D>), dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->lw, \
+                       p->g, p->n, p->col_items, p->col_block0, p->colG, kc)
+    if (d_negH_theta) {
+        if (kc.dot) HK_COL(true, true);
+        else HK_COL(true, false);
+    } else {
+        if (kc.dot) HK_COL(false, true);
+        else HK_COL(false, false);
+    }
+#undef HK_COL
     hk_prof_mark(p, HK_PROF_COL, false, stream);
     hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->perm, p->n, p->col_item0, p->col_nseg,
                        p->colG, p->a, fc, d_grad_theta, d_negH_theta);
@@ -942,9 +961,11 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
     PairConst kc;
     FinConst fc;
     hk_make_consts(p, hyper, &kc, &fc);
-    // the log-likelihood alone still needs the first moments: they carry the
-    // correction for the rounded FP32 exponent constants
-    const int mode = d_negH_hyper ? HK_MODE_HESS : HK_MODE_GRAD;
+    // the row pass carries the moments the requested hyperparameter derivatives
+    // need: none for the log-likelihood and the rate derivatives (Eq. 4, Eq. 5
+    // only need lambda), first moments for the hyperparameter gradient, second
+    // moments for its Hessian diagonal
+    const int mode = d_negH_hyper ? HK_MODE_HESS : (d_grad_hyper ? HK_MODE_GRAD : HK_MODE_LOGLIK);
     const int64_t npad = p->npad;
 
     hk_prof_mark(p, HK_PROF_EVAL, true, stream);
@@ -958,11 +979,13 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 #define HK_FIN(M)                                                                                              \
     hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->ts, d_theta,       \
                        p->perm, p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, fc,             \
-                       p->chunk_wide_col, p->lam, p->wv, p->a, p->blockpart, p->status)
-    if (mode == HK_MODE_GRAD) HK_ROW(HK_MODE_GRAD);
+                       p->lam, p->lw, p->a, p->blockpart, p->status)
+    if (mode == HK_MODE_LOGLIK) HK_ROW(HK_MODE_LOGLIK);
+    else if (mode == HK_MODE_GRAD) HK_ROW(HK_MODE_GRAD);
     else HK_ROW(HK_MODE_HESS);
     hk_prof_mark(p, HK_PROF_ROW, false, stream);
-    if (mode == HK_MODE_GRAD) HK_FIN(HK_MODE_GRAD);
+    if (mode == HK_MODE_LOGLIK) HK_FIN(HK_MODE_LOGLIK);
+    else if (mode == HK_MODE_GRAD) HK_FIN(HK_MODE_GRAD);
     else HK_FIN(HK_MODE_HESS);
 #undef HK_ROW
 #undef HK_FIN
@@ -980,7 +1003,7 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream) {
     hipLaunchKernelGGL(k_tfac<false>, dim3((unsigned)(p->npad / 256)), dim3(256), 0, stream, (const double *)nullptr,
                        p->perm, p->ts, p->n, kc.omega, p->theta_s, p->theta_v, p->chunk_wide, p->tstep, p->status);
-    hipLaunchKernelGGL(k_row<HK_MODE_GRAD>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
+    hipLaunchKernelGGL(k_row<HK_MODE_LOGLIK>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
                        p->theta_v, p->chunk_wide, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart,
                        p->colpart, kc);
 }

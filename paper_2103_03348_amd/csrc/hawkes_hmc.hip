@@ -18,8 +18,8 @@
 //                  subset entries staged in time order for the subset passes
 //   k_sub_row      X_i = sum_{k in M, t_k < t_i} theta_k E_ik (rows = all events),
 //                  one-wavefront items with partial sums
-//   k_sub_fin      lambda_i, block sums of log lambda_i, and the row chunks
-//                  staged for the column pass (w_i = c_e / lambda_i)
+//   k_sub_fin      lambda_i, block sums of log lambda_i, and the column
+//                  pass's row weights log2(c_e / lambda_i)
 //   k_sub_col      G_k = sum_{t_i > t_k} E_ik w_i, H_k = sum (E_ik w_i)^2, items
 //   k_sub_colfin   Eq. 4 / Eq. 5 on the subset; inside hmc_step also the
 //                  leapfrog's gradient in z, kick and drift
@@ -62,10 +62,8 @@ struct hk_subset {
     double *sts;         // [mpad] times
     int *qwide;          // [nq] 1 where the 64-entry chunk q spans more than HK_SUB_FACT_SPAN / omega
     double *qstep;       // [nq] exp(-omega (T_{q+1} - T_q)), T_q the time of chunk q's first entry
-    // row-chunk staging of the subset column pass, written by k_sub_fin
-    float *wv;           // [npad] c_e / lambda_i times exp(-omega (t_i - T_c)) on split chunks
-    int *cwide;          // [nchunks] 1 where the row chunk takes the direct exponent
-    double *cstep;       // [nchunks] exp(-omega (T_{c+1} - T_c))
+    // the subset column pass's row weights, written by k_sub_fin
+    double *lw;          // [npad] log2(c_e / lambda_i) (HK_EXP_FLOOR on padding)
     double *colG;        // [n_items][2][HK_WAVE]
     double *gsub;        // [mpad] Eq. 4 on the subset, time order
     double *hsub;        // [mpad] Eq. 5 on the subset, time order
@@ -207,23 +205,14 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
     double lam_part = 0.0;
     if (i < n) {
         const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
-        double b0 = 0.0, x0 = 0.0, b2 = 0.0, x2 = 0.0;
+        // the log-likelihood-only row pass: B0 (row and column partials) and X0
+        double b0 = 0.0, x0 = 0.0;
         for (int sg = 0; sg < row_nseg[I]; ++sg) {
             const float *rp = rowpart + (int64_t)(row_item0[I] + sg) * HK_NROW * HK_TILE + r;
             b0 += rp[0];
-            b2 += rp[2 * HK_TILE];
             x0 += rp[5 * HK_TILE];
-            x2 += rp[7 * HK_TILE];
         }
-        for (int J = I; J < ntiles; ++J) {
-            const int64_t stride = (int64_t)(J + 1) * HK_TILE;
-            b0 += (double)colpart[colpart_off[J] + i];
-            b2 += (double)colpart[colpart_off[J] + 2 * stride + i];
-        }
-        // first-order correction for the rounded FP32 exponent constants
-        const double ln2 = 0.6931471805599453;
-        b0 -= ln2 * fc.dkbt * b2;
-        x0 -= ln2 * fc.rho_ex * x2;
+        for (int J = I; J < ntiles; ++J) b0 += (double)colpart[colpart_off[J] + i];
         lam_static[i] = fc.c_b * b0 * fc.corr + fc.c_e * x0 * fc.corr;
         // integral term: background (all events) + excitation of the fixed-rate events
         const double ti = ts[i];
@@ -432,16 +421,13 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
 // chunk's row items (late chunks have the most, one per run of subset sources
 // before them) and combine their partial sums in a fixed order, so that the
 // partial-sum reads are in flight together; wavefront 0 then finalises the
-// rows.  The chunk's sum of log lambda goes to blockpart[chunk].  It also
-// stages the chunk for the subset column pass: w_i = c_e / lambda_i times the
-// split factor exp(-omega (t_i - T_c)), the chunk's split flag and its step
-// factor.
+// rows.  The chunk's sum of log lambda goes to blockpart[chunk], and the
+// subset column pass's weight w_i = c_e / lambda_i to lw as its log2 (FP64).
 __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const double *__restrict__ lam_static,
                                                  const int *__restrict__ ritem0, const int *__restrict__ rnseg,
                                                  const double *__restrict__ xpart, const double *__restrict__ ts,
                                                  int64_t n, int64_t npad, const FinConst fc,
-                                                 double *__restrict__ lam, float *__restrict__ wv,
-                                                 int *__restrict__ cwide, double *__restrict__ cstep,
+                                                 double *__restrict__ lam, double *__restrict__ lw,
                                                  double *__restrict__ blockpart, int *__restrict__ status) {
     __shared__ double part[SUB_ROWFIN_WAVES][HK_WAVE];
     const int b = blockIdx.x, lane = threadIdx.x & (HK_WAVE - 1);
@@ -450,13 +436,8 @@ __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const do
     const int64_t i = i0 + lane;
     // wavefront 0's own operands are fetched before the reduction, so that their
     // latency overlaps the partial-sum reads
-    double tsi = 0.0, tsc = 0.0, tsnext = 0.0, lst = 0.0;
-    if (wq == 0) {
-        tsi = ts[i];
-        tsc = ts[i0];
-        if (i0 + HK_WAVE < npad) tsnext = ts[i0 + HK_WAVE];
-        if (i < n) lst = lam_static[i];
-    }
+    double lst = 0.0;
+    if (wq == 0 && i < n) lst = lam_static[i];
     {
         double x = 0.0;
         if (i < n) {
@@ -479,13 +460,6 @@ __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const do
     }
     __syncthreads();
     if (wq != 0) return;
-    const double dti = tsi - tsc;
-    // the column pass squares its terms: its split limit is HK_COL_SPAN
-    const bool wide = __any(i < n && fc.omega * dti > HK_COL_SPAN);
-    if (lane == 0) {
-        cwide[b] = wide;
-        cstep[b] = i0 + HK_WAVE < npad ? exp(-fc.omega * (tsnext - tsc)) : 0.0;
-    }
     double v = 0.0;
     if (i < n) {
         double x = part[0][lane];
@@ -494,12 +468,11 @@ __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const do
         const double l = lst + fc.c_e * fc.corr * x;
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
-        const double wd = l > 0.0 ? fc.c_e / l : 0.0;
-        wv[i] = (float)(wide ? wd : wd * exp(-fc.omega * dti));
         v = log(l);
+        lw[i] = l > 0.0 ? fmax(fc.log2_ce - v * 1.4426950408889634, HK_EXP_FLOOR) : HK_EXP_FLOOR;
     } else {
         lam[i] = 1.0;
-        wv[i] = 0.0f;
+        lw[i] = HK_EXP_FLOOR;
     }
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (lane == 0) blockpart[b] = v;
@@ -507,113 +480,115 @@ __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const do
 
 // Column pass on the subset: lanes own subset entries (time order), rows are
 // all events after them, broadcast from LDS.  Same arithmetic as the full
-// column pass: time factors in FP64, spatial exponent from pre-scaled FP64
-// coordinates, rounded once.
-template <bool WITH_H, bool MASKED, bool FACT>
-__device__ __forceinline__ void sub_col_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
-                                              const double *__restrict__ rtd, const int *__restrict__ rg, int pj,
-                                              double tsj, double xj, double yj, const PairConst kc, float &G,
-                                              float &H) {
+// column pass: each term c_e E_ik / lambda_i is the exponential of its whole
+// exponent, log2(c_e / lambda_i) - omega (t_i - t_k) / ln2 - |s (x_i - x_k)|^2,
+// formed in FP64 and split into an exact power of two and an FP32 fraction.
+struct SubColRow {  // one staged row
+    double2 u;      // DOT: 2 u_i; else u_i (u = s x)
+    double c;       // lw_i + kw (t_i - T_ref) (DOT: minus |u_i|^2), at least HK_EXP_FLOOR
+};
+
+__device__ __forceinline__ float sub_exp2_split(double e) {
+    const double n = rint(e);
+    return __builtin_amdgcn_ldexpf(fexp2((float)(e - n)), (int)n);
+}
+
+template <bool WITH_H, bool MASKED, bool DOT>
+__device__ __forceinline__ void sub_col_sweep(const SubColRow *__restrict__ rows, const int *__restrict__ rg, int pj,
+                                              double xk, double yk, double dk, float &G, float &H) {
 #pragma unroll kSubUnroll
     for (int s = 0; s < HK_WAVE; ++s) {
-        const double2 p = rxy[s];
-        const double dx = p.x - xj, dy = p.y - yj;
-        const double aed = -fma(dx, dx, dy * dy);
-        float E = fexp2(FACT ? (float)aed : (float)fma(rtd[s] - tsj, kc.kw_d, aed));
-        if (MASKED && !(pj < rg[s])) E = 0.0f;
-        const float ew = E * rv[s];
-        G += ew;
-        if (WITH_H) H = fmaf(ew, ew, H);
+        const SubColRow r = rows[s];
+        double e;
+        if (DOT) {
+            e = fma(r.u.x, xk, fma(r.u.y, yk, r.c + dk));
+        } else {
+            const double dx = r.u.x - xk, dy = r.u.y - yk;
+            e = fma(-dx, dx, fma(-dy, dy, r.c + dk));
+        }
+        float T = sub_exp2_split(e);
+        if (MASKED && !(pj < rg[s])) T = 0.0f;
+        G += T;
+        if (WITH_H) H = fmaf(T, T, H);
     }
 }
 
 // One item: a chunk of 64 subset entries (the lanes) against a range of row
-// chunks after them; the entries' partial sums go to the item's slot.
-template <bool WITH_H>
+// chunks after them; the entries' partial sums go to the item's slot.  Times
+// enter relative to the subset chunk's first entry.
+template <bool WITH_H, bool DOT>
 __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ ts, const int *__restrict__ xi,
-                                                      const int *__restrict__ yi, const float *__restrict__ wv,
-                                                      const int *__restrict__ cwide, const double *__restrict__ cstep,
+                                                      const int *__restrict__ yi, const double *__restrict__ lw,
                                                       const int *__restrict__ g, const int *__restrict__ pos,
                                                       const double2 *__restrict__ sxy, const double *__restrict__ sts,
                                                       int64_t m, const hk_item *__restrict__ items,
                                                       const PairConst kc, double *__restrict__ colG) {
-    __shared__ double2 rxy[HK_WAVE];
-    __shared__ float rv[HK_WAVE];
-    __shared__ double rtd[HK_WAVE];
+    __shared__ SubColRow rows[HK_WAVE];
     __shared__ int rg[HK_WAVE];
     const hk_item it = items[blockIdx.x];
     const int lane = threadIdx.x;
-    const int64_t r = (int64_t)it.tile * HK_WAVE + lane;
+    const int64_t q0 = (int64_t)it.tile * HK_WAVE;
+    const int64_t r = q0 + lane;
     const bool live = r < m;
     const int pj = live ? pos[r] : 0;
-    const double tsj = sts[r];
+    const double t_ref = sts[q0];
     const double2 pxy = sxy[r];
+    double dk = -kc.kw_d * (sts[r] - t_ref);
+    if (DOT) dk -= fma(pxy.x, pxy.x, pxy.y * pxy.y);
+    if (!live) dk = HK_EXP_FLOOR;
     // the chunk's latest entry (entries are in time order)
-    const int64_t r_last = min((int64_t)it.tile * HK_WAVE + HK_WAVE, m) - 1;
+    const int64_t r_last = min(q0 + HK_WAVE, m) - 1;
     const double q_tmax = sts[r_last];
     const int pos_last = pos[r_last];
     double Gd = 0.0, Hd = 0.0;
-    // the entry's split factor exp(omega (t_j - T_c)), evaluated at the first
-    // split chunk with a causal pair (at most exp(HK_COL_SPAN)) and carried
-    // to later chunks by their step factors
-    double uj = 0.0;
-    bool have_uj = false;
     // a row chunk is loaded into registers one chunk ahead, so that the loads of
     // the next chunk are in flight during this one's sweep (items are never empty)
     int nx, ny, ng;
-    float nw;
-    double nt;
+    double nl, nt;
     {
         const int64_t i = (int64_t)it.c_begin * HK_WAVE + lane;
         nx = xi[i];
         ny = yi[i];
-        nw = wv[i];
+        nl = lw[i];
         nt = ts[i];
         ng = g[i];
     }
     for (int c = it.c_begin; c < it.c_end; ++c) {
-        if (have_uj) uj *= cstep[c - 1];
         const int px = nx, py = ny, pg = ng;
-        const float pw = nw;
-        const double pt = nt;
+        const double pl = nl, pt = nt;
         if (c + 1 < it.c_end) {
             const int64_t i = (int64_t)(c + 1) * HK_WAVE + lane;
             nx = xi[i];
             ny = yi[i];
-            nw = wv[i];
+            nl = lw[i];
             nt = ts[i];
             ng = g[i];
         }
         const double Tc = ts[(int64_t)c * HK_WAVE];
         if (Tc - q_tmax > kc.dt_cut_ex) break;  // cutoff: all later rows too far
-        const bool fact = cwide[c] == 0;
-        rxy[lane] = make_double2((double)px * kc.sx, (double)py * kc.sx);
-        rv[lane] = pw;
-        rtd[lane] = pt;
-        rg[lane] = pg;
+        {
+            const double ux = (double)px * kc.sx, uy = (double)py * kc.sx;
+            double cr = pl + kc.kw_d * (pt - t_ref);
+            SubColRow w;
+            if (DOT) {
+                cr -= fma(ux, ux, uy * uy);
+                w.u = make_double2(2.0 * ux, 2.0 * uy);
+            } else {
+                w.u = make_double2(ux, uy);
+            }
+            w.c = fmax(cr, HK_EXP_FLOOR);
+            rows[lane] = w;
+            rg[lane] = pg;
+        }
         __syncthreads();
         float G = 0.0f, H = 0.0f;
         // rows whose tie groups all start after the chunk's last entry need no mask
-        if (pos_last < rg[0]) {
-            if (fact) sub_col_sweep<WITH_H, false, true>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
-            else sub_col_sweep<WITH_H, false, false>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
-        } else {
-            if (fact) sub_col_sweep<WITH_H, true, true>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
-            else sub_col_sweep<WITH_H, true, false>(rxy, rv, rtd, rg, pj, tsj, pxy.x, pxy.y, kc, G, H);
-        }
-        if (G != 0.0f) {
-            if (fact) {
-                if (!have_uj) {
-                    uj = exp(kc.omega * (tsj - Tc));
-                    have_uj = true;
-                }
-                Gd += uj * (double)G;
-                if (WITH_H) Hd += (uj * uj) * (double)H;
-            } else {
-                Gd += (double)G;
-                if (WITH_H) Hd += (double)H;
-            }
-        }
+        if (pos_last < rg[0])
+            sub_col_sweep<WITH_H, false, DOT>(rows, rg, pj, pxy.x, pxy.y, dk, G, H);
+        else
+            sub_col_sweep<WITH_H, true, DOT>(rows, rg, pj, pxy.x, pxy.y, dk, G, H);
+        Gd += (double)G;
+        if (WITH_H) Hd += (double)H;
         __syncthreads();
     }
     double *cg = colG + (int64_t)blockIdx.x * 2 * HK_WAVE;
@@ -822,8 +797,8 @@ __global__ void k_hmc_init(int64_t m, uint64_t seed, uint64_t counter, const dou
 // H = -(sum log lambda - Lam_static - theta0-part) + sum z^2/(2 s^2) + sum p^2/(2M)
 __global__ void k_hmc_accept(const double *__restrict__ scal, const double *__restrict__ Lam_static,
                              double inv_s2, uint64_t seed, uint64_t counter, int64_t m,
-                             const double *__restrict__ z0, double *__restrict__ z, double *__restrict__ out,
-                             int *__restrict__ flag) {
+                             const double *__restrict__ z0, double *__restrict__ z, double *__restrict__ z_prop,
+                             double *__restrict__ out, int *__restrict__ flag) {
     __shared__ int acc;
     if (threadIdx.x == 0) {
         const double ll0 = scal[0] - Lam_static[0] - scal[1];
@@ -849,8 +824,10 @@ __global__ void k_hmc_accept(const double *__restrict__ scal, const double *__re
         out[7] = H1;
     }
     __syncthreads();
-    if (!acc)
-        for (int64_t k = threadIdx.x; k < m; k += blockDim.x) z[k] = z0[k];
+    for (int64_t k = threadIdx.x; k < m; k += blockDim.x) {
+        if (z_prop) z_prop[k] = z[k];
+        if (!acc) z[k] = z0[k];
+    }
 }
 
 // theta_full[idx_k] = exp(z_k) (after a rejection restores z)
@@ -873,7 +850,7 @@ void hk_subset_free(hawkes_plan p) {
     hk_subset *s = p->sub;
     if (!s) return;
     void *ptrs[] = {s->pos, s->slot, s->cidx, s->ritems, s->ritem0, s->rnseg, s->xpart, s->items, s->item0, s->nseg,
-                    s->lam_static, s->Lam_static, s->a, s->tv, s->sxy, s->sts, s->qwide, s->qstep, s->wv, s->cwide, s->cstep, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->off, s->vz, s->scal,
+                    s->lam_static, s->Lam_static, s->a, s->tv, s->sxy, s->sts, s->qwide, s->qstep, s->lw, s->colG, s->gsub, s->hsub, s->sums, s->z0, s->p, s->off, s->vz, s->scal,
                     s->grid};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -999,9 +976,7 @@ extern "C" hawkes_status hawkes_plan_set_subset(hawkes_plan p, int64_t m, const 
     SC(dalloc(&s->sts, s->mpad));
     SC(dalloc(&s->qwide, s->nq));
     SC(dalloc(&s->qstep, s->nq));
-    SC(dalloc(&s->wv, p->npad));
-    SC(dalloc(&s->cwide, p->nchunks));
-    SC(dalloc(&s->cstep, p->nchunks));
+    SC(dalloc(&s->lw, p->npad));
     SC(dalloc(&s->colG, (size_t)s->n_items * 2 * HK_WAVE));
     SC(dalloc(&s->gsub, s->mpad));
     SC(dalloc(&s->hsub, s->mpad));
@@ -1060,8 +1035,7 @@ static void sub_rows(hawkes_plan p, const double *z, const double *off, double *
                        s->tv, s->sxy, s->sts, s->qwide, s->qstep, s->ritems, kc, s->xpart);
     hipLaunchKernelGGL(k_sub_fin, dim3(p->nchunks), dim3(SUB_ROWFIN_WAVES * HK_WAVE), 0, stream, s->lam_static,
                        s->ritem0, s->rnseg,
-                       s->xpart, p->ts, p->n, p->npad, fc, p->lam, s->wv, s->cwide, s->cstep, p->blockpart,
-                       p->status);
+                       s->xpart, p->ts, p->n, p->npad, fc, p->lam, s->lw, p->blockpart, p->status);
 }
 
 // The column half: Eq. 4 (and Eq. 5) on the subset, optionally with the fused
@@ -1069,12 +1043,17 @@ static void sub_rows(hawkes_plan p, const double *z, const double *off, double *
 static void sub_cols(hawkes_plan p, bool with_h, const PairConst &kc, const FinConst &fc, const SubUpd *upd,
                      hipStream_t stream) {
     hk_subset *s = p->sub;
-    if (with_h)
-        hipLaunchKernelGGL(k_sub_col<true>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, s->wv,
-                           s->cwide, s->cstep, p->g, s->pos, s->sxy, s->sts, s->m, s->items, kc, s->colG);
-    else
-        hipLaunchKernelGGL(k_sub_col<false>, dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, s->wv,
-                           s->cwide, s->cstep, p->g, s->pos, s->sxy, s->sts, s->m, s->items, kc, s->colG);
+#define HK_SUBCOL(H, D)                                                                                        \
+    hipLaunchKernelGGL((k_sub_col<H, D>), dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, s->lw, \
+                       p->g, s->pos, s->sxy, s->sts, s->m, s->items, kc, s->colG)
+    if (with_h) {
+        if (kc.dot) HK_SUBCOL(true, true);
+        else HK_SUBCOL(true, false);
+    } else {
+        if (kc.dot) HK_SUBCOL(false, true);
+        else HK_SUBCOL(false, false);
+    }
+#undef HK_SUBCOL
     if (upd)
         hipLaunchKernelGGL(k_sub_colfin<true>, dim3(s->nq), dim3(SUB_FIN_WAVES * HK_WAVE), 0, stream, s->item0,
                            s->nseg, s->colG, s->a, s->m, fc, with_h, s->gsub, s->hsub, *upd);
@@ -1095,6 +1074,16 @@ __global__ void k_z_from_theta(const double *__restrict__ theta, const int64_t *
                                double *__restrict__ z) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k < m) z[k] = log(theta[cidx[k]]);
+}
+
+// z_k = log theta_{idx_k} - beta t_{idx_k} (slot order)
+__global__ void k_z_of_rates(const double *__restrict__ theta, const int *__restrict__ pos,
+                             const int *__restrict__ slot, const int64_t *__restrict__ cidx,
+                             const double *__restrict__ ts, int64_t m, double beta, double *__restrict__ z) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int k = slot[r];
+    z[k] = log(theta[cidx[k]]) - beta * ts[pos[r]];
 }
 
 // d loglik / d z_k = theta_k g_k and d loglik / d beta = sum_k t_k theta_k g_k
@@ -1207,7 +1196,7 @@ extern "C" hawkes_status hmc_step(hawkes_plan p, const hawkes_hyper *hyper, hawk
                        a->d_mass, s->slot, s->a, m, s->scal + 4);
     if (tree && (st = hk_tree_launch(p, a->d_z, nullptr, s->scal + 6, stream)) != HAWKES_OK) return st;
     hipLaunchKernelGGL(k_hmc_accept, dim3(1), dim3(256), 0, stream, s->scal, s->Lam_static, inv_s2, a->seed,
-                       a->counter, m, s->z0, a->d_z, a->d_out, (int *)(s->scal + 8));
+                       a->counter, m, s->z0, a->d_z, a->d_z_proposal, a->d_out, (int *)(s->scal + 8));
     hipLaunchKernelGGL(k_sub_theta_full, dim3(gb), dim3(256), 0, stream, a->d_z, off, s->cidx, m, a->d_theta);
     HK_CHECK(hipGetLastError());
     return HAWKES_OK;
@@ -1281,5 +1270,17 @@ hawkes_status hk_subset_exact(hawkes_plan p, const hawkes_hyper *hy, const doubl
     HK_CHECK(hipGetLastError());
     *gsub = s->gsub;
     *hsub = s->hsub;
+    return HAWKES_OK;
+}
+
+extern "C" hawkes_status hawkes_subset_z(hawkes_plan p, const double *d_theta, double beta, double *d_z,
+                                         hipStream_t stream) {
+    if (!p || !d_theta || !d_z || !isfinite(beta)) return HAWKES_E_INVALID;
+    if (!p->sub) return HAWKES_E_UNSUPPORTED;
+    hk_subset *s = p->sub;
+    p->last_stream = stream;
+    hipLaunchKernelGGL(k_z_of_rates, dim3(nblk(s->m, 256)), dim3(256), 0, stream, d_theta, s->pos, s->slot, s->cidx,
+                       p->ts, s->m, beta, d_z);
+    HK_CHECK(hipGetLastError());
     return HAWKES_OK;
 }

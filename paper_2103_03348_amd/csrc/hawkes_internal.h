@@ -26,12 +26,24 @@
 // FP32 range.
 #define HK_FACT_SPAN 40.0
 
-// The column pass splits the same factor only for chunks of span at most this
-// over omega.  Its staged weight w_i exp(-omega (t_i - T_c)) is small by up to
-// exp(-span) and Eq. 5 squares it, so a wide split would push the squared
-// terms of small H_j towards FP32 underflow (by up to exp(-2 span) before the
-// column factor restores them); at 8 the loss stays below exp(-16).
-#define HK_COL_SPAN 8.0
+// The column passes form the whole exponent of a term c_e E_ij / lambda_i in
+// FP64 (log2 units): log2(c_e / lambda_i), the time term and the spatial term.
+// Exponents are clamped below at this value (every term with an exponent below
+// about -150 is zero in FP32 anyway), which keeps their integer parts inside
+// int32 for padding rows, zero weights and very distant pairs.
+#define HK_EXP_FLOOR (-1.0e5)
+
+// The column passes' spatial exponent -|s (x_i - x_j)|^2 is expanded as
+// 2 s x_i . s x_j - |s x_i|^2 - |s x_j|^2 (one FP64 operation fewer per pair
+// than the differences) when the pre-scaled coordinates are small enough for
+// the cancellation to cost at most ~2^-30 absolute: |s x|^2 <= HK_DOT_MAX2 for
+// every event.  Wider sets (relative to the bandwidth h) take the differences.
+#define HK_DOT_MAX2 524288.0
+
+// Floor of Eq. 5's entries under the log in the learned preconditioner's
+// training target log max(H_k, HK_LOGH_FLOOR) (an entry without later events
+// is exactly 0).
+#define HK_LOGH_FLOOR 1.0e-30
 
 // Time offset given to padding events: their pair terms underflow to exactly
 // zero while every square stays finite in FP32.
@@ -92,9 +104,8 @@ struct hawkes_plan_s {
     float *theta_s;           // [npad] rates in sorted order (FP32), 0 on padding
     float *theta_v;           // [npad] staged rates of the row pass (split time factor applied)
     int *chunk_wide;          // [nchunks] 1 where the chunk takes the direct exponent
-    int *chunk_wide_col;      // [nchunks] the same for the column pass (HK_COL_SPAN)
     double *tstep;            // [nchunks] exp(-omega (T_{c+1} - T_c)) of the last k_tfac
-    float *wv;                // [npad] staged column-pass weights w_i exp(-omega (t_i - T_c))
+    double *lw;               // [npad] log2(c_e / lambda_i) of the last evaluation (HK_EXP_FLOOR on padding)
     float *rowpart;           // [n_row_items][HK_NROW][HK_TILE] row partial sums of each piece
     float *colpart;           // triangular [tile][HK_NCOL][(tile+1)*HK_TILE]: background column partials
     double *lam;              // [npad] lambda_i, sorted
@@ -118,6 +129,8 @@ hipError_t hk_sort_pairs(double *key, int *idx, int64_t n2, hipStream_t stream);
 // z^T V^{-1} z for z [m] in subset slot order (either output may be NULL).
 hawkes_status hk_tree_launch(hawkes_plan p, const double *d_z, double *d_vz, double *d_quad, hipStream_t stream);
 int64_t hk_tree_tips(hawkes_plan p);
+// diagonal of V^{-1} of the plan's tree [m], slot order (device), or NULL
+const double *hk_tree_precision_diag(hawkes_plan p);
 void hk_tree_free(hawkes_plan p);
 // Blocks of a pair pass (0 = row, 1 = column) resident at once on `device`:
 // compute units times the pass kernels' occupancy.
@@ -138,12 +151,18 @@ struct PairConst {
     float kw;      // -omega / ln 2
     float cw;      // ln 2 (kw - kw_f): first-order correction of the rounded kw, per unit dt
     float rex;     // kex / kbx: a_e = a_b rex in the row pass
+    // low parts of the two FP32 constants above (kbt - (double)kbt_f, rex - (double)rex_f):
+    // the log-likelihood-only row pass, which carries no first moments to correct
+    // their rounding with, applies them inside the pair loop instead
+    float kbt_lo;
+    float rex_lo;
     double omega;  // excitation decay rate (time factors formed in FP64)
     double kw_d;   // kw in FP64 (exponents formed in FP64)
     double sx;     // sqrt(-kex): fixed-point coordinate -> coordinate whose squared distance is -a_e
     double sbx;    // sqrt(-kbx): the same for the background exponent a_b
     double dt_cut;     // row pass: time gap past which both terms are below 2^-160 (INFINITY: no cutoff)
     double dt_cut_ex;  // column pass: the same for the excitation term alone
+    int dot;           // column passes: expand the spatial exponent (HK_DOT_MAX2 holds for the plan)
 };
 
 struct FinConst {
@@ -152,6 +171,7 @@ struct FinConst {
     double cb1, ce1;       // c_b / mu0 and c_e / theta0
     double Kx, Kh;         // log2-unit moment -> r^2 moment: -2 tau_x^2 ln 2, -2 h^2 ln 2
     double corr;           // 1 / (1 + exp2 bias)
+    double log2_ce;        // log2(c_e) (-inf when theta0 = 0)
     double t0, t1;
     // First-order correction for the rounding of the FP32 exponent constants:
     // a term computed as exp2(a + d) equals exp2(a) (1 + d ln 2 + O(d^2)), and d
@@ -169,8 +189,9 @@ bool hk_hyper_ok(const hawkes_hyper *h);
 hawkes_status hk_subset_exact(hawkes_plan p, const hawkes_hyper *hy, const double *d_theta, hipStream_t stream,
                               const double **gsub, const double **hsub);
 void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, FinConst *fc);
-// Row pass over all pairs (first moments included) with the sorted FP32 rates
-// already in p->theta_s; leaves the partial sums in p->rowpart / p->colpart.
+// Log-likelihood-only row pass (no moments) with the sorted FP32 rates already
+// in p->theta_s; leaves the partial sums B0 (row slot 0, column slot 0) and X0
+// (row slot 5) in p->rowpart / p->colpart.
 void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream);
 
 // Optional timing of the passes with HIP events recorded on the launch stream.

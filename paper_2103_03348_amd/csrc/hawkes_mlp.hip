@@ -253,22 +253,47 @@ __global__ void k_features(const double *__restrict__ t, const double *__restric
     for (int j = 0; j < MLP_IN; ++j) feat[(int64_t)k * MLP_IN + j] = f[j];
 }
 
-// ---- mass update ---------------------------------------------------------------------------
-// curvature_k = max(theta^2 H - theta g, 0) + 1/s^2 (exact) or max(exp(pred), 1/s^2)
-// (learned: the network predicts the log of the exact estimate); mass <- (count mass
-// + curvature) / (count + 1)
-__global__ void k_mass_update(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
-                              const double *__restrict__ hsub, const float *__restrict__ pred,
-                              const double *__restrict__ theta, const int64_t *__restrict__ cidx, double inv_s2,
-                              double count, double *__restrict__ mass) {
+// ---- curvature and mass update ---------------------------------------------------------
+// In z (theta_k = exp(z_k + beta t_k), so d theta_k / d z_k = theta_k) the
+// log-posterior's curvature on the diagonal is
+//   c_k = theta_k^2 H_k - theta_k g_k + P_kk
+// with g, H Eq. 4 and Eq. 5 on the subset and P the prior's precision
+// diagonal: 1/sigma^2 (iid prior) or (V^{-1})_kk / sigma^2 (Eq. 2).
+__device__ __forceinline__ double prior_prec(const double *__restrict__ pdiag, int k, double inv_s2) {
+    return pdiag ? pdiag[k] * inv_s2 : inv_s2;
+}
+
+// The exact curvature c_k (slot order, FP64) and log max(H_k, HK_LOGH_FLOOR)
+// (FP32, the learned preconditioner's target), either output may be NULL.
+__global__ void k_curvature(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
+                            const double *__restrict__ hsub, const double *__restrict__ theta,
+                            const int64_t *__restrict__ cidx, const double *__restrict__ pdiag, double inv_s2,
+                            double *__restrict__ curv, float *__restrict__ log_h) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= m) return;
     const int k = slot[r];
     const double th = theta[cidx[k]];
-    double curv;
-    if (pred) curv = fmax(exp((double)pred[k]), inv_s2);
-    else curv = fmax(th * th * hsub[r] - th * gsub[r], 0.0) + inv_s2;
-    mass[k] = (count * mass[k] + curv) / (count + 1.0);
+    if (curv) curv[k] = th * th * hsub[r] - th * gsub[r] + prior_prec(pdiag, k, inv_s2);
+    if (log_h) log_h[k] = (float)log(fmax(hsub[r], HK_LOGH_FLOOR));
+}
+
+// mass <- (count mass + e_k) / (count + 1) with the estimate
+//   exact:   e_k = max(theta^2 H - theta g, 0) + P_kk
+//   learned: e_k = theta^2 exp(pred_k) + P_kk   (pred: the network's log H_k)
+__global__ void k_mass_update(const int *__restrict__ slot, int64_t m, const double *__restrict__ gsub,
+                              const double *__restrict__ hsub, const float *__restrict__ pred,
+                              const double *__restrict__ theta, const int64_t *__restrict__ cidx,
+                              const double *__restrict__ pdiag, double inv_s2, double count,
+                              double *__restrict__ mass) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int k = slot[r];
+    const double th = theta[cidx[k]];
+    const double prec = prior_prec(pdiag, k, inv_s2);
+    double est;
+    if (pred) est = th * th * exp((double)pred[k]) + prec;
+    else est = fmax(th * th * hsub[r] - th * gsub[r], 0.0) + prec;
+    mass[k] = (count * mass[k] + est) / (count + 1.0);
 }
 
 }  // namespace
@@ -382,22 +407,54 @@ extern "C" hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hy, 
     return HAWKES_OK;
 }
 
+// The prior's precision diagonal for prior = 0 (iid: NULL, 1/sigma^2) or 1 (the
+// plan's tree); false when the prior is unknown or its tree is not set.
+static bool prior_diag(hawkes_plan p, int prior, int64_t m, const double **pdiag) {
+    *pdiag = nullptr;
+    if (prior == 0) return true;
+    if (prior != 1 || hk_tree_tips(p) != m) return false;
+    *pdiag = hk_tree_precision_diag(p);
+    return *pdiag != nullptr;
+}
+
 extern "C" hawkes_status hawkes_mass_update(hawkes_plan p, const hawkes_hyper *hy, const double *d_theta,
-                                            const float *d_pred, double sigma_z, int64_t count, double *d_mass,
-                                            hipStream_t stream) {
+                                            const float *d_pred, double sigma_z, int prior, int64_t count,
+                                            double *d_mass, hipStream_t stream) {
     if (!p || !hk_hyper_ok(hy) || !d_theta || !d_mass || !(sigma_z > 0.0) || count < 0) return HAWKES_E_INVALID;
     if (!p->sub) return HAWKES_E_UNSUPPORTED;
     int64_t m;
     const int64_t *cidx;
     const int *pos, *slot;
     hk_subset_view(p, &m, &cidx, &pos, &slot);
+    const double *pdiag;
+    if (!prior_diag(p, prior, m, &pdiag)) return prior == 1 ? HAWKES_E_UNSUPPORTED : HAWKES_E_INVALID;
     const double *gsub = nullptr, *hsub = nullptr;
     if (!d_pred) {
         hawkes_status st = hk_subset_exact(p, hy, d_theta, stream, &gsub, &hsub);
         if (st != HAWKES_OK) return st;
     }
     hipLaunchKernelGGL(k_mass_update, dim3(nblk(m, 256)), dim3(256), 0, stream, slot, m, gsub, hsub, d_pred, d_theta,
-                       cidx, 1.0 / (sigma_z * sigma_z), (double)count, d_mass);
+                       cidx, pdiag, 1.0 / (sigma_z * sigma_z), (double)count, d_mass);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
+extern "C" hawkes_status hawkes_subset_curvature(hawkes_plan p, const hawkes_hyper *hy, const double *d_theta,
+                                                 double sigma_z, int prior, double *d_curv, float *d_log_h,
+                                                 hipStream_t stream) {
+    if (!p || !hk_hyper_ok(hy) || !d_theta || !(sigma_z > 0.0) || (!d_curv && !d_log_h)) return HAWKES_E_INVALID;
+    if (!p->sub) return HAWKES_E_UNSUPPORTED;
+    int64_t m;
+    const int64_t *cidx;
+    const int *pos, *slot;
+    hk_subset_view(p, &m, &cidx, &pos, &slot);
+    const double *pdiag;
+    if (!prior_diag(p, prior, m, &pdiag)) return prior == 1 ? HAWKES_E_UNSUPPORTED : HAWKES_E_INVALID;
+    const double *gsub = nullptr, *hsub = nullptr;
+    hawkes_status st = hk_subset_exact(p, hy, d_theta, stream, &gsub, &hsub);
+    if (st != HAWKES_OK) return st;
+    hipLaunchKernelGGL(k_curvature, dim3(nblk(m, 256)), dim3(256), 0, stream, slot, m, gsub, hsub, d_theta, cidx,
+                       pdiag, 1.0 / (sigma_z * sigma_z), d_curv, d_log_h);
     HK_CHECK(hipGetLastError());
     return HAWKES_OK;
 }

@@ -18,7 +18,12 @@
 //  * V^{-1} z is the gradient of half the quadratic form: a pre-order pass
 //    pushes the adjoint of each node to its children,
 //    mbar_b = alpha_b mbar_a + d_a, mbar_c = alpha_c mbar_a - d_a,
-//    d_a = (m_b - m_c) / s_a, starting from mbar_root = m_root / (v_root + tau0).
+//    d_a = (m_b - m_c) / s_a, starting from mbar_root = m_root / (v_root + tau0);
+//  * the diagonal of V^{-1} (the prior's precision, used by the diagonal mass
+//    matrix) is 1 / Var(z_k | every other tip): a pre-order pass carries the
+//    variance u_a of what the rest of the tree says about node a, u_root =
+//    tau0, u_b = (u_a (v_c + w_c)) / (u_a + v_c + w_c) + w_b for child b with
+//    sibling c, and (V^{-1})_kk = 1 / u_k at tip k.
 //
 // The v, alpha, s depend on the tree only and are formed once on the host in
 // FP64.  On the device one block walks the levels of the tree (nodes grouped by
@@ -47,6 +52,7 @@ struct hk_tree {
     int root;
     double root_inv;     // 1 / (v_root + tau0)
     int *level0_h;       // host copy of level0 (launch loop bounds)
+    double *pdiag;       // [m] diagonal of V^{-1}, tip (slot) order (device)
 };
 
 namespace {
@@ -129,7 +135,7 @@ hipError_t dalloc(T **p, size_t count) {
 void hk_tree_free(hawkes_plan p) {
     hk_tree *t = p->tree;
     if (!t) return;
-    void *ptrs[] = {t->order, t->level0, t->child, t->coef, t->mv, t->dd};
+    void *ptrs[] = {t->order, t->level0, t->child, t->coef, t->mv, t->dd, t->pdiag};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete[] t->level0_h;
@@ -138,6 +144,8 @@ void hk_tree_free(hawkes_plan p) {
 }
 
 int64_t hk_tree_tips(hawkes_plan p) { return p->tree ? p->tree->m : 0; }
+
+const double *hk_tree_precision_diag(hawkes_plan p) { return p->tree ? p->tree->pdiag : nullptr; }
 
 hawkes_status hk_tree_launch(hawkes_plan p, const double *d_z, double *d_vz, double *d_quad, hipStream_t stream) {
     hk_tree *t = p->tree;
@@ -219,6 +227,23 @@ extern "C" hawkes_status hawkes_plan_set_tree(hawkes_plan p, int64_t n_nodes, co
     }
     const double rv = var[root] + tau0;
     logdet += log(rv);
+    // diagonal of V^{-1}: pre-order pass of the outside variances (reverse post-order)
+    std::vector<double> outside(n_nodes, 0.0), pdiag(m, 0.0);
+    outside[root] = tau0;
+    for (auto it = post.rbegin(); it != post.rend(); ++it) {
+        const int v = *it;
+        if (v < m) {
+            if (!(outside[v] > 0.0)) return HAWKES_E_INVALID;  // tip fixed by the others: V is singular
+            pdiag[v] = 1.0 / outside[v];
+            continue;
+        }
+        for (int k = 0; k < 2; ++k) {
+            const int b = child[2 * v + k], c = child[2 * v + 1 - k];
+            const double u = outside[v], vs = var[c] + length[c];
+            const double x = u + vs > 0.0 ? u * vs / (u + vs) : 0.0;
+            outside[b] = x + length[b];
+        }
+    }
     const int H = m > 1 ? height[root] : 0;
     std::vector<int> level0(H + 1, 0), order;
     for (int64_t v = m; v < n_nodes; ++v) level0[height[v]]++;  // heights 1..H
@@ -256,10 +281,12 @@ extern "C" hawkes_status hawkes_plan_set_tree(hawkes_plan p, int64_t n_nodes, co
     TC(dalloc(&t->coef, coef.size()));
     TC(dalloc(&t->mv, (size_t)n_nodes));
     TC(dalloc(&t->dd, (size_t)n_nodes));
+    TC(dalloc(&t->pdiag, (size_t)m));
     TC(hipMemcpy(t->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
     TC(hipMemcpy(t->level0, start.data(), sizeof(int) * (H + 1), hipMemcpyHostToDevice));
     TC(hipMemcpy(t->child, child.data(), sizeof(int) * child.size(), hipMemcpyHostToDevice));
     TC(hipMemcpy(t->coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice));
+    TC(hipMemcpy(t->pdiag, pdiag.data(), sizeof(double) * m, hipMemcpyHostToDevice));
 #undef TC
     return HAWKES_OK;
 }

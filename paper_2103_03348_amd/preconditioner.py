@@ -1,15 +1,15 @@
 """Learned diagonal preconditioner for the HMC step.
 
-A 12 -> 64 -> 64 -> 1 tanh network predicts, for free event k, the log of the
-exact diagonal mass estimate max(theta_k^2 H_k - theta_k g_k, 0) + 1/sigma_z^2
-(the z-space curvature from Eq. 4 and the Eq. 5 Hessian diagonal) from cheap
-per-event features (grid-cell counts, recent-window counts, log theta, time
-rank, time to the window end).  It is trained on the GPU by the library's own
-forward, back-propagation and Adam kernels on exact estimates collected at
-saved HMC states.  The sampler folds max(exp(prediction), 1/sigma_z^2) into
-its running-average mass and still folds in the exact estimate at a coarser
-interval; because any positive mass leaves the target invariant, the sampler
-stays exact whatever the network predicts.
+A 12 -> 64 -> 64 -> 1 tanh network predicts, for free event k, log H_k: the
+log of Eq. 5's Hessian diagonal, which the paper uses as the HMC mass, from
+cheap per-event features (grid-cell counts, recent-window counts, log theta,
+time rank, time to the window end).  It is trained on the GPU by the library's
+own forward, back-propagation and Adam kernels on exact Eq. 5 diagonals that
+the library computes at saved HMC states.  The sampler folds the learned
+estimate theta_k^2 exp(prediction) + P_kk (the prior's precision P added when
+the mass is formed) into its running-average mass and still folds in the exact
+estimate at a coarser interval; because any positive mass leaves the target
+invariant, the sampler stays exact whatever the network predicts.
 """
 from __future__ import annotations
 
@@ -62,9 +62,9 @@ class LearnedPreconditioner:
         return self.feat
 
     def collect(self, n_states: int, eps: float, thin: int = 1):
-        """Advance the sampler (current mass) and record features and the log of
-        the exact mass estimate at n_states states.  Returns (X [n_states*m, 12],
-        T [n_states*m])."""
+        """Advance the sampler (current mass) and record the features and the
+        training target log max(H_k, 1e-30) (Eq. 5 on the subset, computed by the
+        library) at n_states states.  Returns (X [n_states*m, 12], T [n_states*m])."""
         m = self.s.m
         X = torch.empty((n_states * m, N_FEATURES), dtype=torch.float32, device=self.dev)
         T = torch.empty(n_states * m, dtype=torch.float32, device=self.dev)
@@ -72,7 +72,7 @@ class LearnedPreconditioner:
             for _ in range(thin):
                 self.s.step(eps)
             X[k * m:(k + 1) * m].copy_(self.features())
-            T[k * m:(k + 1) * m].copy_(torch.log(self.s.exact_curvature()).float())
+            self.s.curvature(log_h=T[k * m:(k + 1) * m])
         return X, T
 
     # ---- training ------------------------------------------------------------------------------
@@ -105,11 +105,16 @@ class LearnedPreconditioner:
         return hist
 
     def evaluate(self, X: torch.Tensor, T: torch.Tensor) -> float:
-        """Mean squared error of the prediction on (X, T)."""
-        y = torch.empty(X.shape[0], dtype=torch.float32, device=self.dev)
-        _lib.check(_lib.lib().hawkes_mlp_forward(_lib.ptr(self.params), _lib.ptr(X), X.shape[0], _lib.ptr(y),
-                                                 _lib.stream_handle()), "hawkes_mlp_forward")
-        return float(((y.double() - T.double()) ** 2).mean().item())
+        """Mean squared error of the prediction on (X, T), by the library's loss
+        (hawkes_mlp_grad over all rows; its gradient is discarded)."""
+        n = X.shape[0]
+        work = torch.empty(int(_lib.lib().hawkes_mlp_workspace_floats(n)), dtype=torch.float32, device=self.dev)
+        grad = torch.empty(self.np, dtype=torch.float64, device=self.dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        _lib.check(_lib.lib().hawkes_mlp_grad(_lib.ptr(self.params), _lib.ptr(X.contiguous()), n, None,
+                                              _lib.ptr(T.contiguous()), n, _lib.ptr(work), _lib.ptr(grad),
+                                              _lib.ptr(loss), None, _lib.stream_handle()), "hawkes_mlp_grad")
+        return float(loss.item())
 
     # ---- use in the sampler --------------------------------------------------------------------
     def predict(self) -> torch.Tensor:
@@ -123,6 +128,6 @@ class LearnedPreconditioner:
         pred = self.predict()
         _lib.check(_lib.lib().hawkes_mass_update(sampler.plan.handle, ctypes.byref(sampler.hyper),
                                                  _lib.ptr(sampler.theta), _lib.ptr(pred), sampler.sigma_z,
-                                                 sampler.mass_count, _lib.ptr(sampler.mass), _lib.stream_handle()),
-                   "hawkes_mass_update")
+                                                 sampler.prior, sampler.mass_count, _lib.ptr(sampler.mass),
+                                                 _lib.stream_handle()), "hawkes_mass_update")
         sampler.mass_count += 1

@@ -11,11 +11,12 @@ per iteration.  Between iterations it adapts:
   * the diagonal mass matrix, as the running average of preconditioner
     estimates computed at a fixed interval (the paper's adaptation, which keeps
     Monte Carlo estimates asymptotically unbiased).  The estimate is either the
-    exact z-space curvature theta^2 H - theta g + 1/sigma_z^2 (Eq. 4 and Eq. 5 by
-    the O(N M) subset path, floored at the prior precision), or the learned
-    prediction of a small network (preconditioner.py), or the identity-scaled
-    prior precision (no preconditioning).
-Only the scalar control (step size, iteration counters) lives on the host.
+    exact z-space curvature theta^2 H - theta g + P (Eq. 4 and Eq. 5 by the O(N
+    M) subset path, floored at the prior's precision P), or theta^2 exp(y) + P
+    with y a small network's prediction of log H (preconditioner.py), or the
+    prior's precision alone (no preconditioning).
+Only the scalar control (step size, iteration counters) lives on the host; every
+quantity of the method is computed by the library.
 """
 from __future__ import annotations
 
@@ -76,36 +77,35 @@ class HmcSampler:
         self.beta = float(beta)  # temporal trend: theta_k = exp(z_k + beta t_k) (Sec. 2.2)
         self.prior = 0           # 0: z ~ N(0, sigma_z^2 I); 1: phylogenetic prior (set_tree)
         self._jrng = np.random.default_rng(seed)
-        t_sub = plan._t[self.idx]
-        self.z = (torch.log(self.theta[self.idx]) - self.beta * t_sub).contiguous()
+        self.z = torch.empty(self.m, dtype=torch.float64, device=self.dev)
+        _lib.check(_lib.lib().hawkes_subset_z(plan.handle, _lib.ptr(self.theta), self.beta, _lib.ptr(self.z),
+                                              _lib.stream_handle()), "hawkes_subset_z")
+        # the prior's precision 1/sigma_z^2 until the first estimate is folded in
         self.mass = torch.full((self.m,), 1.0 / self.sigma_z ** 2, dtype=torch.float64, device=self.dev)
         self.mass_count = 0
         self.out = torch.zeros(8, dtype=torch.float64, device=self.dev)
-        self._g = torch.empty(self.m, dtype=torch.float64, device=self.dev)
-        self._h = torch.empty(self.m, dtype=torch.float64, device=self.dev)
 
     # ---- preconditioner estimates ----------------------------------------------------------
-    def exact_curvature(self) -> torch.Tensor:
-        """-d2 log pi / dz^2 on the subset at the current state (chain rule on Eq. 4, 5)."""
-        _lib.check(_lib.lib().hawkes_subset_grad(self.plan.handle, ctypes.byref(self.hyper), _lib.ptr(self.theta),
-                                                 0, None, _lib.ptr(self._g), _lib.ptr(self._h),
-                                                 _lib.stream_handle()), "hawkes_subset_grad")
-        th = torch.exp(self.z)
-        prec = 1.0 / self.sigma_z ** 2
-        return torch.clamp(th * th * self._h - th * self._g, min=0.0) + prec
+    def curvature(self, curv: torch.Tensor = None, log_h: torch.Tensor = None):
+        """The library's hawkes_subset_curvature at the current state, into the
+        given device buffers (slot order): the exact z-space curvature
+        theta^2 H - theta g + P (FP64) and log max(H, 1e-30) (FP32)."""
+        _lib.check(_lib.lib().hawkes_subset_curvature(self.plan.handle, ctypes.byref(self.hyper),
+                                                      _lib.ptr(self.theta), self.sigma_z, self.prior,
+                                                      _lib.ptr(curv), _lib.ptr(log_h), _lib.stream_handle()),
+                   "hawkes_subset_curvature")
 
-    def exact_theta_hessian(self) -> torch.Tensor:
-        """Eq. 5 on the subset (the learned preconditioner's training target)."""
-        _lib.check(_lib.lib().hawkes_subset_grad(self.plan.handle, ctypes.byref(self.hyper), _lib.ptr(self.theta),
-                                                 0, None, None, _lib.ptr(self._h), _lib.stream_handle()),
-                   "hawkes_subset_grad")
-        return self._h.clone()
+    def exact_curvature(self) -> torch.Tensor:
+        """-d2 log pi / dz^2 on the subset at the current state (a new FP64 tensor)."""
+        out = torch.empty(self.m, dtype=torch.float64, device=self.dev)
+        self.curvature(curv=out)
+        return out
 
     def fold_exact(self):
         """Fold the exact curvature at the current state into the running-average mass."""
         _lib.check(_lib.lib().hawkes_mass_update(self.plan.handle, ctypes.byref(self.hyper), _lib.ptr(self.theta),
-                                                 None, self.sigma_z, self.mass_count, _lib.ptr(self.mass),
-                                                 _lib.stream_handle()), "hawkes_mass_update")
+                                                 None, self.sigma_z, self.prior, self.mass_count,
+                                                 _lib.ptr(self.mass), _lib.stream_handle()), "hawkes_mass_update")
         self.mass_count += 1
 
     def set_tree(self, parent, length, tau0):
@@ -140,7 +140,8 @@ class HmcSampler:
         if self.jitter > 0:
             eps = eps * self._jrng.uniform(1.0 - self.jitter, 1.0 + self.jitter)
         args = _lib.HmcArgs(self.z.data_ptr(), self.theta.data_ptr(), self.mass.data_ptr(), float(eps), self.L,
-                            self.sigma_z, self.seed, self.counter, 0, self.out.data_ptr(), self.beta, self.prior)
+                            self.sigma_z, self.seed, self.counter, 0, self.out.data_ptr(), self.beta, self.prior,
+                            None)
         _lib.check(_lib.lib().hmc_step(self.plan.handle, ctypes.byref(self.hyper), ctypes.byref(args),
                                        _lib.stream_handle()), "hmc_step")
         self.counter += 1

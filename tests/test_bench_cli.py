@@ -22,6 +22,9 @@ def test_bench_roofline_constants():
     # non-packed FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
     assert abs(bench.PEAK_FP32_NONPACKED_TFLOPS - 78.6432) < 1e-9
     assert bench.PEAK_FP32_PUBLISHED_TFLOPS == 157.3
+    # the algorithmic count of the measured evaluation: 59 flops and 3 exponentials per pair
+    assert bench.FLOPS_PER_PAIR == 59
     assert bench.FLOPS_PER_PAIR == bench.FLOPS_ROW_PER_PAIR + bench.FLOPS_COL_PER_PAIR
+    assert bench.EXPS_ROW_PER_PAIR + bench.EXPS_COL_PER_PAIR == 3
     # the traffic figure is either the measured one or withheld, never something else
     assert bench.k_row_traffic() in (None, bench.K_ROW_TRAFFIC_BYTES)

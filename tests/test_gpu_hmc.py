@@ -8,6 +8,8 @@ import oracle
 from oracle import hmc as ohmc
 from paper_2103_03348_amd import synth
 
+from gpu_helpers import h_rel_all
+
 pytestmark = pytest.mark.gpu
 
 
@@ -69,8 +71,7 @@ def test_subset_grad_matches_oracle(gpu, cfg):
     a = es.hyper[3] * (1.0 - np.exp(-es.hyper[4] * (es.t.max() - es.t[es.subset])))
     rel_l = abs(ll - ref["loglik"]) / abs(ref["loglik"])
     rel_g = np.max(np.abs(g - gi) / np.maximum(gi + 2 * a, 1e-300))
-    sig = hi >= 1e-4 * hi.max()
-    rel_h = np.max(np.abs(h - hi)[sig] / hi[sig])
+    rel_h = h_rel_all(h, hi)
     print(f"\nsubset {cfg}: n={es.n} m={es.subset.shape[0]} loglik rel {rel_l:.2e} g {rel_g:.2e} H {rel_h:.2e}")
     assert rel_l < (1e-9 if cfg == "n23422" else 2e-6 * es.n / abs(ref["loglik"]))
     assert rel_g < 1e-6
@@ -382,3 +383,77 @@ def test_hmc_step_with_tree_prior_replays_oracle(gpu):
             assert bool(o[0]) == r["accepted"]
         if r["accepted"]:
             np.testing.assert_allclose(z.cpu().numpy(), r["z_proposal"], atol=1e-6)
+
+
+def test_hmc_step_replays_oracle_n23422(gpu):
+    """Whole hmc_step iterations on the N = 23,422 workload (1,610 free rates:
+    26 subset chunks, so the fused kick/drift, the per-chunk staging of the
+    updated rates and the batched energy gather all run over many chunks), L =
+    20, two Philox counters each, for the iid prior, the temporal trend and the
+    phylogenetic prior, against the FP64 oracle's iterations stored by
+    tests/golden/make_hmc_replay.py.  Compared on every counter, accepted or
+    not: the end of the leapfrog path, H0, the energy change and the
+    log-likelihood at the proposal; the accept decision wherever the oracle's
+    log u is not within 1e-4 of -dH.
+
+    Tolerances: the log-likelihood's target of 1e-9 relative at each end, so
+    2e-9 |loglik| on dH and 1e-9 |H0| on H0; the path's end to 1e-6 (the FP32
+    gradient's ~1e-7 relative error carried through 20 steps of size 0.03)."""
+    import os
+
+    import torch
+
+    from oracle import tree as otree  # noqa: F401  (the stored file was written with it)
+    from paper_2103_03348_amd import _lib
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hmc_replay_N23422.npz")
+    gold = np.load(path)
+    es = synth.config(3)
+    plan, idx = _setup(es)
+    m = es.subset.shape[0]
+    eps, L, sigma = float(gold["eps"]), int(gold["L"]), float(gold["sigma"])
+    mass = gold["mass"]
+    z0 = gold["z0"]
+    np.testing.assert_array_equal(z0, np.log(es.theta[es.subset]))
+    par, ln = synth.coalescent_tree(m, seed=int(gold["tree_seed"]), scale=float(m))
+    par, ln = np.ascontiguousarray(par), np.ascontiguousarray(ln)
+    _lib.check(_lib.lib().hawkes_plan_set_tree(plan.handle, 2 * m - 1, par.ctypes.data_as(ctypes.c_void_p),
+                                               ln.ctypes.data_as(ctypes.c_void_p), float(gold["tree_tau0"])),
+               "set_tree")
+    dev = "cuda:0"
+    for name in ("iid", "trend", "tree"):
+        for counter in (0, 1):
+            key = f"{name}_{counter}"
+            beta, seed = float(gold[f"{key}_beta"]), int(gold[f"{key}_seed"])
+            z = torch.as_tensor(z0.copy(), device=dev)
+            th = torch.as_tensor(es.theta.copy(), device=dev)
+            ms = torch.as_tensor(mass, device=dev)
+            out = torch.zeros(8, dtype=torch.float64, device=dev)
+            zp = torch.zeros(m, dtype=torch.float64, device=dev)
+            args = _lib.HmcArgs(z.data_ptr(), th.data_ptr(), ms.data_ptr(), eps, L, sigma, seed, counter, 0,
+                                out.data_ptr(), beta, 1 if name == "tree" else 0, zp.data_ptr())
+            hy = _lib.Hyper.of(es.hyper)
+            _lib.check(_lib.lib().hmc_step(plan.handle, ctypes.byref(hy), ctypes.byref(args), _lib.stream_handle()),
+                       "hmc_step")
+            torch.cuda.synchronize()
+            assert plan.status() == 0
+            o = out.cpu().numpy()
+            zpg = zp.cpu().numpy()
+            dH, H0, llp = float(gold[f"{key}_dH"]), float(gold[f"{key}_H0"]), float(gold[f"{key}_loglik_proposal"])
+            acc = bool(gold[f"{key}_accepted"])
+            dz = float(np.max(np.abs(zpg - gold[f"{key}_z_proposal"])))
+            print(f"\n{key}: dH gpu {o[1]:.9f} oracle {dH:.9f} | H0 rel {abs(o[6] - H0) / abs(H0):.2e} | "
+                  f"loglik(prop) rel {abs(o[5] - llp) / abs(llp):.2e} | z_prop max abs {dz:.2e} | "
+                  f"accepted gpu {int(o[0])} oracle {int(acc)}", flush=True)
+            assert abs(o[1] - dH) <= 2e-9 * abs(llp)
+            assert abs(o[6] - H0) <= 1e-9 * abs(H0)
+            assert abs(o[5] - llp) <= 1e-9 * abs(llp)
+            assert dz < 1e-6
+            if abs(np.log(float(gold[f"{key}_u"])) + dH) > 1e-4:
+                assert bool(o[0]) == acc
+            zg = z.cpu().numpy()
+            if bool(o[0]):
+                np.testing.assert_array_equal(zg, zpg)
+            else:
+                np.testing.assert_array_equal(zg, z0)
+    plan.close()

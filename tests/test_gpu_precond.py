@@ -129,49 +129,105 @@ def test_features_match_oracle(gpu, cfg):
     np.testing.assert_allclose(F[sub], ref, rtol=1e-6, atol=1e-6)
 
 
-def test_exact_mass_update_matches_oracle(gpu):
-    """mass <- curvature (count 0): max(theta^2 H - theta g, 0) + 1/sigma^2 on the subset."""
+@pytest.mark.parametrize("variant", ["iid", "trend", "tree"])
+def test_curvature_and_mass_update_match_oracle(gpu, variant):
+    """hawkes_subset_curvature: the z-space curvature theta^2 H - theta g + P
+    (Eq. 4, Eq. 5 and the chain rule through theta_k = exp(z_k + beta t_k)) and
+    log H, against the oracle's z_hessian_diag (itself pinned by central
+    differences of the log-posterior gradient) at beta = 0, at beta != 0 and
+    with the tree prior of Eq. 2 (P = diag(V^{-1}) / sigma^2 there); then the
+    exact and the learned mass estimates folded by hawkes_mass_update."""
     import torch
 
+    from oracle import tree as otree
     from paper_2103_03348_amd import _lib
 
     es = synth.small(1200, seed=32, all_free=False)
     plan = _plan_with_subset(es)
+    m = es.subset.shape[0]
     sig = 0.5
-    mass = torch.zeros(es.subset.shape[0], dtype=torch.float64, device="cuda:0")
+    beta = -0.004 if variant == "trend" else 0.0
+    prior = 1 if variant == "tree" else 0
+    V = None
+    if prior:
+        par, ln = synth.coalescent_tree(m, seed=32, scale=float(m))
+        par, ln = np.ascontiguousarray(par), np.ascontiguousarray(ln)
+        _lib.check(_lib.lib().hawkes_plan_set_tree(plan.handle, 2 * m - 1, par.ctypes.data_as(ctypes.c_void_p),
+                                                   ln.ctypes.data_as(ctypes.c_void_p), 0.8), "set_tree")
+        V = otree.covariance(par, ln, 0.8)
+    z = np.log(es.theta[es.subset]) + 0.1
+    th = ohmc.rates(es.t, es.theta, es.subset, z, beta)
     hy = _lib.Hyper.of(es.hyper)
-    dth = _t(es.theta)
-    _lib.check(_lib.lib().hawkes_mass_update(plan.handle, ctypes.byref(hy), _lib.ptr(dth), None, sig, 0,
+    dth = _t(th)
+    # z recovered from the rates by the library
+    dz = torch.empty(m, dtype=torch.float64, device="cuda:0")
+    _lib.check(_lib.lib().hawkes_subset_z(plan.handle, _lib.ptr(dth), beta, _lib.ptr(dz), _lib.stream_handle()),
+               "subset_z")
+    curv = torch.empty(m, dtype=torch.float64, device="cuda:0")
+    logh = torch.empty(m, dtype=torch.float32, device="cuda:0")
+    _lib.check(_lib.lib().hawkes_subset_curvature(plan.handle, ctypes.byref(hy), _lib.ptr(dth), sig, prior,
+                                                  _lib.ptr(curv), _lib.ptr(logh), _lib.stream_handle()),
+               "curvature")
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(dz.cpu().numpy(), z, rtol=0, atol=1e-13)
+    ref = ohmc.z_hessian_diag(es.t, es.x, es.y, es.theta, es.subset, z, es.hyper, 0.0, sig, beta=beta, prior_v=V)
+    prec = ohmc.prior_precision_diag(m, sig, V)
+    r = oracle.evaluate_es(es, theta=th, want=("grad_theta", "negH_theta"))
+    H, g = r["negH_theta"][es.subset], r["grad_theta"][es.subset]
+    tk = th[es.subset]
+    # C11 scale of the chain rule's terms: theta^2 H + theta (|g| + 2 a) + P
+    a = es.hyper[3] * (1.0 - np.exp(-es.hyper[4] * (es.t.max() - es.t[es.subset])))
+    scale = tk * tk * H + tk * (np.abs(g) + 2 * a) + prec
+    c = curv.cpu().numpy()
+    rel = float(np.max(np.abs(c - ref) / scale))
+    lh = logh.cpu().numpy().astype(np.float64)
+    lh_ref = np.log(np.maximum(H, 1e-30))
+    print(f"\n[{variant}] curvature rel {rel:.2e}  log H max abs {np.max(np.abs(lh - lh_ref)):.2e}", flush=True)
+    assert rel < 1e-6
+    # FP32 output of log H: its rounding (|log H| <= 69, 2^-24 relative) plus Eq. 5's 1e-6
+    np.testing.assert_allclose(lh, lh_ref, rtol=2e-7, atol=2e-6)
+    # exact estimate, floored at the prior's precision (count 0: the mass becomes it)
+    mass = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+    _lib.check(_lib.lib().hawkes_mass_update(plan.handle, ctypes.byref(hy), _lib.ptr(dth), None, sig, prior, 0,
                                              _lib.ptr(mass), _lib.stream_handle()), "mass")
     torch.cuda.synchronize()
-    ref = ohmc.z_hessian_diag(es.t, es.x, es.y, es.theta, es.subset, np.log(es.theta[es.subset]), es.hyper, 0.0, sig)
-    ref = np.maximum(ref - 1.0 / sig ** 2, 0.0) + 1.0 / sig ** 2
-    np.testing.assert_allclose(mass.cpu().numpy(), ref, rtol=1e-6)
+    want = np.maximum(ref - prec, 0.0) + prec
+    assert float(np.max(np.abs(mass.cpu().numpy() - want) / scale)) < 1e-6
+    # learned estimate theta^2 exp(pred) + P, folded with weight 1/2 (count 1)
+    pred = np.linspace(-6.0, 1.0, m).astype(np.float32)
+    dpred = torch.as_tensor(pred, device="cuda:0")
+    mass0 = mass.clone()
+    _lib.check(_lib.lib().hawkes_mass_update(plan.handle, ctypes.byref(hy), _lib.ptr(dth), _lib.ptr(dpred), sig,
+                                             prior, 1, _lib.ptr(mass), _lib.stream_handle()), "mass learned")
+    torch.cuda.synchronize()
+    est = tk * tk * np.exp(pred.astype(np.float64)) + prec
+    np.testing.assert_allclose(mass.cpu().numpy(), 0.5 * (mass0.cpu().numpy() + est), rtol=1e-13)
+    plan.close()
 
 
 def test_learned_preconditioner_gain(gpu):
-    """What the trained network gains over the method without it.  On exact
-    z-curvature estimates collected along an HMC chain (N = 23,422, 1,610 free
+    """What the trained network gains over the method without it.  On Eq. 5
+    diagonals (log H) collected along an HMC chain (N = 23,422, 1,610 free
     rates) and held out from training, the network's prediction must beat
-    (a) its untrained self by a wide margin, (b) the best constant predictor
-    (the targets' mean), and (c) the unpreconditioned mass 1/sigma_z^2, which is
-    what the sampler uses without any preconditioner.  On this workload the
-    prior precision 1/sigma_z^2 = 4 is most of the curvature (the likelihood
-    adds about 1%), so (c) is a small margin: the network recovers about half
-    of the curvature's variation from the grid-count features."""
+    (a) its untrained self by a wide margin and (b) the best constant
+    predictor (the targets' mean); and (c) at the chain's last state the
+    learned mass theta^2 exp(y) + 1/sigma_z^2 must be closer to the exact mass
+    theta^2 H + 1/sigma_z^2 than the unpreconditioned 1/sigma_z^2 is."""
     import torch
 
+    from paper_2103_03348_amd import _lib
     from paper_2103_03348_amd.hawkes import Plan
     from paper_2103_03348_amd.preconditioner import LearnedPreconditioner
     from paper_2103_03348_amd.sampler import HmcSampler
 
     es = synth.config(3)
     dev = "cuda:0"
+    sig = 2.0
     t = torch.as_tensor(es.t, device=dev)
     xy = torch.as_tensor(np.stack([es.x, es.y], 1), device=dev).contiguous()
     plan = Plan(t, xy, es.t0)
     smp = HmcSampler(plan, torch.as_tensor(es.theta, device=dev), torch.as_tensor(es.subset, device=dev),
-                     es.hyper, sigma_z=0.5, L=20, seed=3)
+                     es.hyper, sigma_z=sig, L=20, seed=3)
     r = smp.run(0, 150, eps0=0.05, mass="exact", refresh=25, record=False)
     pre = LearnedPreconditioner(smp, t, xy, seed=3)
     X, T = pre.collect(60, r["eps"], thin=2)
@@ -181,20 +237,19 @@ def test_learned_preconditioner_gain(gpu):
     loss0 = pre.evaluate(Xva, Tva)
     pre.train(Xtr, Ttr, steps=800, batch=4096, lr=2e-3, seed=3)
     loss1 = pre.evaluate(Xva, Tva)
-    Tv = Tva.double().cpu().numpy()
-    var = float(Tv.var())
-    y = torch.empty(Xva.shape[0], dtype=torch.float32, device=dev)
-    from paper_2103_03348_amd import _lib
-    _lib.check(_lib.lib().hawkes_mlp_forward(_lib.ptr(pre.params), _lib.ptr(Xva), Xva.shape[0], _lib.ptr(y),
-                                             _lib.stream_handle()), "forward")
-    prec = 1.0 / 0.5 ** 2
-    exact = np.exp(Tv)
-    learned = np.maximum(np.exp(y.double().cpu().numpy()), prec)
-    err_learned = float(np.mean(np.abs(learned - exact) / exact))
+    var = float(Tva.double().var().item())
+    # masses at the last state (its features and targets are the last m rows)
+    y = pre.predict().double().cpu().numpy()
+    th = smp.theta[smp.idx].double().cpu().numpy()
+    H = np.exp(T[-m:].double().cpu().numpy())
+    prec = 1.0 / sig ** 2
+    exact = th * th * H + prec
+    err_learned = float(np.mean(np.abs(th * th * np.exp(y) + prec - exact) / exact))
     err_identity = float(np.mean(np.abs(prec - exact) / exact))
     plan.close()
-    print(f"\nheld-out MSE (log curvature): untrained {loss0:.3e} trained {loss1:.3e} constant {var:.3e}; "
-          f"mean relative mass error: learned {err_learned:.3e}, identity {err_identity:.3e}", flush=True)
+    print(f"\nheld-out MSE (log H): untrained {loss0:.3e} trained {loss1:.3e} constant {var:.3e}; "
+          f"mean relative mass error at the last state: learned {err_learned:.3e}, identity {err_identity:.3e}",
+          flush=True)
     assert loss1 < 0.01 * loss0
     assert loss1 < 0.8 * var
     assert err_learned < err_identity
