@@ -137,13 +137,21 @@ def test_autograd_backward_n100k(gpu, n100k):
     assert rel_fd_gpu < 1e-6
 
     # a backward after the plan has evaluated something else recomputes the
-    # intensities (stale forward) and still gives the same gradient
+    # intensities (stale forward).  That evaluation asks for the rate gradient
+    # alone and so takes the log-likelihood-only row pass, whose intensities
+    # are rounded differently from the forward's (its FP32 exponent constants
+    # are completed inside the pair loop rather than through the first
+    # moments): the gradient is held to the oracle at the same bar.
     theta2 = torch.as_tensor(es.theta, device=dev).requires_grad_(True)
     ll2 = autograd.loglik(theta2, hyper.detach(), plan)
     plan.eval(torch.ones(es.n, dtype=torch.float64, device=dev), es.hyper, loglik=True)
     ll2.backward()
     torch.cuda.synchronize()
-    assert np.max(np.abs(theta2.grad.cpu().numpy() - gt) / scale) < 1e-12
+    g2 = theta2.grad.cpu().numpy()
+    rel_g2 = np.max(np.abs(g2 - ref["grad_theta"]) / scale)
+    print(f"[autograd N=100,000] stale-forward backward: grad_theta {rel_g2:.2e}", flush=True)
+    assert rel_g2 < 1e-6
+    assert np.max(np.abs(g2 - gt) / scale) < 2e-6
     plan.close()
 
 
