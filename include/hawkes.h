@@ -62,8 +62,10 @@ typedef enum {
     HAWKES_E_DEVICE = 4,         /* a HIP runtime call failed                                  */
     HAWKES_E_NOMEM = 5,          /* device allocation failed                                   */
     HAWKES_E_UNSUPPORTED = 6,    /* the call needs state that is not set (e.g. no subset)     */
-    HAWKES_E_STALE = 7           /* the plan's intensities are not those the call refers to
+    HAWKES_E_STALE = 7,          /* the plan's intensities are not those the call refers to
                                     (see hawkes_grad_theta_from_last); nothing was enqueued   */
+    HAWKES_E_CAPACITY = 8        /* a size exceeds the fixed capacity of an allocation-free
+                                    entry point; nothing was enqueued                         */
 } hawkes_status;
 
 /* Hyperparameters, in the order (mu0, tau_x, tau_t, theta0, omega, h) used for
@@ -292,6 +294,24 @@ hawkes_status hawkes_mlp_train_step(float *d_params, float *d_adam_m, float *d_a
                                     int64_t B, float *d_work, double *d_grad, double *d_loss, int *d_err,
                                     hipStream_t stream);
 
+/* Allocation-free variant of hawkes_mlp_train_step, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid allocation).  Same arguments and
+ * results except that the workspace and the FP64 gradient are not passed: they
+ * live in a fixed device array of the library, about 4.3 MB per GPU, taken once
+ * per device on the first call there and held until the process ends.  The
+ * call allocates nothing and calls no allocating routine.
+ *   B  at most hawkes_mlp_noalloc_max_batch() (4096); a larger batch returns
+ *      HAWKES_E_CAPACITY with nothing enqueued.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (different streams or host threads without ordering) race and give
+ * undefined results; calls ordered on one stream are safe.  No part of the
+ * array needs clearing between calls (each kernel writes what it reads). */
+int64_t hawkes_mlp_noalloc_max_batch(void);
+hawkes_status hawkes_mlp_train_step_noalloc(float *d_params, float *d_adam_m, float *d_adam_v, int step, float lr,
+                                            const float *d_x, int64_t n_rows, const int *d_rows,
+                                            const float *d_target, int64_t B, double *d_loss, int *d_err,
+                                            hipStream_t stream);
 /* Per-event network inputs for the subset (slot order), d_feat [m][12] FP32.
  * With cell(e; s) = floor((x_e - gx0)/s), floor((y_e - gy0)/s) and time bin
  * floor((t_e - T0) omega):

@@ -29,8 +29,9 @@ STATUS = {
     5: "HAWKES_E_NOMEM",
     6: "HAWKES_E_UNSUPPORTED",
     7: "HAWKES_E_STALE",
+    8: "HAWKES_E_CAPACITY",
 }
-OK, E_INVALID, E_ZERO_INTENSITY, E_NONFINITE, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_STALE = range(8)
+OK, E_INVALID, E_ZERO_INTENSITY, E_NONFINITE, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_STALE, E_CAPACITY = range(9)
 
 
 class HawkesError(RuntimeError):
@@ -88,6 +89,9 @@ SIGNATURES = {
     "hawkes_mlp_grad": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "hawkes_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _i64, _vp, _vp,
                                              _i64, _vp, _vp, _vp, _vp, _vp]),
+    "hawkes_mlp_noalloc_max_batch": (_i64, []),
+    "hawkes_mlp_train_step_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _i64, _vp,
+                                                     _vp, _i64, _vp, _vp, _vp]),
     "hawkes_features": (ctypes.c_int, [_vp, _HyP, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "hawkes_mass_update": (ctypes.c_int, [_vp, _HyP, _vp, _vp, ctypes.c_double, ctypes.c_int, _i64, _vp, _vp]),
     "hawkes_subset_z": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _vp]),

@@ -58,6 +58,10 @@
 
 enum { HK_MODE_LOGLIK = 0, HK_MODE_GRAD = 1, HK_MODE_HESS = 2 };
 
+// Largest batch of the allocation-free network training step (its workspace
+// is a fixed device array of about 4.3 MB per GPU).
+#define HK_NOALLOC_MLP_MAX_B 4096
+
 struct hk_item {  // one piece of a pair-pass block: a chunk range of one tile
     int tile;     // row tile (row pass) or column tile (column pass)
     int c_begin;  // first chunk of the swept index

@@ -2,16 +2,21 @@
 // tanh network (forward, back-propagation, Adam) and the running-average mass
 // update that consumes either its prediction or the exact Hessian diagonal.
 //
-// The network predicts, from cheap features of free event m, the log of the
-// exact diagonal mass estimate max(theta_m^2 H_m - theta_m g_m, 0) + 1/sigma_z^2
-// built from Eq. 4 and Eq. 5 (the z-space curvature of the log posterior).  The
-// exact column pass remains the training target, the periodic fallback and the
-// judge, so the sampler stays exact: any positive mass leaves the target
-// distribution invariant.
+// The network predicts, from cheap features of free event m, log H_m: the log
+// of Eq. 5's Hessian diagonal, which the paper uses as the HMC mass.  The mass
+// formed from it is theta_m^2 exp(prediction) + P_mm (the prior's precision
+// added when the mass is formed).  The exact column pass remains the training
+// target, the periodic fallback and the judge, so the sampler stays exact: any
+// positive mass leaves the target distribution invariant.
+//
+// hawkes_mlp_train_step_noalloc is the training step for callers that cannot
+// allocate: its workspace and gradient live in a fixed device array of this
+// file (one copy per GPU, held until the process ends).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "hawkes_internal.h"
 
@@ -339,6 +344,59 @@ extern "C" hawkes_status hawkes_mlp_grad(const float *d_params, const float *d_x
     if (!d_params || !d_x || !d_target || !d_work || !d_grad || B < 1 || n_rows < 1) return HAWKES_E_INVALID;
     if (!d_rows && B > n_rows) return HAWKES_E_INVALID;
     mlp_grad_launch(d_params, d_x, n_rows, d_rows, d_target, B, d_work, d_grad, d_loss, d_err, stream);
+    HK_CHECK(hipGetLastError());
+    return HAWKES_OK;
+}
+
+// ---- allocation-free training step ---------------------------------------------------------
+// The FP32 workspace of mlp_grad_launch for a batch of at most
+// HK_NOALLOC_MLP_MAX_B samples (h1, h2, d1, d2, y, dy, the loss partials),
+// then, 256-byte aligned, the FP64 gradient.  Every kernel of the step writes
+// the parts it reads before reading them, so nothing needs clearing between
+// calls.
+constexpr int64_t kNoallocWorkFloats =
+    ((4 * (int64_t)HK_NOALLOC_MLP_MAX_B * MLP_H + 2 * (int64_t)HK_NOALLOC_MLP_MAX_B + 2 +
+      2 * (int64_t)((HK_NOALLOC_MLP_MAX_B + 255) / 256) + 63) / 64) * 64;
+constexpr int64_t kNoallocFloats = kNoallocWorkFloats + 2 * (int64_t)MLP_NP;
+static __device__ __align__(256) float scratch[kNoallocFloats];
+
+// Device address of `scratch` on the current device, looked up once per device
+// (each GPU holds its own copy of the array at its own address).  In host code
+// the array's name is only a host-side stand-in, never a device address.
+static constexpr int kNoallocMaxDevices = 64;
+
+static hawkes_status noalloc_scratch(float **out) {
+    static std::mutex mu;
+    static float *ptr[kNoallocMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoallocMaxDevices) return HAWKES_E_DEVICE;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HAWKES_E_DEVICE;
+        ptr[dev] = (float *)p;
+    }
+    *out = ptr[dev];
+    return HAWKES_OK;
+}
+
+extern "C" int64_t hawkes_mlp_noalloc_max_batch(void) { return HK_NOALLOC_MLP_MAX_B; }
+
+extern "C" hawkes_status hawkes_mlp_train_step_noalloc(float *d_params, float *d_adam_m, float *d_adam_v, int step,
+                                                       float lr, const float *d_x, int64_t n_rows,
+                                                       const int *d_rows, const float *d_target, int64_t B,
+                                                       double *d_loss, int *d_err, hipStream_t stream) {
+    if (!d_params || !d_adam_m || !d_adam_v || step < 1 || !d_x || !d_target || B < 1 || n_rows < 1)
+        return HAWKES_E_INVALID;
+    if (!d_rows && B > n_rows) return HAWKES_E_INVALID;
+    if (B > HK_NOALLOC_MLP_MAX_B) return HAWKES_E_CAPACITY;
+    float *work = nullptr;
+    const hawkes_status st = noalloc_scratch(&work);
+    if (st != HAWKES_OK) return st;
+    double *grad = (double *)(work + kNoallocWorkFloats);
+    mlp_grad_launch(d_params, d_x, n_rows, d_rows, d_target, B, work, grad, d_loss, d_err, stream);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(MLP_NP, 256)), dim3(256), 0, stream, d_params, (const double *)grad,
+                       d_adam_m, d_adam_v, step, lr, 0.9f, 0.999f, 1e-8f);
     HK_CHECK(hipGetLastError());
     return HAWKES_OK;
 }
