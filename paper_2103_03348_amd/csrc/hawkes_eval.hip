@@ -100,17 +100,17 @@ __device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float v) {
 // caller's order when FROM_CALLER, else already in theta_s), and for the split
 // excitation time factor the staged rate of each event,
 // theta_v_j = theta_j exp(omega (t_j - T_c)) with T_c its chunk's first time,
-// plus a flag per chunk that spans more than HK_FACT_SPAN / omega (those chunks
-// use the direct exponent and stage theta_j itself), and the chunk's step factor
+// plus a flag per chunk that spans more than `span_max` in time (those chunks
+// take the row pass's precise form and stage theta_j itself), and the chunk's step factor
 // tstep_c = exp(-omega (T_{c+1} - T_c)) (0 for the last chunk), with which the
 // pair passes carry a row's or column's own split factor from one chunk to the
 // next instead of evaluating it anew.  One wavefront per chunk.
 template <bool FROM_CALLER>
 __global__ __launch_bounds__(256) void k_tfac(const double *__restrict__ theta, const int *__restrict__ perm,
                                               const double *__restrict__ ts, int64_t n, double omega,
-                                              float *__restrict__ theta_s, float *__restrict__ theta_v,
-                                              int *__restrict__ chunk_wide, double *__restrict__ tstep,
-                                              int *__restrict__ status) {
+                                              double span_max, float *__restrict__ theta_s,
+                                              float *__restrict__ theta_v, int *__restrict__ chunk_precise,
+                                              double *__restrict__ tstep, int *__restrict__ status) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // grid covers npad exactly
     const int lane = threadIdx.x & (HK_WAVE - 1);
     double th = 0.0;
@@ -124,41 +124,99 @@ __global__ __launch_bounds__(256) void k_tfac(const double *__restrict__ theta, 
         th = (double)theta_s[i];
     }
     const double dti = ts[i] - ts[i - lane];
-    const bool wide = __any(i < n && omega * dti > HK_FACT_SPAN);
-    theta_v[i] = (!wide && th > 0.0) ? (float)(th * exp(omega * dti)) : (float)th;
+    const bool precise = __any(i < n && dti > span_max);
+    theta_v[i] = (!precise && th > 0.0) ? (float)(th * exp(omega * dti)) : (float)th;
     if (lane == 0) {
-        chunk_wide[i / HK_WAVE] = wide;
+        chunk_precise[i / HK_WAVE] = precise;
         const int64_t nxt = i + HK_WAVE;
         tstep[i / HK_WAVE] = nxt < (int64_t)gridDim.x * blockDim.x ? exp(-omega * (ts[nxt] - ts[i])) : 0.0;
     }
 }
 
 // ------------------------------------------------------------------------------------
-// Time factorisation of the excitation.  exp(-omega (t_i - t_j)) splits into
-// exp(-omega (t_i - T_c)) exp(omega (t_j - T_c)) for a chunk reference time T_c;
-// both factors are formed in FP64 once per event and chunk, so that only the
-// spatial part exp(-r^2 / 2h^2) goes through the FP32 exp2 of the pair loop
-// (and the pair loop saves the time term of the exponent).  The split is used
-// when omega times the chunk's time span is at most HK_FACT_SPAN, which keeps
-// both factors far inside the FP32 range; a chunk that spans more time (sparse
-// data) takes the direct exponent instead, with the rounding of the FP32 rate
-// constant corrected to first order inside the loop.
+// 2^e for an FP64 exponent: exact integer part, FP32 fraction.  The term's
+// relative error is then a few FP32 roundings whatever |e| (rounding the whole
+// exponent to FP32 would give an error that grows with |e|).  e must be at
+// least HK_EXP_FLOOR (the integer part stays inside int32).
+__device__ __forceinline__ float exp2_split(double e) {
+    const double n = rint(e);
+    return __builtin_amdgcn_ldexpf(fexp2((float)(e - n)), (int)n);
+}
 
-// One sweep of a 64-column chunk by one wavefront: 64 steps, each lane pairing
-// its row with column (lane + s) mod 64 of the chunk.
+// ------------------------------------------------------------------------------------
+// The row pass sweeps a 64-column chunk in one of two forms, chosen per chunk.
 //
-// The three sums lambda_i is built from (background row sum B0, background
-// column sum, excitation X0) accumulate every term in FP64: a plain FP32 sum of
-// positive terms rounds away every term below half an ulp of the running sum,
-// which biases lambda low (by ~2e-8 relative on clustered data).  The moments
-// used only by derivatives stay in FP32 blocks.
+// Fast form (a chunk whose events span at most min(HK_FACT_SPAN / omega,
+// HK_COMPACT_TAU tau_t) in time; every chunk of the dense workloads).  The
+// excitation's time factor is split at the chunk's first time T_c:
+// exp(-omega (t_i - t_j)) = exp(-omega (t_i - T_c)) exp(omega (t_j - T_c)),
+// both factors formed in FP64 once per event and chunk, so only the spatial
+// part exp(-r^2 / 2h^2) goes through the FP32 exp2 of the pair loop.  Times
+// enter relative to T_c, rounded to FP32: the rounding of the column's offset
+// is at most 2^-25 of the chunk's span, and the row's relative to dt plus that
+// span, so on a compact chunk dt is nearly as accurate as the FP64 difference.
+//
+// Precise form (every other chunk: sparse data).  dt is the FP64 difference of
+// the times, both exponents are formed whole in FP64 and exponentiated by
+// exp2_split, so a term's error does not grow with the size of its exponent or
+// with the time span of the chunk.  It costs about a third more per pair and is
+// taken only where the data is too sparse in time for the fast form.
+//
+// In both forms one sweep is 64 steps, each lane pairing its row with column
+// (lane + s) mod 64 of the chunk.  The three sums lambda_i is built from
+// (background row sum B0, background column sum, excitation X0) accumulate
+// every term in FP64: a plain FP32 sum of positive terms rounds away every term
+// below half an ulp of the running sum, which biases lambda low (by ~2e-8
+// relative on clustered data).  The moments used only by derivatives stay in
+// FP32 blocks.
 //
 // The spatial exponent of the background is formed in FP64 from coordinates
-// pre-scaled by sqrt(-kbx) (two subtractions, a product and an FMA, rounded
-// once), which costs fewer instructions than integer differences converted to
-// FP32 and scaled, and carries no rounded FP32 scale; the excitation's exponent
-// is that value times the FP32 ratio kex / kbx.
-template <int MODE, bool MASK_BG, bool MASK_EX, bool FACT>
+// pre-scaled by sqrt(-kbx) (two subtractions, a product and an FMA); the fast
+// form rounds it once to FP32, which costs fewer instructions than integer
+// differences converted to FP32 and scaled and carries no rounded FP32 scale.
+// The excitation's spatial exponent is that value times the ratio kex / kbx.
+//
+// Constants: in the log-likelihood-only mode the FP32 constants are completed
+// by their low parts inside the loop (the fast form) or taken exact in FP64
+// (the precise form); the other modes use the FP32-rounded values in both forms
+// and correct their rounding to first order through the first moments.
+
+// One pair's terms into the accumulators (b: background term, te: theta_j E_ij,
+// ar, ae: spatial exponents of the two kernels in log2 units, dt = t_i - t_j).
+template <int MODE>
+__device__ __forceinline__ void row_accumulate(float b, float te, float ar, float ae, float dt, float dt2,
+                                               float (&blk)[HK_NROW], float (&C)[HK_NCOL], double &B0d,
+                                               double &X0c, double &C0d) {
+#pragma clang fp contract(off)
+    B0d += (double)b;
+    C0d = rot_next_d(C0d) + (double)b;
+    if (MODE >= HK_MODE_GRAD) {
+        const float p1 = b * ar, p2 = b * dt2;
+        blk[1] += p1;
+        blk[2] += p2;
+        C[1] = rot_next(C[1]) + p1;
+        C[2] = rot_next(C[2]) + p2;
+        if (MODE >= HK_MODE_HESS) {
+            const float p11 = p1 * ar, p22 = p2 * dt2;
+            blk[3] += p11;
+            blk[4] += p22;
+            C[3] = rot_next(C[3]) + p11;
+            C[4] = rot_next(C[4]) + p22;
+        }
+    }
+    X0c += (double)te;
+    if (MODE >= HK_MODE_GRAD) {
+        blk[6] = fmaf(te, dt, blk[6]);
+        const float q = te * ae;
+        blk[7] += q;
+        if (MODE >= HK_MODE_HESS) {
+            blk[8] = fmaf(te, dt2, blk[8]);
+            blk[9] = fmaf(q, ae, blk[9]);
+        }
+    }
+}
+
+template <int MODE, bool MASK_BG, bool MASK_EX, bool FAST>
 __device__ __forceinline__ void row_sweep(const float2 *__restrict__ rec, const double2 *__restrict__ rxy,
                                           const double *__restrict__ rtd,
                                           double tsi, int lane, float ti, double xr, double yr,
@@ -168,63 +226,46 @@ __device__ __forceinline__ void row_sweep(const float2 *__restrict__ rec, const 
     // explicit FMAs only: a contracted (rotated + product) cannot take the DPP
     // operand, while a plain add of the shared product can
 #pragma clang fp contract(off)
+    const double kbt_d = MODE == HK_MODE_LOGLIK ? kc.kbt_x : (double)kc.kbt;
+    const double rex_d = MODE == HK_MODE_LOGLIK ? kc.rex_x : (double)kc.rex;
 #pragma unroll 16
     for (int s = 0; s < HK_WAVE; ++s) {
         const float2 r = rec[lane + s];
         const double2 pj = rxy[lane + s];
-        // a chunk that spans a long time takes dt from the FP64 times: relative to
-        // the chunk start, both operands could then be large
-        const float dt = FACT ? ti - r.x : (float)(tsi - rtd[lane + s]);
         const double dx = xr - pj.x, dy = yr - pj.y;
-        const float ar = (float)(-fma(dx, dx, dy * dy));
-        const float dt2 = dt * dt;
-        // LOGLIK: the rounded FP32 constants are completed by their low parts
-        // here; the other modes correct them through the first moments
-        float b = fexp2(MODE == HK_MODE_LOGLIK ? fmaf(dt2, kc.kbt, fmaf(dt2, kc.kbt_lo, ar)) : fmaf(dt2, kc.kbt, ar));
-        const float ae = MODE == HK_MODE_LOGLIK ? fmaf(ar, kc.rex, ar * kc.rex_lo) : ar * kc.rex;
-        float E;
-        if (FACT) {
+        float b, E, ar, ae, dt, dt2;
+        if (FAST) {
+            dt = ti - r.x;
+            ar = (float)(-fma(dx, dx, dy * dy));
+            dt2 = dt * dt;
+            b = fexp2(MODE == HK_MODE_LOGLIK ? fmaf(dt2, kc.kbt, fmaf(dt2, kc.kbt_lo, ar)) : fmaf(dt2, kc.kbt, ar));
+            ae = MODE == HK_MODE_LOGLIK ? fmaf(ar, kc.rex, ar * kc.rex_lo) : ar * kc.rex;
             E = fexp2(ae);
         } else {
-            E = fexp2(fmaf(dt, kc.kw, ae));
-            E *= fmaf(dt, kc.cw, 1.0f);
+            const double dtd = tsi - rtd[lane + s];
+            const double ard = -fma(dx, dx, dy * dy);
+            const double aed = ard * rex_d;
+            b = exp2_split(fmax(fma(dtd * kbt_d, dtd, ard), HK_EXP_FLOOR));
+            // a masked sweep also meets later columns (dt < 0, masked below): their
+            // exponent is held at 2^128 so that its integer part stays in range
+            double ee = fmax(fma(dtd, kc.kw_d, aed), HK_EXP_FLOOR);
+            if (MASK_BG || MASK_EX) ee = fmin(ee, 128.0);
+            E = exp2_split(ee);
+            ar = (float)ard;
+            ae = (float)aed;
+            dt = (float)dtd;
+            dt2 = dt * dt;
         }
         if (MASK_BG || MASK_EX) {
             const int j = cbase + ((lane + s) & (HK_WAVE - 1));
             if (MASK_BG && !(j < irow)) b = 0.0f;
             if (!(j < gr)) E = 0.0f;
         }
-        const float te = E * r.y;
-        B0d += (double)b;
-        C0d = rot_next_d(C0d) + (double)b;
-        if (MODE >= HK_MODE_GRAD) {
-            const float p1 = b * ar, p2 = b * dt2;
-            blk[1] += p1;
-            blk[2] += p2;
-            C[1] = rot_next(C[1]) + p1;
-            C[2] = rot_next(C[2]) + p2;
-            if (MODE >= HK_MODE_HESS) {
-                const float p11 = p1 * ar, p22 = p2 * dt2;
-                blk[3] += p11;
-                blk[4] += p22;
-                C[3] = rot_next(C[3]) + p11;
-                C[4] = rot_next(C[4]) + p22;
-            }
-        }
-        X0c += (double)te;
-        if (MODE >= HK_MODE_GRAD) {
-            blk[6] = fmaf(te, dt, blk[6]);
-            const float q = te * ae;
-            blk[7] += q;
-            if (MODE >= HK_MODE_HESS) {
-                blk[8] = fmaf(te, dt2, blk[8]);
-                blk[9] = fmaf(q, ae, blk[9]);
-            }
-        }
+        row_accumulate<MODE>(b, E * r.y, ar, ae, dt, dt2, blk, C, B0d, X0c, C0d);
     }
 }
 
-template <int MODE, bool FACT>
+template <int MODE, bool FAST>
 __device__ __forceinline__ void row_sweep_masked(const float2 *__restrict__ rec, const double2 *__restrict__ rxy,
                                                  const double *__restrict__ rtd,
                                                  double tsi, int lane, float ti, double xr, double yr,
@@ -233,17 +274,17 @@ __device__ __forceinline__ void row_sweep_masked(const float2 *__restrict__ rec,
                                                  float (&C)[HK_NCOL], double &B0d, double &X0c, double &C0d) {
     const int cbase = c * HK_WAVE;
     if (c == wave_chunk)
-        row_sweep<MODE, true, true, FACT>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+        row_sweep<MODE, true, true, FAST>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
     else if (cbase + HK_WAVE - 1 >= wave_gmin)
-        row_sweep<MODE, false, true, FACT>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+        row_sweep<MODE, false, true, FAST>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
     else
-        row_sweep<MODE, false, false, FACT>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+        row_sweep<MODE, false, false, FAST>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
 }
 
 template <int MODE>
 __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, const int *__restrict__ xi,
                                                   const int *__restrict__ yi, const float *__restrict__ theta_v,
-                                                  const int *__restrict__ chunk_wide, const double *__restrict__ tstep,
+                                                  const int *__restrict__ chunk_precise, const double *__restrict__ tstep,
                                                   const int *__restrict__ g, const hk_item *__restrict__ items,
                                                   const int *__restrict__ block0,
                                                   const int64_t *__restrict__ colpart_off,
@@ -296,9 +337,7 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
             // accumulators in place across chunks.
             const double Tlast = ts[(int64_t)c * HK_WAVE + HK_WAVE - 1];
             const bool block_live = !(tile_tmin - Tlast > kc.dt_cut);
-            // times relative to the chunk's first event: for the pairs that carry
-            // the sums (close in time) both operands of dt are then small and
-            // exact to FP32
+            // fast form: times relative to the chunk's first event, rounded to FP32
             const double Tc = ts[(int64_t)c * HK_WAVE];
             const float ti = (float)(tsi - Tc);
             if (block_live && tid < HK_WAVE) {
@@ -306,7 +345,7 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
                 const double tj = ts[j];
                 float2 r;
                 r.x = (float)(tj - Tc);
-                r.y = theta_v[j];  // theta_j, times exp(omega (t_j - T_c)) when the chunk is split
+                r.y = theta_v[j];  // theta_j, times exp(omega (t_j - T_c)) on a fast chunk
                 rec[tid] = r;
                 rec[tid + HK_WAVE] = r;
                 const double2 pj = make_double2((double)xi[j] * kc.sbx, (double)yi[j] * kc.sbx);
@@ -315,7 +354,7 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
                 rtd[tid] = rtd[tid + HK_WAVE] = tj;
             }
             __syncthreads();
-            const bool fact = chunk_wide[c] == 0;
+            const bool fact = chunk_precise[c] == 0;
             float blk[HK_NROW], C[HK_NCOL];
             double C0d = 0.0, X0c = 0.0;
 #pragma unroll
@@ -439,8 +478,8 @@ constexpr int HK_TOT_LANES = 32;
 __device__ void fin_totals(const double *__restrict__ blockpart, int nblocks, double *__restrict__ loglik,
                            double *__restrict__ grad_hyper, double *__restrict__ negH_hyper,
                            int *__restrict__ status, double *tot) {
-    const int k = threadIdx.x / HK_TOT_LANES, l = threadIdx.x % HK_TOT_LANES;
-    if (k < HK_NSUM) {
+    const int l = threadIdx.x % HK_TOT_LANES, groups = (int)blockDim.x / HK_TOT_LANES;
+    for (int k = threadIdx.x / HK_TOT_LANES; k < HK_NSUM; k += groups) {
         const double *part = blockpart + (int64_t)k * nblocks;
         double sum = 0.0, c = 0.0, plain = 0.0;
 #pragma unroll 4
@@ -689,11 +728,6 @@ __device__ __forceinline__ double col_exponent(const ColRow &r, double xj, doubl
     return fma(-dx, dx, fma(-dy, dy, r.c + dj));
 }
 
-// 2^e for an FP64 exponent: exact integer part, FP32 fraction
-__device__ __forceinline__ float exp2_split(double e) {
-    const double n = rint(e);
-    return __builtin_amdgcn_ldexpf(fexp2((float)(e - n)), (int)n);
-}
 
 template <bool MASKED, bool DOT>
 __device__ __forceinline__ float col_term(const ColRow *__restrict__ rows, const int *__restrict__ rg, int s,
@@ -807,12 +841,25 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
 // Column finalisation, one block per 64-event chunk: the HK_FIN_WAVES
 // wavefronts split the column pieces round robin (reads in flight), then the
 // first combines them in a fixed order.
+//
+// With `totals` set, one block more (the last) reduces the row finalisation's
+// block partials to the scalar results instead (the work of k_fin2, whose
+// inputs are complete once the column pass runs): one launch fewer per
+// evaluation.
 __global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_colfin(const int *__restrict__ perm, int64_t n,
                                                 const int *__restrict__ col_item0, const int *__restrict__ col_nseg,
                                                 const double *__restrict__ colG, const double *__restrict__ a,
                                                 const FinConst fc, double *__restrict__ grad_theta,
-                                                double *__restrict__ negH_theta) {
+                                                double *__restrict__ negH_theta, int totals,
+                                                const double *__restrict__ blockpart, int nfin,
+                                                double *__restrict__ loglik, double *__restrict__ grad_hyper,
+                                                double *__restrict__ negH_hyper, int *__restrict__ status) {
     __shared__ double part[HK_FIN_WAVES][2][HK_WAVE];
+    if (totals && blockIdx.x == gridDim.x - 1) {
+        __shared__ double tot[HK_NSUM];
+        fin_totals(blockpart, nfin, loglik, grad_hyper, negH_hyper, status, tot);
+        return;
+    }
     const int lane = threadIdx.x & (HK_WAVE - 1), wv = threadIdx.x / HK_WAVE;
     const int64_t j = (int64_t)blockIdx.x * HK_WAVE + lane;
     const int J = (int)(j / HK_TILE), r = (int)(j % HK_TILE);
@@ -886,6 +933,9 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
         kc->dot = 2.0 * umax * umax <= HK_DOT_MAX2;
     }
     kc->rex = (float)(kex / kbx);
+    kc->kbt_x = kbt;
+    kc->rex_x = kex / kbx;
+    kc->span_max = fmin(HK_FACT_SPAN / hy->omega, HK_COMPACT_TAU * hy->tau_t);
     kc->kbt_lo = (float)(kbt - (double)kc->kbt);
     kc->rex_lo = (float)(kex / kbx - (double)kc->rex);
     fc->dkbt = (double)kc->kbt - kbt;
@@ -909,8 +959,11 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
 }
 
 // Column pass and its finalisation on the plan's current w, a (Eq. 4, Eq. 5).
+// With `totals`, the same launch as the column finalisation also reduces the
+// row finalisation's block partials to d_loglik, d_grad_hyper, d_negH_hyper.
 static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, double *d_grad_theta,
-                       double *d_negH_theta, hipStream_t stream) {
+                       double *d_negH_theta, hipStream_t stream, bool totals = false, double *d_loglik = nullptr,
+                       double *d_grad_hyper = nullptr, double *d_negH_hyper = nullptr) {
     hk_prof_mark(p, HK_PROF_COL, true, stream);
 #define HK_COL(H, D)                                                                                        \
     hipLaunchKernelGGL((k_col<H, D>), dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->lw, \
@@ -924,8 +977,9 @@ static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, d
     }
 #undef HK_COL
     hk_prof_mark(p, HK_PROF_COL, false, stream);
-    hipLaunchKernelGGL(k_colfin, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->perm, p->n, p->col_item0, p->col_nseg,
-                       p->colG, p->a, fc, d_grad_theta, d_negH_theta);
+    hipLaunchKernelGGL(k_colfin, dim3(p->nchunks + (totals ? 1 : 0)), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream,
+                       p->perm, p->n, p->col_item0, p->col_nseg, p->colG, p->a, fc, d_grad_theta, d_negH_theta,
+                       totals ? 1 : 0, p->blockpart, p->nchunks, d_loglik, d_grad_hyper, d_negH_hyper, p->status);
 }
 
 extern "C" int64_t hawkes_plan_epoch(hawkes_plan p) { return p ? p->epoch : -1; }
@@ -970,11 +1024,11 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 
     hk_prof_mark(p, HK_PROF_EVAL, true, stream);
     hipLaunchKernelGGL(k_tfac<true>, dim3((unsigned)(npad / 256)), dim3(256), 0, stream, d_theta, p->perm, p->ts,
-                       p->n, kc.omega, p->theta_s, p->theta_v, p->chunk_wide, p->tstep, p->status);
+                       p->n, kc.omega, kc.span_max, p->theta_s, p->theta_v, p->chunk_precise, p->tstep, p->status);
     hk_prof_mark(p, HK_PROF_ROW, true, stream);
 #define HK_ROW(M)                                                                                              \
     hipLaunchKernelGGL(k_row<M>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,          \
-                       p->theta_v, p->chunk_wide, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off,             \
+                       p->theta_v, p->chunk_precise, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off,             \
                        p->rowpart, p->colpart, kc)
 #define HK_FIN(M)                                                                                              \
     hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->ts, d_theta,       \
@@ -989,12 +1043,16 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
     else HK_FIN(HK_MODE_HESS);
 #undef HK_ROW
 #undef HK_FIN
-    hipLaunchKernelGGL(k_fin2, dim3(1), dim3(HK_NSUM * HK_TOT_LANES), 0, stream, p->blockpart, p->nchunks, d_loglik,
-                       d_grad_hyper, d_negH_hyper, p->status);
+    // the scalar results come from the block partials: with a column pass, in
+    // its finalisation's launch; without, in a launch of their own
+    const bool col = d_grad_theta || d_negH_theta;
+    if (!col)
+        hipLaunchKernelGGL(k_fin2, dim3(1), dim3(HK_NSUM * HK_TOT_LANES), 0, stream, p->blockpart, p->nchunks,
+                           d_loglik, d_grad_hyper, d_negH_hyper, p->status);
     p->epoch += 1;
     p->eval_epoch = p->epoch;
     p->eval_hyper = *hyper;
-    if (d_grad_theta || d_negH_theta) launch_col(p, kc, fc, d_grad_theta, d_negH_theta, stream);
+    if (col) launch_col(p, kc, fc, d_grad_theta, d_negH_theta, stream, true, d_loglik, d_grad_hyper, d_negH_hyper);
     hk_prof_mark(p, HK_PROF_EVAL, false, stream);
     HK_CHECK(hipGetLastError());
     return HAWKES_OK;
@@ -1002,9 +1060,9 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 
 void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream) {
     hipLaunchKernelGGL(k_tfac<false>, dim3((unsigned)(p->npad / 256)), dim3(256), 0, stream, (const double *)nullptr,
-                       p->perm, p->ts, p->n, kc.omega, p->theta_s, p->theta_v, p->chunk_wide, p->tstep, p->status);
+                       p->perm, p->ts, p->n, kc.omega, kc.span_max, p->theta_s, p->theta_v, p->chunk_precise, p->tstep, p->status);
     hipLaunchKernelGGL(k_row<HK_MODE_LOGLIK>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
-                       p->theta_v, p->chunk_wide, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart,
+                       p->theta_v, p->chunk_precise, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart,
                        p->colpart, kc);
 }
 

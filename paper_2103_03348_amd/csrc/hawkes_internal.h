@@ -26,6 +26,12 @@
 // FP32 range.
 #define HK_FACT_SPAN 40.0
 
+// The row pass takes its fast form (split time factor, FP32 times relative to
+// the chunk's first event) on a chunk that spans at most HK_COMPACT_TAU tau_t
+// (and HK_FACT_SPAN / omega) in time; on a wider chunk, the precise form (FP64
+// time differences, whole exponents formed in FP64 with an exact power of two).
+#define HK_COMPACT_TAU 0.5
+
 // The column passes form the whole exponent of a term c_e E_ij / lambda_i in
 // FP64 (log2 units): log2(c_e / lambda_i), the time term and the spatial term.
 // Exponents are clamped below at this value (every term with an exponent below
@@ -107,7 +113,7 @@ struct hawkes_plan_s {
     // per-evaluation scratch (device)
     float *theta_s;           // [npad] rates in sorted order (FP32), 0 on padding
     float *theta_v;           // [npad] staged rates of the row pass (split time factor applied)
-    int *chunk_wide;          // [nchunks] 1 where the chunk takes the direct exponent
+    int *chunk_precise;       // [nchunks] 1 where the row pass takes its precise form on the chunk
     double *tstep;            // [nchunks] exp(-omega (T_{c+1} - T_c)) of the last k_tfac
     double *lw;               // [npad] log2(c_e / lambda_i) of the last evaluation (HK_EXP_FLOOR on padding)
     float *rowpart;           // [n_row_items][HK_NROW][HK_TILE] row partial sums of each piece
@@ -162,6 +168,9 @@ struct PairConst {
     float rex_lo;
     double omega;  // excitation decay rate (time factors formed in FP64)
     double kw_d;   // kw in FP64 (exponents formed in FP64)
+    double kbt_x;  // kbt exact in FP64 (the row pass's precise form, log-likelihood-only mode)
+    double rex_x;  // kex / kbx exact in FP64 (the same)
+    double span_max;   // row pass: the fast form's largest chunk time span
     double sx;     // sqrt(-kex): fixed-point coordinate -> coordinate whose squared distance is -a_e
     double sbx;    // sqrt(-kbx): the same for the background exponent a_b
     double dt_cut;     // row pass: time gap past which both terms are below 2^-160 (INFINITY: no cutoff)

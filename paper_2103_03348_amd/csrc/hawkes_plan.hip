@@ -151,7 +151,7 @@ void free_plan(hawkes_plan p) {
     hk_subset_free(p);
     hk_tree_free(p);
     void *ptrs[] = {p->ts, p->xi, p->yi, p->perm, p->g, p->row_items, p->row_block0, p->row_item0, p->row_nseg,
-                    p->colpart_off, p->col_items, p->col_block0, p->col_item0, p->col_nseg, p->theta_s, p->theta_v, p->chunk_wide, p->tstep, p->lw, p->rowpart,
+                    p->colpart_off, p->col_items, p->col_block0, p->col_item0, p->col_nseg, p->theta_s, p->theta_v, p->chunk_precise, p->tstep, p->lw, p->rowpart,
                     p->colpart, p->lam, p->a, p->colG, p->blockpart, p->status};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -360,7 +360,7 @@ extern "C" hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const d
     // ---- per-evaluation scratch ----
     PC(dalloc(&p->theta_s, npad));
     PC(dalloc(&p->theta_v, npad));
-    PC(dalloc(&p->chunk_wide, p->nchunks));
+    PC(dalloc(&p->chunk_precise, p->nchunks));
     PC(dalloc(&p->lw, npad));
     PC(dalloc(&p->tstep, p->nchunks));
     PC(dalloc(&p->rowpart, (size_t)p->n_row_items * HK_NROW * HK_TILE));
