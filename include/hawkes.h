@@ -313,16 +313,17 @@ hawkes_status hawkes_mlp_train_step_noalloc(float *d_params, float *d_adam_m, fl
                                             const float *d_target, int64_t B, double *d_loss, int *d_err,
                                             hipStream_t stream);
 /* Per-event network inputs for the subset (slot order), d_feat [m][12] FP32.
- * With cell(e; s) = floor((x_e - gx0)/s), floor((y_e - gy0)/s) and time bin
- * floor((t_e - T0) omega):
- *   0..2  log1p(#other events in the event's cell), s = h, 3h, tau_x
- *   3..5  s = h: log1p(#events in the cell in the previous bin, the next bin,
- *         the next three bins)
- *   6..8  the same for s = 3h
+ * For free event m, with r2_e = (x_e - x_m)^2 + (y_e - y_m)^2 and dt_e = t_e - t_m:
+ *   0..2  log1p(#{e != m : r2_e < r^2}) for r = h, 3h, tau_x (events in a disc)
+ *   3..5  r = h: log1p of the events in the disc with -1/omega <= dt_e < 0,
+ *         with 0 < dt_e <= 1/omega, and with 0 < dt_e <= 3/omega
+ *   6..8  the same for r = 3h
  *   9     z_k;  10  #{e : t_e < t_k} / N;  11  (T1 - t_k) / (T1 - T0)
- * d_t, d_xy are the arrays the plan was built from; (gx0, gy0) <= the minimum
- * coordinates.  Counting uses grids sized from the plan's bounding box;
- * HAWKES_E_UNSUPPORTED if a grid would exceed 2^26 (space) or 2^28 (space-time) cells. */
+ * Counts are exact: a grid of cells of size 3h (origin (gx0, gy0) <= the
+ * minimum coordinates) only enumerates the candidates, each tested by its
+ * FP64 distance.  d_t, d_xy are the arrays the plan was built from.
+ * HAWKES_E_UNSUPPORTED if the grid would exceed 2^26 cells.  Uses a workspace
+ * of the plan's subset (grown on demand; a growth synchronises `stream`). */
 hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hyper, const double *d_t, const double *d_xy,
                               const double *d_z, double gx0, double gy0, float *d_feat, hipStream_t stream);
 
@@ -335,7 +336,7 @@ hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hyper, const do
  * 1/sigma_z^2 for prior = 0 (z ~ N(0, sigma_z^2 I)), (V^{-1})_kk / sigma_z^2 for
  * prior = 1 (Eq. 2 on the tree of hawkes_plan_set_tree).
  *   d_curv  [m] FP64, slot order: c_k                              -- may be NULL
- *   d_log_h [m] FP32, slot order: log max(H_k, 1e-30), the learned
+ *   d_log_h [m] FP32, slot order: log max(H_k, 1e-6), the learned
  *           preconditioner's training target (Eq. 5 is 0 for an event
  *           with no later event)                                   -- may be NULL
  * HAWKES_E_UNSUPPORTED without a subset, or with prior = 1 and no tree of m tips. */

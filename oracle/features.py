@@ -1,17 +1,20 @@
 """Per-event inputs of the learned preconditioner, by their plain definition
-(brute-force counting).  Test infrastructure only.
+(brute-force counting over all events).  Test infrastructure only.
 
-For a free event m at (x_m, t_m), with cell(e; s) = (floor((x_e - gx0)/s),
-floor((y_e - gy0)/s)) and bin(e) = floor((t_e - T0) * omega):
-  f0..f2  log1p(#other events in m's cell), cell sizes s = h, 3h, tau_x
-  f3..f5  cell size h:  log1p(#events with bin = bin_m - 1),
-                        log1p(#events with bin = bin_m + 1),
-                        log1p(#events with bin_m + 1 <= bin <= bin_m + 3)
-  f6..f8  the same three with cell size 3h
+For a free event m at (x_m, t_m), with r2_e = (x_e - x_m)^2 + (y_e - y_m)^2 and
+dt_e = t_e - t_m:
+  f0..f2  log1p(#{e != m : r2_e < r^2}) for r = h, 3h, tau_x
+  f3..f5  r = h:  log1p(#{e : r2_e < r^2, -1/omega <= dt_e < 0}),
+                  log1p(#{e : r2_e < r^2, 0 < dt_e <= 1/omega}),
+                  log1p(#{e : r2_e < r^2, 0 < dt_e <= 3/omega})
+  f6..f8  the same three with r = 3h
   f9      z_m = log theta_m
   f10     #{e : t_e < t_m} / N     (time rank)
   f11     (T1 - t_m) / (T1 - T0)   (time to the window end)
-The grid origin (gx0, gy0) is part of the input.
+r^2 is r * r and r2_e is formed as dx * dx + dy * dy, each rounded once in
+FP64; 1/omega and 3/omega are 1.0 / omega and 3.0 / omega in FP64.  The grid
+origin (gx0, gy0) is accepted for the library's signature and does not change
+any count.
 """
 from __future__ import annotations
 
@@ -27,25 +30,21 @@ def features(t, x, y, idx, z, hyper, t0, gx0, gy0):
     n = t.shape[0]
     T1 = float(t.max())
     span = T1 - t0
-    bins = np.floor((t - t0) * omega)
+    w1 = 1.0 / omega
+    w3 = 3.0 / omega
     F = np.zeros((idx.shape[0], 12))
-
-    def cell(s):
-        return np.floor((x - gx0) / s), np.floor((y - gy0) / s)
-
-    cells = {s: cell(s) for s in (h, 3.0 * h, tau_x)}
     for r, m in enumerate(idx):
-        for c, s in enumerate((h, 3.0 * h, tau_x)):
-            cx, cy = cells[s]
-            same = (cx == cx[m]) & (cy == cy[m])
-            F[r, c] = np.log1p(same.sum() - 1)
-        for base, s in ((3, h), (6, 3.0 * h)):
-            cx, cy = cells[s]
-            same = (cx == cx[m]) & (cy == cy[m])
-            b = bins[m]
-            F[r, base + 0] = np.log1p(np.sum(same & (bins == b - 1)))
-            F[r, base + 1] = np.log1p(np.sum(same & (bins == b + 1)))
-            F[r, base + 2] = np.log1p(np.sum(same & (bins >= b + 1) & (bins <= b + 3)))
+        dx = x - x[m]
+        dy = y - y[m]
+        r2 = dx * dx + dy * dy
+        dt = t - t[m]
+        for c, rad in enumerate((h, 3.0 * h, tau_x)):
+            F[r, c] = np.log1p(np.sum(r2 < rad * rad) - 1)
+        for base, rad in ((3, h), (6, 3.0 * h)):
+            near = r2 < rad * rad
+            F[r, base + 0] = np.log1p(np.sum(near & (dt >= -w1) & (dt < 0.0)))
+            F[r, base + 1] = np.log1p(np.sum(near & (dt > 0.0) & (dt <= w1)))
+            F[r, base + 2] = np.log1p(np.sum(near & (dt > 0.0) & (dt <= w3)))
         F[r, 9] = z[r]
         F[r, 10] = np.sum(t < t[m]) / n
         F[r, 11] = (T1 - t[m]) / span if span > 0 else 0.0

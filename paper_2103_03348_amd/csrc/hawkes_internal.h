@@ -47,9 +47,12 @@
 #define HK_DOT_MAX2 524288.0
 
 // Floor of Eq. 5's entries under the log in the learned preconditioner's
-// training target log max(H_k, HK_LOGH_FLOOR) (an entry without later events
-// is exactly 0).
-#define HK_LOGH_FLOOR 1.0e-30
+// training target log max(H_k, HK_LOGH_FLOOR).  An entry without later events
+// is exactly 0, and an entry below the floor changes its event's mass
+// theta^2 H + P by at most 1e-6 theta^2: the floor spends none of the network's
+// capacity on the long tail of such entries (log H reaches -70 on the
+// clustered workloads) that the mass does not feel.
+#define HK_LOGH_FLOOR 1.0e-6
 
 // Time offset given to padding events: their pair terms underflow to exactly
 // zero while every square stays finite in FP32.

@@ -190,20 +190,26 @@ __global__ void k_adam(float *__restrict__ params, const double *__restrict__ gr
 }
 
 // ---- features -------------------------------------------------------------------------------
-struct GridSpec {
-    double gx0, gy0, t0, omega;
-    double s[3];     // cell sizes h, 3h, tau_x
-    int nx[3], ny[3];
-    int nbins;       // time bins of width 1/omega
-    int64_t off_sp[3], off_st[2];  // offsets of the spatial grids and the space-time grids (h, 3h)
-    int64_t total;
+// Disc and time-window counts around each free event, exact by their
+// definition: a spatial grid of cells of size 3h over all events (counting
+// sort: per-cell counts, one exclusive scan, a scatter of the events' times
+// and coordinates into cell order) gives each free event the candidates in the
+// cells that a disc of radius tau_x (the largest radius) around it touches;
+// the candidates are then tested exactly.  Distances are dx * dx + dy * dy and
+// radii r * r, each rounded once in FP64 (no contraction), so every count is
+// the same integer as the definition's.
+struct FeatGrid {
+    double gx0, gy0, s;  // origin and cell size 3h
+    int nx, ny;
 };
 
-__device__ __forceinline__ void cell_of(double x, double y, const GridSpec &G, int c, int &cx, int &cy) {
-    cx = (int)floor((x - G.gx0) / G.s[c]);
-    cy = (int)floor((y - G.gy0) / G.s[c]);
-    cx = min(max(cx, 0), G.nx[c] - 1);
-    cy = min(max(cy, 0), G.ny[c] - 1);
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+__device__ __forceinline__ int cell_x(double x, const FeatGrid &G) {
+    return clampi((int)floor((x - G.gx0) / G.s), 0, G.nx - 1);
+}
+__device__ __forceinline__ int cell_y(double y, const FeatGrid &G) {
+    return clampi((int)floor((y - G.gy0) / G.s), 0, G.ny - 1);
 }
 
 __global__ void k_fill_zero(int *__restrict__ a, int64_t n) {
@@ -211,51 +217,121 @@ __global__ void k_fill_zero(int *__restrict__ a, int64_t n) {
         a[i] = 0;
 }
 
-__global__ void k_grid_count(const double *__restrict__ t, const double *__restrict__ xy, int64_t n,
-                             const GridSpec G, int *__restrict__ grid) {
+__global__ void k_cell_count(const double *__restrict__ xy, int64_t n, const FeatGrid G, int *__restrict__ cnt) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= n) return;
-    const double x = xy[2 * e], y = xy[2 * e + 1];
-    const int b = min(max((int)floor((t[e] - G.t0) * G.omega), 0), G.nbins - 1);
-    for (int c = 0; c < 3; ++c) {
-        int cx, cy;
-        cell_of(x, y, G, c, cx, cy);
-        atomicAdd(&grid[G.off_sp[c] + (int64_t)cy * G.nx[c] + cx], 1);
-        if (c < 2) atomicAdd(&grid[G.off_st[c] + ((int64_t)cy * G.nx[c] + cx) * G.nbins + b], 1);
+    atomicAdd(&cnt[(int64_t)cell_y(xy[2 * e + 1], G) * G.nx + cell_x(xy[2 * e], G)], 1);
+}
+
+// Exclusive scan of the cell counts by one block: each thread scans a
+// contiguous segment, the segment totals are scanned in LDS, then each thread
+// writes its segment's offsets.  start[cells] = n.  fill is cleared for the
+// scatter.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_cell_scan(const int *__restrict__ cnt, int64_t cells,
+                                                           int *__restrict__ start, int *__restrict__ fill) {
+    __shared__ int tot[kScanThreads];
+    const int64_t seg = (cells + kScanThreads - 1) / kScanThreads;
+    const int64_t lo = min(cells, threadIdx.x * seg), hi = min(cells, lo + seg);
+    int sum = 0;
+    for (int64_t c = lo; c < hi; ++c) sum += cnt[c];
+    tot[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < kScanThreads; ++k) {
+            const int v = tot[k];
+            tot[k] = run;
+            run += v;
+        }
+        start[cells] = run;
+    }
+    __syncthreads();
+    int run = tot[threadIdx.x];
+    for (int64_t c = lo; c < hi; ++c) {
+        start[c] = run;
+        run += cnt[c];
+        fill[c] = 0;
     }
 }
 
-__global__ void k_features(const double *__restrict__ t, const double *__restrict__ xy,
-                           const int64_t *__restrict__ cidx, const int *__restrict__ pos, const int *__restrict__ slot,
-                           const int *__restrict__ g, const double *__restrict__ z, int64_t m, int64_t n, double t1,
-                           const GridSpec G, const int *__restrict__ grid, float *__restrict__ feat) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= m) return;
+// Events into cell order (the order inside a cell does not matter for counts).
+__global__ void k_cell_scatter(const double *__restrict__ t, const double *__restrict__ xy, int64_t n,
+                               const FeatGrid G, const int *__restrict__ start, int *__restrict__ fill,
+                               double *__restrict__ ct, double *__restrict__ cx, double *__restrict__ cy) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double x = xy[2 * e], y = xy[2 * e + 1];
+    const int64_t c = (int64_t)cell_y(y, G) * G.nx + cell_x(x, G);
+    const int64_t q = start[c] + atomicAdd(&fill[c], 1);
+    ct[q] = t[e];
+    cx[q] = x;
+    cy[q] = y;
+}
+
+// One wavefront per free event: the lanes split the candidates of the cells a
+// disc of radius tau_x touches, count, and the counts are summed across the
+// wavefront (integers: exact in any order).
+__global__ __launch_bounds__(256) void k_features(const double *__restrict__ t, const double *__restrict__ xy,
+                                                  const int64_t *__restrict__ cidx, const int *__restrict__ pos,
+                                                  const int *__restrict__ slot, const int *__restrict__ g,
+                                                  const double *__restrict__ z, int64_t m, int64_t n, double t0,
+                                                  double t1, double h, double tau_x, double omega, const FeatGrid G,
+                                                  const int *__restrict__ start, const double *__restrict__ ct,
+                                                  const double *__restrict__ cx, const double *__restrict__ cy,
+                                                  float *__restrict__ feat) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & (HK_WAVE - 1);
+    const int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / HK_WAVE;
+    if (r >= m) return;  // whole wavefronts leave together
     const int k = slot[r];
     const int64_t e = cidx[k];
-    const double x = xy[2 * e], y = xy[2 * e + 1];
-    const int b = min(max((int)floor((t[e] - G.t0) * G.omega), 0), G.nbins - 1);
-    float f[MLP_IN];
-    for (int c = 0; c < 3; ++c) {
-        int cx, cy;
-        cell_of(x, y, G, c, cx, cy);
-        f[c] = (float)log1p((double)(grid[G.off_sp[c] + (int64_t)cy * G.nx[c] + cx] - 1));
-        if (c < 2) {
-            const int *st = grid + G.off_st[c] + ((int64_t)cy * G.nx[c] + cx) * G.nbins;
-            const int prev = b > 0 ? st[b - 1] : 0;
-            const int next = b + 1 < G.nbins ? st[b + 1] : 0;
-            int next3 = 0;
-            for (int q = b + 1; q <= b + 3 && q < G.nbins; ++q) next3 += st[q];
-            f[3 + 3 * c] = (float)log1p((double)prev);
-            f[4 + 3 * c] = (float)log1p((double)next);
-            f[5 + 3 * c] = (float)log1p((double)next3);
+    const double xm = xy[2 * e], ym = xy[2 * e + 1], tm = t[e];
+    const double r0 = h * h, h3 = 3.0 * h, r1 = h3 * h3, r2c = tau_x * tau_x;
+    const double w1 = 1.0 / omega, w3 = 3.0 / omega;
+    const int x_lo = cell_x(xm - tau_x, G), x_hi = cell_x(xm + tau_x, G);
+    const int y_lo = cell_y(ym - tau_x, G), y_hi = cell_y(ym + tau_x, G);
+    int c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int yy = y_lo; yy <= y_hi; ++yy) {
+        const int64_t row = (int64_t)yy * G.nx;
+        for (int q = start[row + x_lo] + lane; q < start[row + x_hi + 1]; q += HK_WAVE) {
+            const double dx = cx[q] - xm, dy = cy[q] - ym;
+            const double d2 = dx * dx + dy * dy;
+            const double dt = ct[q] - tm;
+            const bool prev = dt >= -w1 && dt < 0.0, next = dt > 0.0 && dt <= w1, next3 = dt > 0.0 && dt <= w3;
+            if (d2 < r2c) {
+                c[2] += 1;
+                if (d2 < r1) {
+                    c[1] += 1;
+                    c[6] += prev;
+                    c[7] += next;
+                    c[8] += next3;
+                    if (d2 < r0) {
+                        c[0] += 1;
+                        c[3] += prev;
+                        c[4] += next;
+                        c[5] += next3;
+                    }
+                }
+            }
         }
     }
-    f[9] = (float)z[k];
-    f[10] = (float)((double)g[pos[r]] / (double)n);
-    const double span = t1 - G.t0;
-    f[11] = (float)(span > 0.0 ? (t1 - t[e]) / span : 0.0);
-    for (int j = 0; j < MLP_IN; ++j) feat[(int64_t)k * MLP_IN + j] = f[j];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+#pragma unroll
+        for (int off = 1; off < HK_WAVE; off <<= 1) c[a] += __shfl_xor(c[a], off);
+    }
+    if (lane == 0) {
+        float f[MLP_IN];
+        // the event itself is inside every disc
+        for (int a = 0; a < 3; ++a) f[a] = (float)log1p((double)(c[a] - 1));
+        for (int a = 3; a < 9; ++a) f[a] = (float)log1p((double)c[a]);
+        f[9] = (float)z[k];
+        f[10] = (float)((double)g[pos[r]] / (double)n);
+        const double span = t1 - t0;
+        f[11] = (float)(span > 0.0 ? (t1 - tm) / span : 0.0);
+        for (int j = 0; j < MLP_IN; ++j) feat[(int64_t)k * MLP_IN + j] = f[j];
+    }
 }
 
 // ---- curvature and mass update ---------------------------------------------------------
@@ -422,45 +498,34 @@ extern "C" hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hy, 
     if (!p || !hk_hyper_ok(hy) || !d_t || !d_xy || !d_z || !d_feat) return HAWKES_E_INVALID;
     if (!p->sub) return HAWKES_E_UNSUPPORTED;
     if (!(gx0 <= p->xmin) || !(gy0 <= p->ymin)) return HAWKES_E_INVALID;
-    GridSpec G;
+    FeatGrid G;
     G.gx0 = gx0;
     G.gy0 = gy0;
-    G.t0 = p->t0;
-    G.omega = hy->omega;
-    G.s[0] = hy->h;
-    G.s[1] = 3.0 * hy->h;
-    G.s[2] = hy->tau_x;
-    int64_t off = 0;
-    const double nbd = floor((p->t1 - p->t0) * hy->omega) + 1.0;
-    if (!(nbd < 1e7)) return HAWKES_E_UNSUPPORTED;
-    G.nbins = (int)nbd;
-    for (int c = 0; c < 3; ++c) {
-        const double nx = floor((p->xmax - gx0) / G.s[c]) + 1.0, ny = floor((p->ymax - gy0) / G.s[c]) + 1.0;
-        if (!(nx * ny < (double)(1 << 26))) return HAWKES_E_UNSUPPORTED;
-        G.nx[c] = (int)nx;
-        G.ny[c] = (int)ny;
-        G.off_sp[c] = off;
-        off += (int64_t)G.nx[c] * G.ny[c];
-    }
-    for (int c = 0; c < 2; ++c) {
-        const double cells = (double)G.nx[c] * G.ny[c] * G.nbins;
-        if (!(cells < (double)(1 << 28))) return HAWKES_E_UNSUPPORTED;
-        G.off_st[c] = off;
-        off += (int64_t)G.nx[c] * G.ny[c] * G.nbins;
-    }
-    G.total = off;
-    hawkes_status st = hk_subset_grid(p, G.total, stream);
+    G.s = 3.0 * hy->h;
+    const double nx = floor((p->xmax - gx0) / G.s) + 1.0, ny = floor((p->ymax - gy0) / G.s) + 1.0;
+    if (!(nx * ny < (double)(1 << 26))) return HAWKES_E_UNSUPPORTED;
+    G.nx = (int)nx;
+    G.ny = (int)ny;
+    const int64_t cells = (int64_t)G.nx * G.ny, n = p->n;
+    // int workspace: counts [cells], starts [cells + 1], fill [cells]; then
+    // (8-byte aligned) the events' times and coordinates in cell order [3 n]
+    const int64_t ints = ((3 * cells + 1 + 1) / 2) * 2;
+    hawkes_status st = hk_subset_grid(p, ints + 6 * n, stream);
     if (st != HAWKES_OK) return st;
-    int *grid = hk_subset_grid_ptr(p);
-    hipLaunchKernelGGL(k_fill_zero, dim3(std::min<int64_t>(nblk(G.total, 256), 4096)), dim3(256), 0, stream, grid,
-                       G.total);
-    hipLaunchKernelGGL(k_grid_count, dim3(nblk(p->n, 256)), dim3(256), 0, stream, d_t, d_xy, p->n, G, grid);
+    int *cnt = hk_subset_grid_ptr(p), *start = cnt + cells, *fill = start + cells + 1;
+    double *ct = (double *)(cnt + ints), *cxs = ct + n, *cys = cxs + n;
+    hipLaunchKernelGGL(k_fill_zero, dim3(std::min<int64_t>(nblk(cells, 256), 4096)), dim3(256), 0, stream, cnt,
+                       cells);
+    hipLaunchKernelGGL(k_cell_count, dim3(nblk(n, 256)), dim3(256), 0, stream, d_xy, n, G, cnt);
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanThreads), 0, stream, cnt, cells, start, fill);
+    hipLaunchKernelGGL(k_cell_scatter, dim3(nblk(n, 256)), dim3(256), 0, stream, d_t, d_xy, n, G, start, fill, ct,
+                       cxs, cys);
     int64_t m;
     const int64_t *cidx;
     const int *pos, *slot;
     hk_subset_view(p, &m, &cidx, &pos, &slot);
-    hipLaunchKernelGGL(k_features, dim3(nblk(m, 256)), dim3(256), 0, stream, d_t, d_xy, cidx, pos, slot, p->g, d_z,
-                       m, p->n, p->t1, G, grid, d_feat);
+    hipLaunchKernelGGL(k_features, dim3(nblk(m * HK_WAVE, 256)), dim3(256), 0, stream, d_t, d_xy, cidx, pos, slot,
+                       p->g, d_z, m, n, p->t0, p->t1, hy->h, hy->tau_x, hy->omega, G, start, ct, cxs, cys, d_feat);
     HK_CHECK(hipGetLastError());
     return HAWKES_OK;
 }

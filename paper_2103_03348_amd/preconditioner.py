@@ -63,7 +63,7 @@ class LearnedPreconditioner:
 
     def collect(self, n_states: int, eps: float, thin: int = 1):
         """Advance the sampler (current mass) and record the features and the
-        training target log max(H_k, 1e-30) (Eq. 5 on the subset, computed by the
+        training target log max(H_k, 1e-6) (Eq. 5 on the subset, computed by the
         library) at n_states states.  Returns (X [n_states*m, 12], T [n_states*m])."""
         m = self.s.m
         X = torch.empty((n_states * m, N_FEATURES), dtype=torch.float32, device=self.dev)

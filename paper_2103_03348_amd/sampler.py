@@ -89,7 +89,7 @@ class HmcSampler:
     def curvature(self, curv: torch.Tensor = None, log_h: torch.Tensor = None):
         """The library's hawkes_subset_curvature at the current state, into the
         given device buffers (slot order): the exact z-space curvature
-        theta^2 H - theta g + P (FP64) and log max(H, 1e-30) (FP32)."""
+        theta^2 H - theta g + P (FP64) and log max(H, 1e-6) (FP32)."""
         _lib.check(_lib.lib().hawkes_subset_curvature(self.plan.handle, ctypes.byref(self.hyper),
                                                       _lib.ptr(self.theta), self.sigma_z, self.prior,
                                                       _lib.ptr(curv), _lib.ptr(log_h), _lib.stream_handle()),

@@ -182,7 +182,7 @@ def test_curvature_and_mass_update_match_oracle(gpu, variant):
     c = curv.cpu().numpy()
     rel = float(np.max(np.abs(c - ref) / scale))
     lh = logh.cpu().numpy().astype(np.float64)
-    lh_ref = np.log(np.maximum(H, 1e-30))
+    lh_ref = np.log(np.maximum(H, 1e-6))
     print(f"\n[{variant}] curvature rel {rel:.2e}  log H max abs {np.max(np.abs(lh - lh_ref)):.2e}", flush=True)
     assert rel < 1e-6
     # FP32 output of log H: its rounding (|log H| <= 69, 2^-24 relative) plus Eq. 5's 1e-6
@@ -251,8 +251,8 @@ def test_learned_preconditioner_gain(gpu):
     print(f"\nheld-out MSE (log H): untrained {loss0:.3e} trained {loss1:.3e} constant {var:.3e}; "
           f"mean relative mass error at the last state: learned {err_learned:.3e}, identity {err_identity:.3e}",
           flush=True)
-    # log H spans tens of units (a long tail of small entries, down to the
-    # 1e-30 floor), so the untrained network's error is mostly the targets'
+    # log H spans about 14 units (a long tail of small entries, down to the
+    # 1e-6 floor), so the untrained network's error is mostly the targets'
     # offset; the decisive checks are the constant predictor and the mass
     assert loss1 < 0.2 * loss0
     assert loss1 < 0.8 * var

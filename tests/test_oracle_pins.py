@@ -483,22 +483,34 @@ def test_adam_later_steps_closed_forms():
 
 
 def test_features_small_hand_case():
-    """Grid-count features on a hand-built set: three events share one h-cell, the
-    time bins are known, and the rank / window features follow their definitions."""
+    """Disc and time-window count features on a hand-built set (h = 0.3,
+    tau_x = 2, omega = 0.5: windows of 2 and 6 time units), counted by hand:
+    the counts, the self-exclusion, the strict and closed window ends and the
+    rank / window-end features follow their definitions."""
     from oracle import features
     hy = (0.7, 2.0, 5.0, 0.3, 0.5, 0.3)
-    t = np.array([0.5, 1.0, 2.5, 2.6, 7.0])       # bins at omega = 0.5: 0, 0, 1, 1, 3
-    x = np.array([0.05, 0.1, 0.2, 5.0, 0.15])     # cells of size 0.3 from gx0 = 0: 0, 0, 0, 16, 0
-    y = np.array([0.05, 0.1, 0.2, 5.0, 0.1])
-    F = features.features(t, x, y, np.array([0, 2]), np.array([0.1, -0.2]), hy, 0.0, 0.0, 0.0)
-    # event 0: others in its h-cell: events 1, 2, 4
-    assert F[0, 0] == pytest.approx(np.log1p(3))
-    # event 0 (bin 0): next bin (1) in its h-cell holds event 2; bins 1..3 hold events 2 and 4
-    assert F[0, 4] == pytest.approx(np.log1p(1)) and F[0, 5] == pytest.approx(np.log1p(2))
-    # event 2 (bin 1): previous bin holds events 0 and 1
-    assert F[1, 3] == pytest.approx(np.log1p(2))
+    #             e0    e1    e2    e3    e4    e5
+    t = np.array([0.5, 1.0, 2.5, 2.6, 7.0, 2.5])
+    x = np.array([0.0, 0.1, 0.0, 5.0, 0.5, 1.5])
+    y = np.array([0.0, 0.1, 0.25, 5.0, 0.0, 0.0])
+    # distances from e0: e1 0.141, e2 0.25, e3 7.07, e4 0.5, e5 1.5
+    # distances from e2: e0 0.25, e1 0.180, e3 6.9, e4 0.559, e5 1.52
+    F = features.features(t, x, y, np.array([0, 2]), np.array([0.1, -0.2]), hy, 0.0, -1.0, -1.0)
+    L = np.log1p
+    # e0: within h = 0.3: e1, e2; within 0.9: + e4; within 2: + e5
+    assert F[0, 0] == L(2) and F[0, 1] == L(3) and F[0, 2] == L(4)
+    # e0, r = h: no earlier event; later within 2 time units: e1 (dt 0.5), e2 (dt 2.0, closed end)
+    assert F[0, 3] == L(0) and F[0, 4] == L(2) and F[0, 5] == L(2)
+    # e0, r = 3h: e4 (dt 6.5) is outside 3/omega = 6
+    assert F[0, 6] == L(0) and F[0, 7] == L(2) and F[0, 8] == L(2)
+    # e2: within h: e0, e1; within 3h: + e4; within 2: + e5 (1.52)
+    assert F[1, 0] == L(2) and F[1, 1] == L(3) and F[1, 2] == L(4)
+    # e2, r = h: earlier within [-2, 0): e1 (dt -1.5); e0 (dt -2.0, closed end) too
+    assert F[1, 3] == L(2) and F[1, 4] == L(0) and F[1, 5] == L(0)
+    # e2, r = 3h: later e4 (dt 4.5) only in the 6-unit window; e5 ties (dt 0) and is far
+    assert F[1, 6] == L(2) and F[1, 7] == L(0) and F[1, 8] == L(1)
     assert F[1, 9] == -0.2
-    assert F[1, 10] == pytest.approx(2 / 5) and F[1, 11] == pytest.approx((7.0 - 2.5) / 7.0)
+    assert F[1, 10] == pytest.approx(2 / 6) and F[1, 11] == pytest.approx((7.0 - 2.5) / 7.0)
 
 
 def test_ess_of_ar1_chain():
