@@ -47,16 +47,19 @@ EXPS_COL_PER_PAIR = 1
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
-# HBM traffic of one k_row launch at N = 23,422, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE scaled by a device-to-device copy of known size (summary and
-# commands in profiles/k_row_k_col_N23422_counters.md): 6.1 MB read + 64.7 MB
-# written.  It holds only for the kernel sources it was measured on, so it is
-# reported only while their hashes match.
-K_ROW_TRAFFIC_BYTES = (2956.8 * 2.0 + 63220.0 * 1.0) * 1024
+# Counters of one k_row launch at N = 23,422 (summary and commands in
+# profiles/k_row_k_col_N23422_counters.md): HBM traffic from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by a device-to-device copy of known size,
+# 6.2 MB read + 64.7 MB written; v_exp_f32 executed per pair from
+# SQ_INSTS_VALU_TRANS_F32 (2.03: the masked diagonal sweeps evaluate some
+# terms they discard).  They hold only for the kernel sources they were
+# measured on, so they are reported only while these hashes match.
+K_ROW_TRAFFIC_BYTES = (3041.5 * 2.0 + 63220.0 * 1.0) * 1024
+K_ROW_TRANS_PER_PAIR = 2.03
 K_ROW_TRAFFIC_SOURCES = {
-    "paper_2103_03348_amd/csrc/hawkes_eval.hip": "766224932625cc74e2961241c7cf8da0798e21f664cf118efb24bd5ca394b747",
-    "paper_2103_03348_amd/csrc/hawkes_internal.h": "2aa8756eb3ee65e588f232f1bdea36771427471e5c46ab11c70b541246ef42bb",
-    "paper_2103_03348_amd/csrc/hawkes_plan.hip": "01aa5fe9f2c06a858611a9f6aded275bb196a13f4fe5b2c6d835bb712a62c2d0",
+    "paper_2103_03348_amd/csrc/hawkes_eval.hip": "4825f6259443667051a9a58d942be9f0523dca362ede183052d66d08e82995ba",
+    "paper_2103_03348_amd/csrc/hawkes_internal.h": "9ab2ecc1fe0cd3b46f406e21574357466a800c182c1a698d4ff675d782a8db8f",
+    "paper_2103_03348_amd/csrc/hawkes_plan.hip": "37d284359db290dc76b08a929904c571c6d6f0f1b42c63d87c34b2ff657fa368",
 }
 
 
@@ -476,7 +479,11 @@ def main():
             "transcendental": {"exp2_per_s": EXPS_ROW_PER_PAIR * pairs / (row_ms * 1e-3),
                                "peak_exp2_per_s_measured": exp_peak["exp2_per_s"],
                                "frac": EXPS_ROW_PER_PAIR * pairs / (row_ms * 1e-3) / exp_peak["exp2_per_s"],
-                               "exps_per_pair": EXPS_ROW_PER_PAIR},
+                               "exps_per_pair": EXPS_ROW_PER_PAIR,
+                               # executed v_exp_f32 (counters) over the same time, while the sources match
+                               "executed_exp2_per_s": (K_ROW_TRANS_PER_PAIR * pairs / (row_ms * 1e-3)
+                                                       if k_row_traffic() is not None and args.config == 1
+                                                       else None)},
         },
         "evaluation_roofline": {"flops_per_pair": FLOPS_PER_PAIR, "ms": eval_ms, "achieved": eval_tf,
                                 "frac": eval_tf / PEAK_FP32_PUBLISHED_TFLOPS,

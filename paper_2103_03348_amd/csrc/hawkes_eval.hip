@@ -176,10 +176,17 @@ __device__ __forceinline__ float exp2_split(double e) {
 // differences converted to FP32 and scaled and carries no rounded FP32 scale.
 // The excitation's spatial exponent is that value times the ratio kex / kbx.
 //
-// Constants: in the log-likelihood-only mode the FP32 constants are completed
-// by their low parts inside the loop (the fast form) or taken exact in FP64
-// (the precise form); the other modes use the FP32-rounded values in both forms
-// and correct their rounding to first order through the first moments.
+// Constants: times enter scaled by st = 1 / (tau_t sqrt(2 ln 2)) (in FP64,
+// before any rounding), so the background's time exponent is exactly -dt'^2 and
+// carries no rounded constant; the time moments are rescaled in FP64 by the
+// finalisation.  The excitation's spatial exponent is the background's times
+// the ratio rex = kex / kbx: in the log-likelihood-only mode the FP32 ratio is
+// completed by its low part inside the loop (the fast form) or taken exact in
+// FP64 (the precise form); the other modes use the FP32-rounded ratio in both
+// forms and correct its rounding to first order through the moment X2.  (A low
+// part added to an exactly representable FP32 value in a separate rounding
+// would mostly be rounded away, one way: the earlier form of the background's
+// time constant biased the log-likelihood-only pass's lambda by about 1e-9.)
 
 // One pair's terms into the accumulators (b: background term, te: theta_j E_ij,
 // ar, ae: spatial exponents of the two kernels in log2 units, dt = t_i - t_j).
@@ -226,7 +233,6 @@ __device__ __forceinline__ void row_sweep(const float2 *__restrict__ rec, const 
     // explicit FMAs only: a contracted (rotated + product) cannot take the DPP
     // operand, while a plain add of the shared product can
 #pragma clang fp contract(off)
-    const double kbt_d = MODE == HK_MODE_LOGLIK ? kc.kbt_x : (double)kc.kbt;
     const double rex_d = MODE == HK_MODE_LOGLIK ? kc.rex_x : (double)kc.rex;
 #pragma unroll 16
     for (int s = 0; s < HK_WAVE; ++s) {
@@ -238,17 +244,17 @@ __device__ __forceinline__ void row_sweep(const float2 *__restrict__ rec, const 
             dt = ti - r.x;
             ar = (float)(-fma(dx, dx, dy * dy));
             dt2 = dt * dt;
-            b = fexp2(MODE == HK_MODE_LOGLIK ? fmaf(dt2, kc.kbt, fmaf(dt2, kc.kbt_lo, ar)) : fmaf(dt2, kc.kbt, ar));
+            b = fexp2(ar - dt2);
             ae = MODE == HK_MODE_LOGLIK ? fmaf(ar, kc.rex, ar * kc.rex_lo) : ar * kc.rex;
             E = fexp2(ae);
         } else {
             const double dtd = tsi - rtd[lane + s];
             const double ard = -fma(dx, dx, dy * dy);
             const double aed = ard * rex_d;
-            b = exp2_split(fmax(fma(dtd * kbt_d, dtd, ard), HK_EXP_FLOOR));
+            b = exp2_split(fmax(fma(-dtd, dtd, ard), HK_EXP_FLOOR));
             // a masked sweep also meets later columns (dt < 0, masked below): their
             // exponent is held at 2^128 so that its integer part stays in range
-            double ee = fmax(fma(dtd, kc.kw_d, aed), HK_EXP_FLOOR);
+            double ee = fmax(fma(dtd, kc.kw_s, aed), HK_EXP_FLOOR);
             if (MASK_BG || MASK_EX) ee = fmin(ee, 128.0);
             E = exp2_split(ee);
             ar = (float)ard;
@@ -282,7 +288,7 @@ __device__ __forceinline__ void row_sweep_masked(const float2 *__restrict__ rec,
 }
 
 template <int MODE>
-__global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, const int *__restrict__ xi,
+__global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ ts, const int *__restrict__ xi,
                                                   const int *__restrict__ yi, const float *__restrict__ theta_v,
                                                   const int *__restrict__ chunk_precise, const double *__restrict__ tstep,
                                                   const int *__restrict__ g, const hk_item *__restrict__ items,
@@ -308,6 +314,7 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
         const int64_t row0 = (int64_t)I * HK_TILE;
         const int irow = (int)(row0 + tid);
         const double tsi = ts[irow];
+        const double tsi_s = tsi * kc.st;  // scaled time (the precise form's FP64 differences)
         const double xr = (double)xi[irow] * kc.sbx, yr = (double)yi[irow] * kc.sbx;
         const int gr = g[irow];
         const int wave_chunk = I * HK_CHUNKS_PER_TILE + wv;
@@ -339,19 +346,19 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
             const bool block_live = !(tile_tmin - Tlast > kc.dt_cut);
             // fast form: times relative to the chunk's first event, rounded to FP32
             const double Tc = ts[(int64_t)c * HK_WAVE];
-            const float ti = (float)(tsi - Tc);
+            const float ti = (float)((tsi - Tc) * kc.st);  // scaled time
             if (block_live && tid < HK_WAVE) {
                 const int64_t j = (int64_t)c * HK_WAVE + tid;
                 const double tj = ts[j];
                 float2 r;
-                r.x = (float)(tj - Tc);
+                r.x = (float)((tj - Tc) * kc.st);
                 r.y = theta_v[j];  // theta_j, times exp(omega (t_j - T_c)) on a fast chunk
                 rec[tid] = r;
                 rec[tid + HK_WAVE] = r;
                 const double2 pj = make_double2((double)xi[j] * kc.sbx, (double)yi[j] * kc.sbx);
                 rxy[tid] = pj;
                 rxy[tid + HK_WAVE] = pj;
-                rtd[tid] = rtd[tid + HK_WAVE] = tj;
+                rtd[tid] = rtd[tid + HK_WAVE] = tj * kc.st;
             }
             __syncthreads();
             const bool fact = chunk_precise[c] == 0;
@@ -366,10 +373,10 @@ __global__ __launch_bounds__(HK_TILE) void k_row(const double *__restrict__ ts, 
             const bool live = block_live && c <= wave_chunk && !(wave_tmin - Tlast > kc.dt_cut);
             if (live) {
                 if (fact)
-                    row_sweep_masked<MODE, true>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
+                    row_sweep_masked<MODE, true>(rec, rxy, rtd, tsi_s, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
                                                  blk, C, B0d, X0c, C0d);
                 else
-                    row_sweep_masked<MODE, false>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
+                    row_sweep_masked<MODE, false>(rec, rxy, rtd, tsi_s, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
                                                   blk, C, B0d, X0c, C0d);
                 // the row's time factor (t_i >= T_c here, so it is at most 1)
                 if (fact) {
@@ -539,11 +546,10 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
             acc[k] = v;
         }
         // moments corrected for the mean exp2 bias and, when the first moments
-        // are present, for the rounding of the FP32 exponent constants
+        // are present, for the rounding of the FP32 ratio rex
         double b0 = acc[0], x0 = acc[5];
         if (MODE >= HK_MODE_GRAD) {
             const double ln2 = 0.6931471805599453;
-            b0 -= ln2 * fc.dkbt * acc[2];
             x0 -= ln2 * fc.rho_ex * acc[7];
         }
         const double B0 = b0 * fc.corr, X0 = x0 * fc.corr;
@@ -558,8 +564,8 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
         lw[i] = lamv > 0.0 ? fmax(fc.log2_ce - s[0] * 1.4426950408889634, HK_EXP_FLOOR) : HK_EXP_FLOOR;
         const double inv = 1.0 / lamv;
         if (MODE >= HK_MODE_GRAD) {
-            const double B1 = acc[1] * fc.corr * fc.Kx, B2 = acc[2] * fc.corr;
-            const double X1 = acc[6] * fc.corr, X2 = acc[7] * fc.corr * fc.Kh;
+            const double B1 = acc[1] * fc.corr * fc.Kx, B2 = acc[2] * fc.corr * fc.Kt;
+            const double X1 = acc[6] * fc.corr * fc.inv_st, X2 = acc[7] * fc.corr * fc.Kh;
             const double tx = fc.tau_x, tt = fc.tau_t, om = fc.omega, hh = fc.h;
             double d1[6];
             d1[0] = fc.cb1 * B0;
@@ -571,8 +577,8 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
 #pragma unroll
             for (int p = 0; p < 6; ++p) s[1 + p] = d1[p] * inv;
             if (MODE >= HK_MODE_HESS) {
-                const double B11 = acc[3] * fc.corr * fc.Kx * fc.Kx, B22 = acc[4] * fc.corr;
-                const double X11 = acc[8] * fc.corr, X22 = acc[9] * fc.corr * fc.Kh * fc.Kh;
+                const double B11 = acc[3] * fc.corr * fc.Kx * fc.Kx, B22 = acc[4] * fc.corr * fc.Kt * fc.Kt;
+                const double X11 = acc[8] * fc.corr * fc.inv_st * fc.inv_st, X22 = acc[9] * fc.corr * fc.Kh * fc.Kh;
                 const double tx2 = tx * tx, tt2 = tt * tt, hh2 = hh * hh;
                 double d2[6];
                 d2[0] = 0.0;
@@ -909,11 +915,10 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     const double kbt = -1.0 / (2.0 * hy->tau_t * hy->tau_t * ln2);
     const double kex = -two_m2k / (2.0 * hy->h * hy->h * ln2);
     const double kw = -hy->omega / ln2;
-    kc->kbt = (float)kbt;
-    kc->kw = (float)kw;
-    kc->cw = (float)(ln2 * (kw - (double)kc->kw));
+    kc->st = sqrt(-kbt);
     kc->omega = hy->omega;
     kc->kw_d = kw;
+    kc->kw_s = kw / kc->st;
     // time gaps beyond which every background term (exponent <= kbt dt^2) and
     // every excitation term (exponent <= kw dt) is below 2^-160: exactly zero in
     // FP32, and below 1e-48 of a unit term in the split form
@@ -933,12 +938,11 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
         kc->dot = 2.0 * umax * umax <= HK_DOT_MAX2;
     }
     kc->rex = (float)(kex / kbx);
-    kc->kbt_x = kbt;
     kc->rex_x = kex / kbx;
     kc->span_max = fmin(HK_FACT_SPAN / hy->omega, HK_COMPACT_TAU * hy->tau_t);
-    kc->kbt_lo = (float)(kbt - (double)kc->kbt);
     kc->rex_lo = (float)(kex / kbx - (double)kc->rex);
-    fc->dkbt = (double)kc->kbt - kbt;
+    fc->Kt = -1.0 / kbt;
+    fc->inv_st = 1.0 / kc->st;
     fc->rho_ex = ((double)kc->rex - kex / kbx) / (double)kc->rex;
     const double corr = 1.0 / (1.0 + HK_EXP2_BIAS);
     const double two_pi = 6.283185307179586;

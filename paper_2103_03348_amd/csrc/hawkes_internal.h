@@ -160,19 +160,19 @@ struct PairConst {
     // With k the coordinates' fixed-point scale (2^k units per unit length),
     // kbx = -2^{-2k} / (2 tau_x^2 ln 2) and kex = -2^{-2k} / (2 h^2 ln 2) map a
     // fixed-point squared distance to the log2 exponents a_b and a_e.
-    float kbt;     // -1 / (2 tau_t^2 ln 2)
-    float kw;      // -omega / ln 2
-    float cw;      // ln 2 (kw - kw_f): first-order correction of the rounded kw, per unit dt
+    // The row pass takes times scaled by st = 1 / (tau_t sqrt(2 ln 2)), so the
+    // background's time exponent is exactly -dt'^2 (no rounded constant).
+    double st;
     float rex;     // kex / kbx: a_e = a_b rex in the row pass
-    // low parts of the two FP32 constants above (kbt - (double)kbt_f, rex - (double)rex_f):
-    // the log-likelihood-only row pass, which carries no first moments to correct
-    // their rounding with, applies them inside the pair loop instead
-    float kbt_lo;
+    // low part of rex (rex - (double)rex_f): the log-likelihood-only row pass,
+    // which carries no first moments to correct its rounding with, applies it
+    // inside the pair loop instead (in an FMA whose exact product is rounded
+    // once, so the low part is not lost)
     float rex_lo;
     double omega;  // excitation decay rate (time factors formed in FP64)
-    double kw_d;   // kw in FP64 (exponents formed in FP64)
-    double kbt_x;  // kbt exact in FP64 (the row pass's precise form, log-likelihood-only mode)
-    double rex_x;  // kex / kbx exact in FP64 (the same)
+    double kw_d;   // -omega / ln 2 in FP64 (exponents formed in FP64)
+    double kw_s;   // kw_d / st: the same per scaled time unit (the row pass's precise form)
+    double rex_x;  // kex / kbx exact in FP64 (the row pass's precise form, log-likelihood-only mode)
     double span_max;   // row pass: the fast form's largest chunk time span
     double sx;     // sqrt(-kex): fixed-point coordinate -> coordinate whose squared distance is -a_e
     double sbx;    // sqrt(-kbx): the same for the background exponent a_b
@@ -189,13 +189,15 @@ struct FinConst {
     double corr;           // 1 / (1 + exp2 bias)
     double log2_ce;        // log2(c_e) (-inf when theta0 = 0)
     double t0, t1;
-    // First-order correction for the rounding of the FP32 exponent constants:
-    // a term computed as exp2(a + d) equals exp2(a) (1 + d ln 2 + O(d^2)), and d
-    // is linear in dt^2 (background) and r^2 (excitation), whose weighted sums
-    // are the first moments the row passes accumulate.  (The background's
-    // spatial exponent is formed in FP64 with an exact scale; the excitation's
-    // time term is formed in FP64 or corrected inside the pair loop.)
-    double dkbt;           // kbt_f - kbt
+    // The row pass's time moments are in scaled time (t' = st t): dt^2 moments
+    // are dt'^2 moments times Kt = 1/st^2 = 2 tau_t^2 ln 2, dt moments dt'
+    // moments times 1/st.
+    double Kt, inv_st;
+    // First-order correction for the rounding of the FP32 ratio rex: a term
+    // computed as exp2(a + d) equals exp2(a) (1 + d ln 2 + O(d^2)), and d is
+    // linear in the excitation's spatial exponent, whose weighted sum X2 the
+    // row pass accumulates.  (The background's exponent carries no rounded
+    // constant; the excitation's time term is exact or formed in FP64.)
     double rho_ex;         // (rex_f - rex) / rex_f: the row pass forms a_e = a_b rex_f
 };
 
