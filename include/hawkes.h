@@ -357,8 +357,11 @@ hawkes_status hawkes_mass_update(hawkes_plan p, const hawkes_hyper *hyper, const
                                  hipStream_t stream);
 
 /* Timing of the pair passes with HIP events recorded on the launch stream.
- * hawkes_profile_enable(p, 1) starts recording around every row pass, column
- * pass and whole evaluation of plan p; 0 stops and discards.
+ * hawkes_profile_enable(p, k) with k >= 1 starts recording around the row
+ * pass, the column pass and the whole evaluation of every k-th evaluation of
+ * plan p (the first, the (k+1)-th, ...); 0 stops and discards.  An event
+ * between two dependent kernels delays the second by several microseconds,
+ * so a k above 1 keeps the timing from slowing most evaluations.
  * hawkes_profile_read synchronises and fills host out[6] with
  * (total ms, count) for the row pass, the column pass and the whole evaluation
  * since the last read, then resets the totals. */
