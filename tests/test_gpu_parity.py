@@ -13,9 +13,9 @@ Tolerances (FP32 pair arithmetic, compensated sums, FP64 finals):
     1e-6 norm-wise.  The column pass forms each term's whole exponent in FP64
     and rounds only its fractional part to FP32, so a term's relative error
     does not grow with the size of its exponent.
-  * sparse data (chunks of 64 events spanning more than 40/omega in time), where
-    the row pass uses the direct exponent instead of the split time factor:
-    the same bounds.
+  * sparse data (chunks of 64 events spanning more than tau_t/2 in time), where
+    the row pass takes its precise form (FP64 time differences, whole
+    exponents in FP64 with an exact power of two): the same bounds.
   * hyperparameter derivatives on sets below 256 events: 1e-5 instead of 1e-6
     (a handful of FP32 terms carry each sum without averaging, and the second
     derivatives in tau_x and h cancel three such sums).
@@ -70,9 +70,10 @@ def test_small_ragged(gpu, n, seed, ties, dup):
 
 @pytest.mark.parametrize("n,seed,per_event", [(300, 31, 3.0), (700, 32, 3.0), (2000, 33, 1.2)])
 def test_sparse_fallback(gpu, n, seed, per_event):
-    """Chunks that span more than the split's limit take the direct exponent:
-    all of them at 3 time units per event, about half of them at 1.2, where
-    the split factors carried by step factors restart after every such chunk."""
+    """Chunks that span more than tau_t/2 in time take the row pass's precise
+    form (every chunk of these sets); at 3 time units per event every chunk
+    also spans more than the split limit 40/omega, at 1.2 about a third of
+    them, where the split factors carried by step factors restart."""
     es = synth.small(n, seed=seed, t_end=per_event * n, ties=2)
     g = run_gpu(es)
     ref = oracle.evaluate_es(es)
@@ -140,6 +141,37 @@ def test_determinism(gpu):
     b = run_gpu(es)
     for k in ("loglik", "grad_theta", "negH_theta", "grad_hyper", "negH_hyper", "lam"):
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+def test_pass_timing_samples_evaluations(gpu):
+    """hawkes_profile_enable(p, k) records HIP events around the passes of the
+    first evaluation and every k-th after it only; 0 discards."""
+    import ctypes
+
+    import torch
+
+    from paper_2103_03348_amd import _lib
+    from paper_2103_03348_amd.hawkes import Plan
+
+    es = synth.small(500, seed=13)
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
+    th = torch.as_tensor(es.theta, device="cuda:0")
+    lib = _lib.lib()
+    assert lib.hawkes_profile_enable(plan.handle, -1) == _lib.E_INVALID
+    _lib.check(lib.hawkes_profile_enable(plan.handle, 3), "profile_enable")
+    for _ in range(7):
+        plan.eval(th, es.hyper, loglik=True, grad_theta=True)
+    out = (ctypes.c_double * 6)()
+    _lib.check(lib.hawkes_profile_read(plan.handle, out), "profile_read")
+    # evaluations 1, 4 and 7 of seven: row pass, column pass, whole evaluation
+    assert [out[1], out[3], out[5]] == [3.0, 3.0, 3.0]
+    assert all(out[2 * k] > 0.0 for k in range(3))
+    _lib.check(lib.hawkes_profile_enable(plan.handle, 0), "profile_disable")
+    plan.eval(th, es.hyper, loglik=True)
+    _lib.check(lib.hawkes_profile_read(plan.handle, out), "profile_read")
+    assert [out[1], out[3], out[5]] == [0.0, 0.0, 0.0]
+    torch.cuda.synchronize()
+    plan.close()
 
 
 def test_permutation_invariance(gpu):
