@@ -222,7 +222,9 @@ def test_exp2_bias_matches_library_constant(gpu):
 
 
 def test_loglik_only_n23422(gpu):
-    """The log-likelihood-only sweep (no moments, double-float exponent constants)."""
+    """The log-likelihood-only row pass (no moments; scaled times, so the
+    background exponent carries no rounded constant, and the excitation ratio
+    completed by its low part inside an FMA)."""
     es = synth.config(1)
     g = run_gpu(es, want_all=False)
     ref = oracle.evaluate_es(es, want=("loglik", "lam", "Lam_n"))
