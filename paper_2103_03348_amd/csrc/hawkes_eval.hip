@@ -206,10 +206,12 @@ __device__ __forceinline__ float exp2_split(double e) {
 template <int MODE>
 __device__ __forceinline__ void row_accumulate(float b, float te, float ar, float ae, float dt, float dt2,
                                                float (&blk)[HK_NROW], float (&C)[HK_NCOL], double &B0d,
-                                               double &X0c, double &C0d) {
+                                               double &X0c, double *__restrict__ acc0) {
 #pragma clang fp contract(off)
-    B0d += (double)b;
-    C0d = rot_next_d(C0d) + (double)b;
+    const double bd = (double)b;
+    B0d += bd;
+    // the column's FP64 sum: an LDS add into this step's slot (no return value)
+    __hip_atomic_fetch_add(acc0, bd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     if (MODE >= HK_MODE_GRAD) {
         const float p1 = b * ar, p2 = b * dt2;
         blk[1] += p1;
@@ -242,7 +244,7 @@ __device__ __forceinline__ void row_sweep(const float2 *__restrict__ rec, const 
                                           double tsi, int lane, float ti, double xr, double yr,
                                           int irow, int gr, int cbase, const PairConst kc,
                                           float (&blk)[HK_NROW], float (&C)[HK_NCOL], double &B0d, double &X0c,
-                                          double &C0d) {
+                                          double *__restrict__ acc0) {
     // explicit FMAs only: a contracted (rotated + product) cannot take the DPP
     // operand, while a plain add of the shared product can
 #pragma clang fp contract(off)
@@ -280,7 +282,7 @@ __device__ __forceinline__ void row_sweep(const float2 *__restrict__ rec, const 
             if (MASK_BG && !(j < irow)) b = 0.0f;
             if (!(j < gr)) E = 0.0f;
         }
-        row_accumulate<MODE>(b, E * r.y, ar, ae, dt, dt2, blk, C, B0d, X0c, C0d);
+        row_accumulate<MODE>(b, E * r.y, ar, ae, dt, dt2, blk, C, B0d, X0c, acc0 + lane + s);
     }
 }
 
@@ -290,14 +292,14 @@ __device__ __forceinline__ void row_sweep_masked(const float2 *__restrict__ rec,
                                                  double tsi, int lane, float ti, double xr, double yr,
                                                  int irow, int gr, int c, int wave_chunk, int wave_gmin,
                                                  const PairConst kc, float (&blk)[HK_NROW],
-                                                 float (&C)[HK_NCOL], double &B0d, double &X0c, double &C0d) {
+                                                 float (&C)[HK_NCOL], double &B0d, double &X0c, double *__restrict__ acc0) {
     const int cbase = c * HK_WAVE;
     if (c == wave_chunk)
-        row_sweep<MODE, true, true, FAST>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+        row_sweep<MODE, true, true, FAST>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, acc0);
     else if (cbase + HK_WAVE - 1 >= wave_gmin)
-        row_sweep<MODE, false, true, FAST>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+        row_sweep<MODE, false, true, FAST>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, acc0);
     else
-        row_sweep<MODE, false, false, FAST>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, C0d);
+        row_sweep<MODE, false, false, FAST>(rec, rxy, rtd, tsi, lane, ti, xr, yr, irow, gr, cbase, kc, blk, C, B0d, X0c, acc0);
 }
 
 template <int MODE>
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ t
     __shared__ double2 rxy[2 * HK_WAVE];
     __shared__ double rtd[2 * HK_WAVE];
     __shared__ float colbuf[HK_WAVES][HK_NCOL][HK_WAVE];
-    __shared__ double colbuf0[HK_WAVES][HK_WAVE];
+    __shared__ double colacc0[HK_WAVES][2 * HK_WAVE];  // column sums of the background, per wave
     constexpr int NC = MODE == HK_MODE_LOGLIK ? 1 : (MODE == HK_MODE_GRAD ? 3 : 5);
     // the wavefront index is made visibly uniform, so that the per-wave chunk
     // bounds below live in scalar registers and select the sweep variant with
@@ -374,9 +376,13 @@ __global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ t
                 rtd[tid] = rtd[tid + HK_WAVE] = tj * kc.st;
             }
             __syncthreads();
+            // the wave's column slots start at zero (the previous chunk's reads of
+            // them ended before the barrier above)
+            colacc0[wv][lane] = 0.0;
+            colacc0[wv][lane + HK_WAVE] = 0.0;
             const bool fact = chunk_precise[c] == 0;
             float blk[HK_NROW], C[HK_NCOL];
-            double C0d = 0.0, X0c = 0.0;
+            double X0c = 0.0;
 #pragma unroll
             for (int a = 0; a < HK_NROW; ++a) blk[a] = 0.0f;
 #pragma unroll
@@ -387,10 +393,10 @@ __global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ t
             if (live) {
                 if (fact)
                     row_sweep_masked<MODE, true>(rec, rxy, rtd, tsi_s, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
-                                                 blk, C, B0d, X0c, C0d);
+                                                 blk, C, B0d, X0c, colacc0[wv]);
                 else
                     row_sweep_masked<MODE, false>(rec, rxy, rtd, tsi_s, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
-                                                  blk, C, B0d, X0c, C0d);
+                                                  blk, C, B0d, X0c, colacc0[wv]);
                 // the row's time factor (t_i >= T_c here, so it is at most 1)
                 if (fact) {
                     if (!have_ui) {
@@ -408,7 +414,6 @@ __global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ t
             }
             // after 64 rotation steps lane l holds the accumulators of column (l - 1) mod 64
             const int col = (lane + HK_WAVE - 1) & (HK_WAVE - 1);
-            colbuf0[wv][col] = C0d;
 #pragma unroll
             for (int a = 1; a < NC; ++a) colbuf[wv][a][col] = C[a];
             __syncthreads();
@@ -417,8 +422,12 @@ __global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ t
             for (int e = tid; e < NC * HK_WAVE; e += HK_TILE) {
                 const int a = e / HK_WAVE, cc = e % HK_WAVE;
                 float v;
-                if (a == 0)
-                    v = (float)(((colbuf0[0][cc] + colbuf0[1][cc]) + colbuf0[2][cc]) + colbuf0[3][cc]);
+                if (a == 0) {
+                    double c0 = 0.0;
+#pragma unroll
+                    for (int w = 0; w < HK_WAVES; ++w) c0 += colacc0[w][cc] + colacc0[w][cc + HK_WAVE];
+                    v = (float)c0;
+                }
                 else
                     v = ((colbuf[0][a][cc] + colbuf[1][a][cc]) + colbuf[2][a][cc]) + colbuf[3][a][cc];
                 cp[a * stride + (int64_t)c * HK_WAVE + cc] = v;
