@@ -82,9 +82,9 @@ typedef struct {
  *   d_t      [n] event times (device, FP64)
  *   d_xy     [n][2] event locations, row-major x0 y0 x1 y1 ... (device, FP64)
  *   t_start  window start T0 (the paper uses 0); must be <= min t
- * Sorts the events by time on the device, converts locations to 32-bit fixed
- * point relative to the bounding-box centre (resolution 2^-31 of the extent),
- * builds the tile tables and allocates all scratch.  Synchronises `stream`.
+ * Sorts the events by time on the device, stores the locations in FP64
+ * relative to the bounding-box centre, builds the tile tables and allocates
+ * all scratch.  Synchronises `stream`.
  * On success *out owns device memory until hawkes_plan_destroy. */
 hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const double *d_t, const double *d_xy,
                                  double t_start, hipStream_t stream);

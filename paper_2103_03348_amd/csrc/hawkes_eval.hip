@@ -303,19 +303,29 @@ __device__ __forceinline__ void row_sweep_masked(const float2 *__restrict__ rec,
 }
 
 template <int MODE>
-__global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ ts, const int *__restrict__ xi,
-                                                  const int *__restrict__ yi, const float *__restrict__ theta_v,
+__global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ ts, const double *__restrict__ xs,
+                                                  const double *__restrict__ ys, const float *__restrict__ theta_v,
                                                   const int *__restrict__ chunk_precise, const double *__restrict__ tstep,
                                                   const int *__restrict__ g, const hk_item *__restrict__ items,
                                                   const int *__restrict__ block0,
                                                   const int64_t *__restrict__ colpart_off,
                                                   float *__restrict__ rowpart, float *__restrict__ colpart,
                                                   const PairConst kc) {
-    __shared__ float2 rec[2 * HK_WAVE];
-    __shared__ double2 rxy[2 * HK_WAVE];
-    __shared__ double rtd[2 * HK_WAVE];
-    __shared__ float colbuf[HK_WAVES][HK_NCOL][HK_WAVE];
-    __shared__ double colacc0[HK_WAVES][2 * HK_WAVE];  // column sums of the background, per wave
+    // one LDS block with the staged chunk first: the sweep's loads then reach
+    // every step's entry with an immediate offset from one address register
+    struct Stage {
+        float2 rec[2 * HK_WAVE];
+        double rtd[2 * HK_WAVE];
+        double2 rxy[2 * HK_WAVE];
+        double colacc0[HK_WAVES][2 * HK_WAVE];  // column sums of the background, per wave
+        float colbuf[HK_WAVES][HK_NCOL][HK_WAVE];
+    };
+    __shared__ Stage L;
+    auto &rec = L.rec;
+    auto &rxy = L.rxy;
+    auto &rtd = L.rtd;
+    auto &colacc0 = L.colacc0;
+    auto &colbuf = L.colbuf;
     constexpr int NC = MODE == HK_MODE_LOGLIK ? 1 : (MODE == HK_MODE_GRAD ? 3 : 5);
     // the wavefront index is made visibly uniform, so that the per-wave chunk
     // bounds below live in scalar registers and select the sweep variant with
@@ -330,7 +340,7 @@ __global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ t
         const int irow = (int)(row0 + tid);
         const double tsi = ts[irow];
         const double tsi_s = tsi * kc.st;  // scaled time (the precise form's FP64 differences)
-        const double xr = (double)xi[irow] * kc.sbx, yr = (double)yi[irow] * kc.sbx;
+        const double xr = xs[irow] * kc.sbx, yr = ys[irow] * kc.sbx;
         const int gr = g[irow];
         const int wave_chunk = I * HK_CHUNKS_PER_TILE + wv;
         const int wave_gmin = g[(int64_t)wave_chunk * HK_WAVE];  // g is non-decreasing
@@ -362,6 +372,7 @@ __global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ t
             // fast form: times relative to the chunk's first event, rounded to FP32
             const double Tc = ts[(int64_t)c * HK_WAVE];
             const float ti = (float)((tsi - Tc) * kc.st);  // scaled time
+            const bool fact = chunk_precise[c] == 0;
             if (block_live && tid < HK_WAVE) {
                 const int64_t j = (int64_t)c * HK_WAVE + tid;
                 const double tj = ts[j];
@@ -370,17 +381,16 @@ __global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ t
                 r.y = theta_v[j];  // theta_j, times exp(omega (t_j - T_c)) on a fast chunk
                 rec[tid] = r;
                 rec[tid + HK_WAVE] = r;
-                const double2 pj = make_double2((double)xi[j] * kc.sbx, (double)yi[j] * kc.sbx);
+                const double2 pj = make_double2(xs[j] * kc.sbx, ys[j] * kc.sbx);
                 rxy[tid] = pj;
                 rxy[tid + HK_WAVE] = pj;
-                rtd[tid] = rtd[tid + HK_WAVE] = tj * kc.st;
+                rtd[tid] = rtd[tid + HK_WAVE] = tj * kc.st;  // the precise form's FP64 scaled time
             }
             __syncthreads();
             // the wave's column slots start at zero (the previous chunk's reads of
             // them ended before the barrier above)
             colacc0[wv][lane] = 0.0;
             colacc0[wv][lane + HK_WAVE] = 0.0;
-            const bool fact = chunk_precise[c] == 0;
             float blk[HK_NROW], C[HK_NCOL];
             double X0c = 0.0;
 #pragma unroll
@@ -392,11 +402,11 @@ __global__ __launch_bounds__(HK_TILE, 4) void k_row(const double *__restrict__ t
             const bool live = block_live && c <= wave_chunk && !(wave_tmin - Tlast > kc.dt_cut);
             if (live) {
                 if (fact)
-                    row_sweep_masked<MODE, true>(rec, rxy, rtd, tsi_s, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
-                                                 blk, C, B0d, X0c, colacc0[wv]);
+                    row_sweep_masked<MODE, true>(rec, rxy, rtd, tsi_s, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin,
+                                                 kc, blk, C, B0d, X0c, colacc0[wv]);
                 else
-                    row_sweep_masked<MODE, false>(rec, rxy, rtd, tsi_s, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin, kc,
-                                                  blk, C, B0d, X0c, colacc0[wv]);
+                    row_sweep_masked<MODE, false>(rec, rxy, rtd, tsi_s, lane, ti, xr, yr, irow, gr, c, wave_chunk, wave_gmin,
+                                                  kc, blk, C, B0d, X0c, colacc0[wv]);
                 // the row's time factor (t_i >= T_c here, so it is at most 1)
                 if (fact) {
                     if (!have_ui) {
@@ -797,8 +807,8 @@ __device__ __forceinline__ void col_sweep(const ColRow *__restrict__ rows, const
 }
 
 template <bool WITH_H, bool DOT>
-__global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, const int *__restrict__ xi,
-                                                  const int *__restrict__ yi, const double *__restrict__ lw,
+__global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, const double *__restrict__ xs,
+                                                  const double *__restrict__ ys, const double *__restrict__ lw,
                                                   const int *__restrict__ g, int64_t n,
                                                   const hk_item *__restrict__ items, const int *__restrict__ block0,
                                                   double *__restrict__ colG, const PairConst kc) {
@@ -814,7 +824,7 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
         const int64_t col0 = (int64_t)J * HK_TILE;
         const int jcol = (int)(col0 + tid);
         const double t_ref = ts[col0];
-        const double uxj = (double)xi[jcol] * kc.sx, uyj = (double)yi[jcol] * kc.sx;
+        const double uxj = xs[jcol] * kc.sx, uyj = ys[jcol] * kc.sx;
         // the column's part of the exponent: omega (t_j - T_ref) / ln2 (DOT:
         // minus |u_j|^2); a padding column's terms are never used
         double dj = -kc.kw_d * (ts[jcol] - t_ref);
@@ -832,7 +842,7 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
             if (Tc - tile_tmax > kc.dt_cut_ex) break;
             if (tid < HK_WAVE) {
                 const int64_t i = (int64_t)c * HK_WAVE + tid;
-                const double ux = (double)xi[i] * kc.sx, uy = (double)yi[i] * kc.sx;
+                const double ux = xs[i] * kc.sx, uy = ys[i] * kc.sx;
                 double cr = lw[i] + kc.kw_d * (ts[i] - t_ref);
                 ColRow r;
                 if (DOT) {
@@ -932,10 +942,9 @@ bool hk_hyper_ok(const hawkes_hyper *h) {
 // Constants shared by the evaluation entry points.
 void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, FinConst *fc) {
     const double ln2 = 0.6931471805599453;
-    const double two_m2k = ldexp(1.0, -2 * p->fxk);
-    const double kbx = -two_m2k / (2.0 * hy->tau_x * hy->tau_x * ln2);
+    const double kbx = -1.0 / (2.0 * hy->tau_x * hy->tau_x * ln2);
     const double kbt = -1.0 / (2.0 * hy->tau_t * hy->tau_t * ln2);
-    const double kex = -two_m2k / (2.0 * hy->h * hy->h * ln2);
+    const double kex = -1.0 / (2.0 * hy->h * hy->h * ln2);
     const double kw = -hy->omega / ln2;
     kc->st = sqrt(-kbt);
     kc->omega = hy->omega;
@@ -953,9 +962,9 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     kc->sx = sqrt(-kex);
     kc->sbx = sqrt(-kbx);
     {
-        // largest |s x|^2 over the plan: the fixed-point coordinates are centred,
-        // so |x_fixed| is at most half the bounding box's larger side (plus rounding)
-        const double half = 0.5 * fmax(p->xmax - p->xmin, p->ymax - p->ymin) * ldexp(1.0, p->fxk) + 1.0;
+        // largest |s x|^2 over the plan: the coordinates are centred, so |x| is
+        // at most half the bounding box's larger side (with a margin for rounding)
+        const double half = 0.5 * fmax(p->xmax - p->xmin, p->ymax - p->ymin) * (1.0 + 1e-12);
         const double umax = half * kc->sx;
         kc->dot = 2.0 * umax * umax <= HK_DOT_MAX2;
     }
@@ -976,7 +985,6 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     fc->c_e = fc->ce1 * hy->theta0;
     fc->log2_ce = log2(fc->c_e);
     // moments are accumulated in log2 units of the exponent: r^2 = -2 s^2 ln2 * a
-    // (the fixed-point scale is already inside kbx / kex)
     fc->Kx = -2.0 * hy->tau_x * hy->tau_x * ln2;
     fc->Kh = -2.0 * hy->h * hy->h * ln2;
     fc->corr = corr;
@@ -992,7 +1000,7 @@ static void launch_col(hawkes_plan p, const PairConst &kc, const FinConst &fc, d
                        double *d_grad_hyper = nullptr, double *d_negH_hyper = nullptr) {
     hk_prof_mark(p, HK_PROF_COL, true, stream);
 #define HK_COL(H, D)                                                                                        \
-    hipLaunchKernelGGL((k_col<H, D>), dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi, p->lw, \
+    hipLaunchKernelGGL((k_col<H, D>), dim3(p->n_col_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xs, p->ys, p->lw, \
                        p->g, p->n, p->col_items, p->col_block0, p->colG, kc)
     if (d_negH_theta) {
         if (kc.dot) HK_COL(true, true);
@@ -1053,7 +1061,7 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
                        p->n, kc.omega, kc.span_max, p->theta_s, p->theta_v, p->chunk_precise, p->tstep, p->status);
     hk_prof_mark(p, HK_PROF_ROW, true, stream);
 #define HK_ROW(M)                                                                                              \
-    hipLaunchKernelGGL(k_row<M>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,          \
+    hipLaunchKernelGGL(k_row<M>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xs, p->ys,          \
                        p->theta_v, p->chunk_precise, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off,             \
                        p->rowpart, p->colpart, kc)
 #define HK_FIN(M)                                                                                              \
@@ -1087,7 +1095,7 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
 void hk_launch_row_loglik(hawkes_plan p, const PairConst &kc, hipStream_t stream) {
     hipLaunchKernelGGL(k_tfac<false>, dim3((unsigned)(p->npad / 256)), dim3(256), 0, stream, (const double *)nullptr,
                        p->perm, p->ts, p->n, kc.omega, kc.span_max, p->theta_s, p->theta_v, p->chunk_precise, p->tstep, p->status);
-    hipLaunchKernelGGL(k_row<HK_MODE_LOGLIK>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xi, p->yi,
+    hipLaunchKernelGGL(k_row<HK_MODE_LOGLIK>, dim3(p->n_row_blocks), dim3(HK_TILE), 0, stream, p->ts, p->xs, p->ys,
                        p->theta_v, p->chunk_precise, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off, p->rowpart,
                        p->colpart, kc);
 }

@@ -272,7 +272,7 @@ __global__ void k_sub_offset(const double *__restrict__ ts, const int *__restric
 __global__ __launch_bounds__(256) void k_sub_theta(
     const double *__restrict__ z, const double *__restrict__ off, const int *__restrict__ slot,
     const int64_t *__restrict__ cidx, int64_t m, const int *__restrict__ pos, const double *__restrict__ ts,
-    const int *__restrict__ xi, const int *__restrict__ yi, const PairConst kc, float *__restrict__ tv,
+    const double *__restrict__ xs, const double *__restrict__ ys, const PairConst kc, float *__restrict__ tv,
     double2 *__restrict__ sxy, double *__restrict__ sts, int *__restrict__ qwide, double *__restrict__ qstep,
     double *__restrict__ theta_full) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_sub_theta(
         const double ze = zeff(z, off, k);
         if (theta_full) theta_full[cidx[k]] = exp(ze);
         tv[r] = (float)exp(wide ? ze : ze + kc.omega * dt);
-        sxy[r] = make_double2((double)xi[pj] * kc.sx, (double)yi[pj] * kc.sx);
+        sxy[r] = make_double2(xs[pj] * kc.sx, ys[pj] * kc.sx);
         sts[r] = t;
     } else {
         tv[r] = 0.0f;
@@ -332,7 +332,7 @@ __device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, c
 // precede the chunk's end (64 at a time through LDS); the rows' partial sums go
 // to the item's slot.
 __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
-    const double *__restrict__ ts, const int *__restrict__ xi, const int *__restrict__ yi, const int *__restrict__ g,
+    const double *__restrict__ ts, const double *__restrict__ xs, const double *__restrict__ ys, const int *__restrict__ g,
     const int *__restrict__ pos, const float *__restrict__ tv, const double2 *__restrict__ sxy,
     const double *__restrict__ sts, const int *__restrict__ qwide, const double *__restrict__ qstep,
     const hk_item *__restrict__ ritems, const PairConst kc, double *__restrict__ xpart) {
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
     const int lane = threadIdx.x;
     const int64_t i = (int64_t)b * HK_WAVE + lane;
     const double tsi = ts[i];
-    const double xr = (double)xi[i] * kc.sx, yr = (double)yi[i] * kc.sx;
+    const double xr = xs[i] * kc.sx, yr = ys[i] * kc.sx;
     const int gr = g[i];
     double acc = 0.0;  // every term in FP64 (see the row pass: FP32 sums drop small terms)
     // under the cutoff, batches whose last entry precedes the chunk's first row
@@ -517,8 +517,8 @@ __device__ __forceinline__ void sub_col_sweep(const SubColRow *__restrict__ rows
 // chunks after them; the entries' partial sums go to the item's slot.  Times
 // enter relative to the subset chunk's first entry.
 template <bool WITH_H, bool DOT>
-__global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ ts, const int *__restrict__ xi,
-                                                      const int *__restrict__ yi, const double *__restrict__ lw,
+__global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ ts, const double *__restrict__ xs,
+                                                      const double *__restrict__ ys, const double *__restrict__ lw,
                                                       const int *__restrict__ g, const int *__restrict__ pos,
                                                       const double2 *__restrict__ sxy, const double *__restrict__ sts,
                                                       int64_t m, const hk_item *__restrict__ items,
@@ -543,23 +543,23 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
     double Gd = 0.0, Hd = 0.0;
     // a row chunk is loaded into registers one chunk ahead, so that the loads of
     // the next chunk are in flight during this one's sweep (items are never empty)
-    int nx, ny, ng;
-    double nl, nt;
+    int ng;
+    double nx, ny, nl, nt;
     {
         const int64_t i = (int64_t)it.c_begin * HK_WAVE + lane;
-        nx = xi[i];
-        ny = yi[i];
+        nx = xs[i];
+        ny = ys[i];
         nl = lw[i];
         nt = ts[i];
         ng = g[i];
     }
     for (int c = it.c_begin; c < it.c_end; ++c) {
-        const int px = nx, py = ny, pg = ng;
-        const double pl = nl, pt = nt;
+        const int pg = ng;
+        const double px = nx, py = ny, pl = nl, pt = nt;
         if (c + 1 < it.c_end) {
             const int64_t i = (int64_t)(c + 1) * HK_WAVE + lane;
-            nx = xi[i];
-            ny = yi[i];
+            nx = xs[i];
+            ny = ys[i];
             nl = lw[i];
             nt = ts[i];
             ng = g[i];
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
         const double Tc = ts[(int64_t)c * HK_WAVE];
         if (Tc - q_tmax > kc.dt_cut_ex) break;  // cutoff: all later rows too far
         {
-            const double ux = (double)px * kc.sx, uy = (double)py * kc.sx;
+            const double ux = px * kc.sx, uy = py * kc.sx;
             double cr = pl + kc.kw_d * (pt - t_ref);
             SubColRow w;
             if (DOT) {
@@ -1029,9 +1029,9 @@ static void sub_rows(hawkes_plan p, const double *z, const double *off, double *
     p->epoch += 1;  // p->lam is overwritten below
     if (with_theta)
         hipLaunchKernelGGL(k_sub_theta, dim3((unsigned)(s->mpad / 256)), dim3(256), 0, stream, z, off, s->slot,
-                           s->cidx, s->m, s->pos, p->ts, p->xi, p->yi, kc, s->tv, s->sxy, s->sts, s->qwide, s->qstep,
+                           s->cidx, s->m, s->pos, p->ts, p->xs, p->ys, kc, s->tv, s->sxy, s->sts, s->qwide, s->qstep,
                            theta_full);
-    hipLaunchKernelGGL(k_sub_row, dim3(s->n_ritems), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, p->g, s->pos,
+    hipLaunchKernelGGL(k_sub_row, dim3(s->n_ritems), dim3(HK_WAVE), 0, stream, p->ts, p->xs, p->ys, p->g, s->pos,
                        s->tv, s->sxy, s->sts, s->qwide, s->qstep, s->ritems, kc, s->xpart);
     hipLaunchKernelGGL(k_sub_fin, dim3(p->nchunks), dim3(SUB_ROWFIN_WAVES * HK_WAVE), 0, stream, s->lam_static,
                        s->ritem0, s->rnseg,
@@ -1044,7 +1044,7 @@ static void sub_cols(hawkes_plan p, bool with_h, const PairConst &kc, const FinC
                      hipStream_t stream) {
     hk_subset *s = p->sub;
 #define HK_SUBCOL(H, D)                                                                                        \
-    hipLaunchKernelGGL((k_sub_col<H, D>), dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xi, p->yi, s->lw, \
+    hipLaunchKernelGGL((k_sub_col<H, D>), dim3(s->n_items), dim3(HK_WAVE), 0, stream, p->ts, p->xs, p->ys, s->lw, \
                        p->g, s->pos, s->sxy, s->sts, s->m, s->items, kc, s->colG)
     if (with_h) {
         if (kc.dot) HK_SUBCOL(true, true);

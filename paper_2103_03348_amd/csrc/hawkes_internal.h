@@ -85,14 +85,13 @@ struct hawkes_plan_s {
     int nchunks;     // npad / HK_WAVE
     double t0;       // window start
     double t1;       // max t
-    double cx, cy;   // fixed-point centre
+    double cx, cy;   // centre of the bounding box
     double xmin, xmax, ymin, ymax;  // bounding box of the locations
-    int fxk;         // x_fixed = rint((x - cx) * 2^fxk)
     int device;
 
     // sorted, padded structure-of-arrays (device)
     double *ts;      // [npad] sorted times; padding = t1 + HK_PAD_DT
-    int *xi, *yi;    // [npad] fixed-point coordinates
+    double *xs, *ys; // [npad] coordinates relative to the centre (x - cx, y - cy)
     int *perm;       // [n] sorted position -> caller index
     int *g;          // [npad] first sorted index with the same time (ties)
 
@@ -157,9 +156,8 @@ int *hk_subset_grid_ptr(hawkes_plan p);
 // Exponent constants of the pair kernels (log2 units) and the FP64 constants of
 // the finalisation; built per call from the hyperparameters.
 struct PairConst {
-    // With k the coordinates' fixed-point scale (2^k units per unit length),
-    // kbx = -2^{-2k} / (2 tau_x^2 ln 2) and kex = -2^{-2k} / (2 h^2 ln 2) map a
-    // fixed-point squared distance to the log2 exponents a_b and a_e.
+    // kbx = -1 / (2 tau_x^2 ln 2) and kex = -1 / (2 h^2 ln 2) map a squared
+    // distance to the log2 exponents a_b and a_e.
     // The row pass takes times scaled by st = 1 / (tau_t sqrt(2 ln 2)), so the
     // background's time exponent is exactly -dt'^2 (no rounded constant).
     double st;
@@ -174,7 +172,7 @@ struct PairConst {
     double kw_s;   // kw_d / st: the same per scaled time unit (the row pass's precise form)
     double rex_x;  // kex / kbx exact in FP64 (the row pass's precise form, log-likelihood-only mode)
     double span_max;   // row pass: the fast form's largest chunk time span
-    double sx;     // sqrt(-kex): fixed-point coordinate -> coordinate whose squared distance is -a_e
+    double sx;     // sqrt(-kex): coordinate -> scaled coordinate whose squared distance is -a_e
     double sbx;    // sqrt(-kbx): the same for the background exponent a_b
     double dt_cut;     // row pass: time gap past which both terms are below 2^-160 (INFINITY: no cutoff)
     double dt_cut_ex;  // column pass: the same for the excitation term alone

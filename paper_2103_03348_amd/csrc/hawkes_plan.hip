@@ -1,4 +1,4 @@
-// Plan construction: stable time sort on the device, fixed-point locations,
+// Plan construction: stable time sort on the device, centred FP64 locations,
 // tie groups, and the tile schedules of the two pair passes.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -72,20 +72,20 @@ __global__ void k_bitonic_step(double *__restrict__ key, int *__restrict__ idx, 
 // ---- sorted structure-of-arrays --------------------------------------------------
 __global__ void k_build_soa(const double *__restrict__ key, const int *__restrict__ idx,
                             const double *__restrict__ xy, int64_t n, int64_t npad, double t1,
-                            double cx, double cy, double scale, double *__restrict__ ts,
-                            int *__restrict__ xi, int *__restrict__ yi, int *__restrict__ perm) {
+                            double cx, double cy, double *__restrict__ ts,
+                            double *__restrict__ xs, double *__restrict__ ys, int *__restrict__ perm) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= npad) return;
     if (i < n) {
         int src = idx[i];
         perm[i] = src;
         ts[i] = key[i];
-        xi[i] = (int)llrint((xy[2 * (int64_t)src] - cx) * scale);
-        yi[i] = (int)llrint((xy[2 * (int64_t)src + 1] - cy) * scale);
+        xs[i] = xy[2 * (int64_t)src] - cx;
+        ys[i] = xy[2 * (int64_t)src + 1] - cy;
     } else {
         ts[i] = t1 + HK_PAD_DT;
-        xi[i] = 0;
-        yi[i] = 0;
+        xs[i] = 0.0;
+        ys[i] = 0.0;
     }
 }
 
@@ -150,7 +150,7 @@ void free_plan(hawkes_plan p) {
     hk_prof_free(p);
     hk_subset_free(p);
     hk_tree_free(p);
-    void *ptrs[] = {p->ts, p->xi, p->yi, p->perm, p->g, p->row_items, p->row_block0, p->row_item0, p->row_nseg,
+    void *ptrs[] = {p->ts, p->xs, p->ys, p->perm, p->g, p->row_items, p->row_block0, p->row_item0, p->row_nseg,
                     p->colpart_off, p->col_items, p->col_block0, p->col_item0, p->col_nseg, p->theta_s, p->theta_v, p->chunk_precise, p->tstep, p->lw, p->rowpart,
                     p->colpart, p->lam, p->a, p->colG, p->blockpart, p->status};
     for (void *q : ptrs)
@@ -264,15 +264,6 @@ extern "C" hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const d
     p->ymax = ymax;
     p->cx = 0.5 * (xmin + xmax);
     p->cy = 0.5 * (ymin + ymax);
-    double half = fmax(fmax(xmax - p->cx, ymax - p->cy), 0.0);
-    // largest power of two keeping every |fixed coordinate| below 2^30, so that
-    // every difference of two coordinates fits in int32
-    int k = 40;
-    if (half > 0) k = (int)floor(log2((1073741823.0 - 2.0) / half));
-    k = std::min(k, 40);
-    k = std::max(k, -60);
-    while (k > -60 && half * ldexp(1.0, k) >= 1073741822.0) --k;
-    p->fxk = k;
 
     // stable sort by time
     int64_t n2 = 1;
@@ -290,15 +281,15 @@ extern "C" hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const d
 
     const int64_t npad = p->npad;
     PC(dalloc(&p->ts, npad));
-    PC(dalloc(&p->xi, npad));
-    PC(dalloc(&p->yi, npad));
+    PC(dalloc(&p->xs, npad));
+    PC(dalloc(&p->ys, npad));
     PC(dalloc(&p->perm, n));
     PC(dalloc(&p->g, npad));
     {
         int thr = 256;
         unsigned blocks = (unsigned)((npad + thr - 1) / thr);
         hipLaunchKernelGGL(k_build_soa, dim3(blocks), dim3(thr), 0, stream, d_key, d_idx, d_xy, n, npad, p->t1,
-                           p->cx, p->cy, ldexp(1.0, p->fxk), p->ts, p->xi, p->yi, p->perm);
+                           p->cx, p->cy, p->ts, p->xs, p->ys, p->perm);
         PC(hipGetLastError());
         int nb = (int)((npad + 1023) / 1024);
         int *d_bmax = nullptr;

@@ -88,6 +88,27 @@ def test_sparse_fallback(gpu, n, seed, per_event):
     assert e["h_rel_all"] < 1e-6
 
 
+@pytest.mark.parametrize("shift", [800.0, 3000.0])
+def test_wide_domain_difference_form(gpu, shift):
+    """A domain thousands of bandwidths wide.  The column passes expand
+    -|u_i - u_j|^2 as 2 u_i.u_j - |u_i|^2 - |u_j|^2 only while every |u|^2 is
+    small enough for the cancellation to be harmless (|u| <= 512 with
+    u = x / (h sqrt(2 ln 2)), i.e. half the domain's side at most ~603 h);
+    here they form the differences.  Half of the events are moved `shift`
+    units away, so that the half side W is about 1,400 h and 5,000 h: the
+    coordinates must keep their FP64 resolution (a term's relative error from
+    rounding them to a grid of spacing W 2^-30 would be ~(d/h)(W/h) 2^-31)."""
+    base = synth.small(1500, seed=41)
+    rng = np.random.default_rng(41)
+    far = rng.random(base.n) < 0.5
+    x = base.x + np.where(far, shift, 0.0)
+    es = synth.EventSet(base.t, x, base.y, base.theta, base.subset, base.z, base.hyper, base.t0, "wide")
+    half = 0.5 * max(np.ptp(es.x), np.ptp(es.y))
+    h = es.hyper[5]
+    assert half > 512.0 * np.sqrt(2.0 * np.log(2.0)) * h
+    _check(es, run_gpu(es), oracle.evaluate_es(es), tiny=True)
+
+
 def test_workload_n1000(gpu):
     es = synth.config(0)
     _check(es, run_gpu(es), oracle.evaluate_es(es))
@@ -185,12 +206,18 @@ def test_permutation_invariance(gpu):
     # tied events keep the caller's order, so a permutation can reorder ties and
     # with them the FP32 summation order: equal to rounding, not bitwise
     assert b["loglik"] == pytest.approx(a["loglik"], rel=1e-11)
-    np.testing.assert_allclose(b["grad_theta"], a["grad_theta"][perm], rtol=1e-6, atol=1e-9)
+    # Eq. 4 is a difference of two positive terms: held, as in the oracle
+    # comparisons, relative to their magnitude (an entry where they nearly cancel
+    # moves by an FP32 rounding of the terms, not of the difference)
+    theta0, omega = es.hyper[3], es.hyper[4]
+    a_int = theta0 * (1.0 - np.exp(-omega * (es.t.max() - es.t)))
+    g_scale = np.maximum(a_int + (a["grad_theta"] + a_int), 1e-300)
+    assert np.max(np.abs(b["grad_theta"] - a["grad_theta"][perm]) / g_scale[perm]) < 1e-6
     np.testing.assert_allclose(b["negH_theta"], a["negH_theta"][perm], rtol=1e-6, atol=1e-12)
 
 
 def test_exact_power_of_two_rescaling(gpu):
-    """x, tau_x, h doubled: the fixed-point coordinates and every FP32 exponent
+    """x, tau_x, h doubled: the pre-scaled coordinates and every FP32 exponent
     argument are bit-identical, so loglik drops by exactly 2 N ln 2 (to FP64 rounding)."""
     es = synth.small(1500, seed=14)
     mu0, tau_x, tau_t, theta0, omega, h = es.hyper
