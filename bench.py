@@ -50,16 +50,16 @@ PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Counters of one k_row launch at N = 23,422 (summary and commands in
 # profiles/k_row_k_col_N23422_counters.md): HBM traffic from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a device-to-device copy of known size,
-# 6.2 MB read + 64.7 MB written; v_exp_f32 executed per pair from
+# 8.1 MB read + 64.7 MB written; v_exp_f32 executed per pair from
 # SQ_INSTS_VALU_TRANS_F32 (2.03: the masked diagonal sweeps evaluate some
 # terms they discard).  They hold only for the kernel sources they were
 # measured on, so they are reported only while these hashes match.
-K_ROW_TRAFFIC_BYTES = (3041.5 * 2.0 + 63220.0 * 1.0) * 1024
+K_ROW_TRAFFIC_BYTES = (3943.7 * 2.0 + 63220.0 * 1.0) * 1024
 K_ROW_TRANS_PER_PAIR = 2.03
 K_ROW_TRAFFIC_SOURCES = {
-    "paper_2103_03348_amd/csrc/hawkes_eval.hip": "43f42afbc79b9871424cb7fe10315504a8f15b0182426ed865511c3f635376d9",
-    "paper_2103_03348_amd/csrc/hawkes_internal.h": "9ab2ecc1fe0cd3b46f406e21574357466a800c182c1a698d4ff675d782a8db8f",
-    "paper_2103_03348_amd/csrc/hawkes_plan.hip": "37d284359db290dc76b08a929904c571c6d6f0f1b42c63d87c34b2ff657fa368",
+    "paper_2103_03348_amd/csrc/hawkes_eval.hip": "7b256665dec6dbeea54e46582b6ed50bf92e6b84d2543605001dc8d3373cbb8e",
+    "paper_2103_03348_amd/csrc/hawkes_internal.h": "481be664cd027540911936b0a54c59c7f3efc41066975e2a2e3dfd04f7647cb1",
+    "paper_2103_03348_amd/csrc/hawkes_plan.hip": "a2bb34e425f3a916c5b437beb86a4ff6cdd3e36fe9423c030d7ea98864abe899",
 }
 
 
