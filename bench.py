@@ -146,6 +146,10 @@ def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_
     tt0 = time.perf_counter()
     plan = Plan(t, xy, es.t0)
     pilot = HmcSampler(plan, theta0, idx, es.hyper, sigma_z=sigma_z, L=L, seed=seed)
+    # a first short run loads the torch kernels of the sampling loop (the accept
+    # sum and the draw copy), about 60 ms once per process, which would
+    # otherwise land in the first timed chain
+    pilot.run(2, 0, eps0=0.05, mass="exact", refresh=refresh)
     r = pilot.run(0, warmup, eps0=0.05, mass="exact", refresh=refresh, record=False)
     pre = LearnedPreconditioner(pilot, t, xy, seed=seed)
     X, T = pre.collect(n_states, r["eps"], thin=2)
@@ -215,9 +219,10 @@ def bench_hmc(es, n_iter=2000, warmup=500, L=20, refresh=50, exact_every=500, n_
     return out
 
 
-def hmc_trace(es, iters, L=20, seed=3):
-    """K exact-mass HMC iterations (after 5 warm-up ones) on the free rates of
-    `es`: the time per iteration, for a kernel-trace profile of hmc_step."""
+def hmc_trace(es, iters, L=20, seed=3, warmup=200):
+    """K exact-mass HMC iterations (after `warmup` ones, during which the GPU's
+    clocks settle) on the free rates of `es`: the time per iteration, for a
+    kernel-trace profile of hmc_step."""
     import numpy as np
     import torch
 
@@ -230,7 +235,10 @@ def hmc_trace(es, iters, L=20, seed=3):
     plan = Plan(t, xy, es.t0)
     smp = HmcSampler(plan, torch.as_tensor(es.theta, device=dev), torch.as_tensor(es.subset, device=dev), es.hyper,
                      sigma_z=0.5, L=L, seed=seed)
-    r = smp.run(iters, 5, eps0=0.2, mass="exact", refresh=50)
+    # a first short run loads the torch kernels of the timed loop (the accept
+    # sum and the draw copy): about 60 ms, once per process
+    smp.run(5, 0, eps0=0.2, mass="exact", refresh=50)
+    r = smp.run(iters, warmup, eps0=0.2, mass="exact", refresh=50)
     plan.close()
     return {"hmc_trace": {"n_events": es.n, "free_rates": int(es.subset.shape[0]), "leapfrog": L, "iterations": iters,
                           "ms_per_iteration": 1e3 * r["seconds"] / iters, "accept": r["accept"]}}
