@@ -8,8 +8,9 @@
 //   k_row      row pass over causal tile pairs: for each row i the background
 //              moments over j < i and the excitation moments over t_j < t_i;
 //              the background is symmetric, so each pair also adds its
-//              background moments to column j through accumulators that rotate
-//              one lane per step around the wavefront (DPP wave_rol)
+//              background terms to column j: the FP32 moments through
+//              accumulators that rotate one lane per step around the wavefront
+//              (DPP wave_rol), the FP64 sum through an LDS add per pair
 //   k_fin      per event: partial sums -> lambda_i (FP64), log lambda_i,
 //              w_i = c_e / lambda_i staged for the column pass, integral term
 //              (App. A), hyperparameter terms; fixed-order block reduction
@@ -180,13 +181,15 @@ __device__ __forceinline__ float exp2_split(double e) {
 // (background row sum B0, background column sum, excitation X0) accumulate
 // every term in FP64: a plain FP32 sum of positive terms rounds away every term
 // below half an ulp of the running sum, which biases lambda low (by ~2e-8
-// relative on clustered data).  The moments used only by derivatives stay in
-// FP32 blocks.
+// relative on clustered data).  The column sum goes through LDS: at step s lane
+// l adds its term to its wavefront's slot l + s (column (l + s) mod 64 owns
+// slots k and k + 64), one slot per lane and instruction and the wavefront's
+// instructions in order, so the order of every sum is fixed.  The moments used
+// only by derivatives stay in FP32 blocks.
 //
 // The spatial exponent of the background is formed in FP64 from coordinates
-// pre-scaled by sqrt(-kbx) (two subtractions, a product and an FMA); the fast
-// form rounds it once to FP32, which costs fewer instructions than integer
-// differences converted to FP32 and scaled and carries no rounded FP32 scale.
+// pre-scaled by sqrt(-kbx) (two subtractions, a product and an FMA) and the
+// fast form rounds it once to FP32, so it carries no rounded FP32 scale.
 // The excitation's spatial exponent is that value times the ratio kex / kbx.
 //
 // Constants: times enter scaled by st = 1 / (tau_t sqrt(2 ln 2)) (in FP64,
