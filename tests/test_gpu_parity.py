@@ -262,6 +262,22 @@ def test_loglik_only_n23422(gpu):
     assert np.max(np.abs(g["lam"] - ref["lam"]) / ref["lam"]) < 2e-6
 
 
+@pytest.mark.parametrize("n,seed,per_event", [(700, 32, 3.0), (2000, 33, 1.2)])
+def test_loglik_only_sparse(gpu, n, seed, per_event):
+    """The log-likelihood-only row pass on sparse data, where chunks take the
+    precise form (FP64 time differences, whole exponents with the exact
+    excitation ratio kex / kbx in FP64): lambda to the same bound, loglik to
+    the per-event bound of small sets."""
+    es = synth.small(n, seed=seed, t_end=per_event * n, ties=2)
+    g = run_gpu(es, want_all=False)
+    ref = oracle.evaluate_es(es, want=("loglik", "lam", "Lam_n"))
+    lam_rel = np.max(np.abs(g["lam"] - ref["lam"]) / ref["lam"])
+    print(f"\nloglik-only sparse n={es.n}: dl {abs(g['loglik'] - ref['loglik']):.3e} lam {lam_rel:.3e}")
+    assert g["status"] == 0
+    assert abs(g["loglik"] - ref["loglik"]) <= 2e-6 * es.n
+    assert lam_rel < 2e-6
+
+
 @pytest.mark.parametrize("cfg", [1, 4])
 def test_underflow_cutoff_changes_nothing(gpu, cfg):
     """The optional cutoff skips pair blocks whose terms are all below 2^-160;
