@@ -241,6 +241,7 @@ def hmc_trace(es, iters, L=20, seed=3, warmup=200):
     r = smp.run(iters, warmup, eps0=0.2, mass="exact", refresh=50)
     plan.close()
     return {"hmc_trace": {"n_events": es.n, "free_rates": int(es.subset.shape[0]), "leapfrog": L, "iterations": iters,
+                          "warmup": warmup,
                           "ms_per_iteration": 1e3 * r["seconds"] / iters, "accept": r["accept"]}}
 
 
@@ -363,6 +364,8 @@ def main():
     ap.add_argument("--hmc-iters", type=int, default=2000)
     ap.add_argument("--hmc-trace", type=int, default=0, metavar="K",
                     help="only run K exact-mass HMC iterations on the N=23,422 workload (for a kernel trace)")
+    ap.add_argument("--hmc-trace-warmup", type=int, default=200, metavar="W",
+                    help="warm-up iterations before the K timed ones of --hmc-trace")
     ap.add_argument("--no-larger", action="store_true", help="skip the N=100,000 and 250,000 evaluations")
     ap.add_argument("--no-hmc-large", action="store_true",
                     help="skip the HMC iteration timing on the N=250,000 workload")
@@ -387,7 +390,7 @@ def main():
     from paper_2103_03348_amd.hawkes import Plan
 
     if args.hmc_trace > 0:
-        print(json.dumps(hmc_trace(synth.config(3), args.hmc_trace)))
+        print(json.dumps(hmc_trace(synth.config(3), args.hmc_trace, warmup=args.hmc_trace_warmup)))
         return
 
     dev = torch.device("cuda:0")
