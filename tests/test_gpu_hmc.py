@@ -101,6 +101,10 @@ def test_subset_rejects_bad_indices(gpu):
         idx = torch.as_tensor(bad, dtype=torch.int64, device="cuda:0")
         code = _lib.lib().hawkes_plan_set_subset(plan.handle, idx.numel(), _lib.ptr(idx), _lib.stream_handle())
         assert code == _lib.E_INVALID, (bad, code)
+    # an empty subset, and one larger than the event set
+    idx = torch.arange(301, dtype=torch.int64, device="cuda:0")
+    assert _lib.lib().hawkes_plan_set_subset(plan.handle, 0, _lib.ptr(idx), _lib.stream_handle()) == _lib.E_INVALID
+    assert _lib.lib().hawkes_plan_set_subset(plan.handle, 301, _lib.ptr(idx), _lib.stream_handle()) == _lib.E_INVALID
     idx = torch.as_tensor(es.subset, dtype=torch.int64, device="cuda:0")
     _lib.check(_lib.lib().hawkes_plan_set_subset(plan.handle, idx.numel(), _lib.ptr(idx), _lib.stream_handle()),
                "set_subset")

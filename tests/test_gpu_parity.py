@@ -149,6 +149,17 @@ def test_invalid_arguments(gpu):
         plan.eval(th, (0.7, -2.0, 5.0, 0.3, 0.5, 0.3))
     with pytest.raises(_lib.HawkesError):
         Plan.from_numpy(es.t, es.x, es.y, t_start=es.t.min() + 1.0)
+    # an empty event set and non-finite inputs are argument errors
+    with pytest.raises(_lib.HawkesError):
+        Plan.from_numpy(np.zeros(0), np.zeros(0), np.zeros(0), 0.0)
+    x_nan = es.x.copy()
+    x_nan[7] = np.nan
+    with pytest.raises(_lib.HawkesError):
+        Plan.from_numpy(es.t, x_nan, es.y, 0.0)
+    t_inf = es.t.copy()
+    t_inf[11] = np.inf
+    with pytest.raises(_lib.HawkesError):
+        Plan.from_numpy(t_inf, es.x, es.y, 0.0)
     bad = th.clone()
     bad[3] = -1.0
     plan.eval(bad, es.hyper)
