@@ -339,3 +339,31 @@ def test_underflow_cutoff_matches_oracle(gpu, case):
     g["status"] = plan.status()
     plan.close()
     _check(es, g, oracle.evaluate_es(es))
+
+
+@pytest.mark.parametrize("case", ["n23422", "sparse"])
+def test_underflow_cutoff_loglik_only_matches_oracle(gpu, case):
+    """The log-likelihood-only row pass (the Metropolis proposals' evaluation)
+    with the cutoff on, against the oracle: loglik and lambda."""
+    import torch
+
+    from paper_2103_03348_amd.hawkes import Plan
+
+    es = synth.config(1) if case == "n23422" else synth.small(3000, seed=35, t_end=3000.0, ties=3)
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
+    plan.set_cutoff(True)
+    th = torch.as_tensor(es.theta, device="cuda:0")
+    out = plan.eval(th, es.hyper, loglik=True)
+    lam = plan.lam().cpu().numpy()
+    ll = float(out["loglik"].item())
+    st = plan.status()
+    plan.close()
+    ref = oracle.evaluate_es(es, want=("loglik", "lam", "Lam_n"))
+    lam_rel = np.max(np.abs(lam - ref["lam"]) / ref["lam"])
+    print(f"\ncutoff loglik-only {case}: dl {abs(ll - ref['loglik']):.3e} lam {lam_rel:.3e}")
+    assert st == 0
+    if case == "n23422":
+        assert abs(ll - ref["loglik"]) / abs(ref["loglik"]) < 1e-9
+    else:
+        assert abs(ll - ref["loglik"]) <= 2e-6 * es.n
+    assert lam_rel < 2e-6
