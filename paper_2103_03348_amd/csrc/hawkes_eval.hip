@@ -749,6 +749,11 @@ __global__ __launch_bounds__(HK_NSUM * HK_TOT_LANES) void k_fin2(const double *_
 // error in the exponent's absolute value would become a relative error of the
 // term that grows with |e_ij|.
 //
+// Eq. 4 alone (no Hessian) splits the row's weight instead: n_i =
+// rint(lw_i) is applied exactly and the rest of the exponent, small for the
+// terms that make up G_j, is rounded once to FP32 (relative error about 2^-24
+// ln2 |e_ij - n_i| per term, larger only for terms negligible in the sum).
+//
 // The exponent is split into a row part (staged), a column part (per lane)
 // and the cross term.  With DOT the spatial part is expanded,
 //   -|u_i - u_j|^2 = 2 u_i . u_j - |u_i|^2 - |u_j|^2   (u = s x),
@@ -759,7 +764,8 @@ __global__ __launch_bounds__(HK_NSUM * HK_TOT_LANES) void k_fin2(const double *_
 // the pairs whose terms are not negligible.
 struct ColRow {     // one staged row
     double2 u;      // DOT: 2 u_i; else u_i
-    double c;       // lw_i + kw (t_i - T_ref) (DOT: minus |u_i|^2), at least HK_EXP_FLOOR
+    double c;       // lw_i + kw (t_i - T_ref) (DOT: minus |u_i|^2), at least HK_EXP_FLOOR; Eq. 4 alone: minus n
+    int n;          // Eq. 4 alone: rint(lw_i) (0 for a row at the floor), applied exactly
 };
 
 template <bool DOT>
@@ -770,10 +776,11 @@ __device__ __forceinline__ double col_exponent(const ColRow &r, double xj, doubl
 }
 
 
-template <bool MASKED, bool DOT>
+template <bool WITH_H, bool MASKED, bool DOT>
 __device__ __forceinline__ float col_term(const ColRow *__restrict__ rows, const int *__restrict__ rg, int s,
                                           int jcol, double xj, double yj, double dj) {
-    float T = exp2_split(col_exponent<DOT>(rows[s], xj, yj, dj));
+    const double e = col_exponent<DOT>(rows[s], xj, yj, dj);
+    float T = WITH_H ? exp2_split(e) : __builtin_amdgcn_ldexpf(fexp2((float)e), rows[s].n);
     if (MASKED) {
         if (!(jcol < rg[s])) T = 0.0f;
     }
@@ -796,8 +803,8 @@ __device__ __forceinline__ void col_sweep(const ColRow *__restrict__ rows, const
     float G1 = 0.0f, H1 = 0.0f;
 #pragma unroll kColUnroll
     for (int s = 0; s < HK_WAVE; s += 2) {
-        const float e0 = col_term<MASKED, DOT>(rows, rg, s, jcol, xj, yj, dj);
-        const float e1 = col_term<MASKED, DOT>(rows, rg, s + 1, jcol, xj, yj, dj);
+        const float e0 = col_term<WITH_H, MASKED, DOT>(rows, rg, s, jcol, xj, yj, dj);
+        const float e1 = col_term<WITH_H, MASKED, DOT>(rows, rg, s + 1, jcol, xj, yj, dj);
         G += e0;
         G1 += e1;
         if (WITH_H) {
@@ -846,7 +853,8 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
             if (tid < HK_WAVE) {
                 const int64_t i = (int64_t)c * HK_WAVE + tid;
                 const double ux = xs[i] * kc.sx, uy = ys[i] * kc.sx;
-                double cr = lw[i] + kc.kw_d * (ts[i] - t_ref);
+                const double lwi = lw[i];
+                double cr = lwi + kc.kw_d * (ts[i] - t_ref);
                 ColRow r;
                 if (DOT) {
                     cr -= fma(ux, ux, uy * uy);
@@ -855,6 +863,12 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
                     r.u = make_double2(ux, uy);
                 }
                 r.c = fmax(cr, HK_EXP_FLOOR);
+                r.n = 0;
+                if (!WITH_H && lwi > HK_EXP_FLOOR) {
+                    const double nw = rint(lwi);
+                    r.n = (int)nw;
+                    r.c -= nw;
+                }
                 rows[tid] = r;
                 rg[tid] = g[i];
             }

@@ -479,13 +479,21 @@ __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const do
 }
 
 // Column pass on the subset: lanes own subset entries (time order), rows are
-// all events after them, broadcast from LDS.  Same arithmetic as the full
-// column pass: each term c_e E_ik / lambda_i is the exponential of its whole
-// exponent, log2(c_e / lambda_i) - omega (t_i - t_k) / ln2 - |s (x_i - x_k)|^2,
-// formed in FP64 and split into an exact power of two and an FP32 fraction.
+// all events after them, broadcast from LDS.  Each term c_e E_ik / lambda_i is
+// the exponential of its whole exponent,
+//   e_ik = log2(c_e / lambda_i) - omega (t_i - t_k) / ln2 - |s (x_i - x_k)|^2,
+// formed in FP64.  With Eq. 5 (WITH_H) the exponent is split into an exact
+// power of two and an FP32 fraction, as in the full column pass: Eq. 5 squares
+// the terms and its small entries are sums of terms with large |e|.  For
+// Eq. 4 alone the row's weight is split instead: n_i = rint(log2(c_e /
+// lambda_i)) is applied exactly (ldexp) and the rest of the exponent, which is
+// small for the terms that make up G_k, is rounded once to FP32 (relative
+// error about 2^-24 ln2 |e_ik - n_i| per term: far below Eq. 4's bound for the
+// terms that carry the sum, larger only for terms that are negligible in it).
 struct SubColRow {  // one staged row
     double2 u;      // DOT: 2 u_i; else u_i (u = s x)
-    double c;       // lw_i + kw (t_i - T_ref) (DOT: minus |u_i|^2), at least HK_EXP_FLOOR
+    double c;       // lw_i + kw (t_i - T_ref) (DOT: minus |u_i|^2), at least HK_EXP_FLOOR; Eq. 4 alone: minus n
+    int n;          // Eq. 4 alone: rint(lw_i) (0 for a row at the floor), applied exactly
 };
 
 __device__ __forceinline__ float sub_exp2_split(double e) {
@@ -506,7 +514,7 @@ __device__ __forceinline__ void sub_col_sweep(const SubColRow *__restrict__ rows
             const double dx = r.u.x - xk, dy = r.u.y - yk;
             e = fma(-dx, dx, fma(-dy, dy, r.c + dk));
         }
-        float T = sub_exp2_split(e);
+        float T = WITH_H ? sub_exp2_split(e) : __builtin_amdgcn_ldexpf(fexp2((float)e), r.n);
         if (MASKED && !(pj < rg[s])) T = 0.0f;
         G += T;
         if (WITH_H) H = fmaf(T, T, H);
@@ -577,6 +585,14 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
                 w.u = make_double2(ux, uy);
             }
             w.c = fmax(cr, HK_EXP_FLOOR);
+            w.n = 0;
+            // a row whose weight is at the floor (zero weight, padding) keeps its
+            // whole exponent in c, which then stays at the floor
+            if (!WITH_H && pl > HK_EXP_FLOOR) {
+                const double nw = rint(pl);
+                w.n = (int)nw;
+                w.c -= nw;
+            }
             rows[lane] = w;
             rg[lane] = pg;
         }
