@@ -317,11 +317,15 @@ hawkes_status hawkes_mlp_train_step_noalloc(float *d_params, float *d_adam_m, fl
  *   0..2  log1p(#{e != m : r2_e < r^2}) for r = h, 3h, tau_x (events in a disc)
  *   3..5  r = h: log1p of the events in the disc with -1/omega <= dt_e < 0,
  *         with 0 < dt_e <= 1/omega, and with 0 < dt_e <= 3/omega
- *   6..8  the same for r = 3h
+ *   6, 7  the first two for r = 3h
+ *   8     max(log2 S_m, -32) / 8, S_m = sum over r2_e < (3h)^2,
+ *         0 < dt_e <= 6/omega of exp(-2 omega dt_e - r2_e / h^2): Eq. 5's
+ *         H_m without the weights c_e / lambda_e
  *   9     z_k;  10  #{e : t_e < t_k} / N;  11  (T1 - t_k) / (T1 - T0)
  * Counts are exact: a grid of cells of size 3h (origin (gx0, gy0) <= the
  * minimum coordinates) only enumerates the candidates, each tested by its
- * FP64 distance.  d_t, d_xy are the arrays the plan was built from.
+ * FP64 distance.  S_m is summed in 64-bit fixed point relative to its largest
+ * term, so it does not depend on the candidates' order.  d_t, d_xy are the arrays the plan was built from.
  * HAWKES_E_UNSUPPORTED if the grid would exceed 2^26 cells.  Uses a workspace
  * of the plan's subset (grown on demand; a growth synchronises `stream`). */
 hawkes_status hawkes_features(hawkes_plan p, const hawkes_hyper *hyper, const double *d_t, const double *d_xy,

@@ -53,6 +53,9 @@
 // capacity on the long tail of such entries (log H reaches -70 on the
 // clustered workloads) that the mass does not feel.
 #define HK_LOGH_FLOOR 1.0e-6
+// Floor of the learned preconditioner's kernel-sum feature, log2 S_m (a sum
+// below 2^-32 of a unit term says only that no later event is near).
+#define HK_KSUM_LOG2_FLOOR (-32.0)
 
 // Time offset given to padding events: their pair terms underflow to exactly
 // zero while every square stays finite in FP32.

@@ -272,6 +272,16 @@ __global__ void k_cell_scatter(const double *__restrict__ t, const double *__res
 // One wavefront per free event: the lanes split the candidates of the cells a
 // disc of radius tau_x touches, count, and the counts are summed across the
 // wavefront (integers: exact in any order).
+//
+// Feature 8 is the forward sum of the squared excitation kernel,
+//   S_m = sum over e with r2_e < (3h)^2, 0 < dt_e <= 6/omega of
+//         exp(a_e),  a_e = -2 omega dt_e - r2_e / h^2,
+// which is Eq. 5's H_m without the weights c_e / lambda_e: as
+// max(log2 S_m, HK_KSUM_LOG2_FLOOR) / 8.  The candidates' order in the cells
+// depends on the grid's scatter, so the sum is formed in a way that does not
+// depend on it: the largest exponent a_max (a maximum is exact) and then
+// sum_e rint(2^36 exp(a_e - a_max)) in 64-bit integers (exact up to 2^27
+// terms), each exponential by the FP32 exp2 (a feature needs no more).
 __global__ __launch_bounds__(256) void k_features(const double *__restrict__ t, const double *__restrict__ xy,
                                                   const int64_t *__restrict__ cidx, const int *__restrict__ pos,
                                                   const int *__restrict__ slot, const int *__restrict__ g,
@@ -288,10 +298,12 @@ __global__ __launch_bounds__(256) void k_features(const double *__restrict__ t, 
     const int64_t e = cidx[k];
     const double xm = xy[2 * e], ym = xy[2 * e + 1], tm = t[e];
     const double r0 = h * h, h3 = 3.0 * h, r1 = h3 * h3, r2c = tau_x * tau_x;
-    const double w1 = 1.0 / omega, w3 = 3.0 / omega;
+    const double w1 = 1.0 / omega, w3 = 3.0 / omega, w6 = 6.0 / omega;
+    const double inv_h2 = 1.0 / (h * h);
     const int x_lo = cell_x(xm - tau_x, G), x_hi = cell_x(xm + tau_x, G);
     const int y_lo = cell_y(ym - tau_x, G), y_hi = cell_y(ym + tau_x, G);
     int c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double amax = -INFINITY;  // largest exponent of feature 8's terms
     for (int yy = y_lo; yy <= y_hi; ++yy) {
         const int64_t row = (int64_t)yy * G.nx;
         for (int q = start[row + x_lo] + lane; q < start[row + x_hi + 1]; q += HK_WAVE) {
@@ -305,7 +317,7 @@ __global__ __launch_bounds__(256) void k_features(const double *__restrict__ t, 
                     c[1] += 1;
                     c[6] += prev;
                     c[7] += next;
-                    c[8] += next3;
+                    if (dt > 0.0 && dt <= w6) amax = fmax(amax, -2.0 * omega * dt - d2 * inv_h2);
                     if (d2 < r0) {
                         c[0] += 1;
                         c[3] += prev;
@@ -317,15 +329,41 @@ __global__ __launch_bounds__(256) void k_features(const double *__restrict__ t, 
         }
     }
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
+    for (int a = 0; a < 8; ++a) {
 #pragma unroll
         for (int off = 1; off < HK_WAVE; off <<= 1) c[a] += __shfl_xor(c[a], off);
+    }
+#pragma unroll
+    for (int off = 1; off < HK_WAVE; off <<= 1) amax = fmax(amax, __shfl_xor(amax, off));
+    // feature 8's terms relative to the largest, in fixed point (2^36 units)
+    long long ksum = 0;
+    if (amax > -INFINITY) {
+        // only the cells the disc of radius 3h touches
+        const int x3_lo = cell_x(xm - h3, G), x3_hi = cell_x(xm + h3, G);
+        const int y3_lo = cell_y(ym - h3, G), y3_hi = cell_y(ym + h3, G);
+        for (int yy = y3_lo; yy <= y3_hi; ++yy) {
+            const int64_t row = (int64_t)yy * G.nx;
+            for (int q = start[row + x3_lo] + lane; q < start[row + x3_hi + 1]; q += HK_WAVE) {
+                const double dx = cx[q] - xm, dy = cy[q] - ym;
+                const double d2 = dx * dx + dy * dy;
+                const double dt = ct[q] - tm;
+                if (d2 < r1 && dt > 0.0 && dt <= w6) {
+                    const double rel = (-2.0 * omega * dt - d2 * inv_h2) - amax;  // <= 0
+                    ksum += llrint((double)exp2f((float)(rel * 1.4426950408889634)) * 68719476736.0);
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < HK_WAVE; off <<= 1) ksum += __shfl_xor(ksum, off);
     }
     if (lane == 0) {
         float f[MLP_IN];
         // the event itself is inside every disc
         for (int a = 0; a < 3; ++a) f[a] = (float)log1p((double)(c[a] - 1));
-        for (int a = 3; a < 9; ++a) f[a] = (float)log1p((double)c[a]);
+        for (int a = 3; a < 8; ++a) f[a] = (float)log1p((double)c[a]);
+        // log2 S_m = log2(ksum) - 36 + a_max / ln 2 (S_m = 0: the floor)
+        const double l2s = ksum > 0 ? log2((double)ksum) - 36.0 + amax * 1.4426950408889634 : -INFINITY;
+        f[8] = (float)(fmax(l2s, HK_KSUM_LOG2_FLOOR) * 0.125);
         f[9] = (float)z[k];
         f[10] = (float)((double)g[pos[r]] / (double)n);
         const double span = t1 - t0;

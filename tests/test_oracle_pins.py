@@ -501,16 +501,57 @@ def test_features_small_hand_case():
     assert F[0, 0] == L(2) and F[0, 1] == L(3) and F[0, 2] == L(4)
     # e0, r = h: no earlier event; later within 2 time units: e1 (dt 0.5), e2 (dt 2.0, closed end)
     assert F[0, 3] == L(0) and F[0, 4] == L(2) and F[0, 5] == L(2)
-    # e0, r = 3h: e4 (dt 6.5) is outside 3/omega = 6
-    assert F[0, 6] == L(0) and F[0, 7] == L(2) and F[0, 8] == L(2)
+    # e0, r = 3h: no earlier event, e1 and e2 within 2 time units
+    assert F[0, 6] == L(0) and F[0, 7] == L(2)
+    # feature 8, the forward squared-kernel sum over r < 3h, 0 < dt <= 12:
+    # e1 (dt 0.5, r^2 0.02), e2 (dt 2.0, r^2 0.0625), e4 (dt 6.5, r^2 0.25), by hand
+    # exp(-0.7222) = 0.485672, exp(-2.6944) = 0.067580, exp(-9.2778) = 0.0000935
+    assert 2.0 ** (8.0 * F[0, 8]) == pytest.approx(0.485672 + 0.067580 + 0.0000935, rel=2e-6)
     # e2: within h: e0, e1; within 3h: + e4; within 2: + e5 (1.52)
     assert F[1, 0] == L(2) and F[1, 1] == L(3) and F[1, 2] == L(4)
     # e2, r = h: earlier within [-2, 0): e1 (dt -1.5); e0 (dt -2.0, closed end) too
     assert F[1, 3] == L(2) and F[1, 4] == L(0) and F[1, 5] == L(0)
-    # e2, r = 3h: later e4 (dt 4.5) only in the 6-unit window; e5 ties (dt 0) and is far
-    assert F[1, 6] == L(2) and F[1, 7] == L(0) and F[1, 8] == L(1)
+    # e2, r = 3h: e0, e1 earlier; no later event within 2 time units
+    assert F[1, 6] == L(2) and F[1, 7] == L(0)
+    # feature 8: e4 alone (dt 4.5, r^2 0.3125); e5 ties (dt 0) and is far, by hand
+    # exp(-4.5 - 3.47222) = 0.000344912
+    assert 2.0 ** (8.0 * F[1, 8]) == pytest.approx(0.000344912, rel=2e-6)
     assert F[1, 9] == -0.2
     assert F[1, 10] == pytest.approx(2 / 6) and F[1, 11] == pytest.approx((7.0 - 2.5) / 7.0)
+
+
+def test_kernel_sum_feature_special_cases():
+    """Feature 8 (forward sum of the squared excitation kernel) in cases with a
+    closed form: one later event at dt = 1/omega and distance h gives
+    exp(-3); no later event gives the floor; the window's ends (dt = 6/omega
+    included, distance 3h excluded); the sum of two neighbours is the sum of
+    their single-neighbour values; and it is invariant to translations and to
+    scaling space with h and time with 1/omega."""
+    import math
+
+    from oracle import features
+    hy = (0.7, 2.0, 5.0, 0.3, 0.5, 0.3)  # omega = 0.5, h = 0.3
+
+    def f8(t, x, y, hyper=hy):
+        return features.features(np.asarray(t, float), np.asarray(x, float), np.asarray(y, float),
+                                 np.array([0]), np.array([0.0]), hyper, 0.0, -1.0, -1.0)[0, 8]
+
+    assert f8([1.0, 3.0], [0.0, 0.3], [0.0, 0.0]) == pytest.approx(-3.0 / math.log(2.0) / 8.0, rel=1e-12)
+    assert f8([1.0, 0.5], [0.0, 0.1], [0.0, 0.0]) == -4.0          # only an earlier event
+    assert f8([1.0, 1.0], [0.0, 0.1], [0.0, 0.0]) == -4.0          # a tie (dt = 0)
+    assert f8([1.0, 13.0], [0.0, 0.0], [0.0, 0.0]) == pytest.approx(-12.0 / math.log(2.0) / 8.0, rel=1e-12)
+    assert f8([1.0, 13.0 + 1e-9], [0.0, 0.0], [0.0, 0.0]) == -4.0  # past 6/omega
+    assert f8([1.0, 2.0], [0.0, 0.9], [0.0, 0.0]) == -4.0          # at 3h: outside
+    a = f8([1.0, 1.7], [0.0, 0.2], [0.0, 0.1])
+    b = f8([1.0, 4.2], [0.0, -0.4], [0.0, 0.3])
+    ab = f8([1.0, 1.7, 4.2], [0.0, 0.2, -0.4], [0.0, 0.1, 0.3])
+    assert 2.0 ** (8.0 * ab) == pytest.approx(2.0 ** (8.0 * a) + 2.0 ** (8.0 * b), rel=1e-12)
+    t, x, y = [1.0, 1.7, 4.2], [0.0, 0.2, -0.4], [0.0, 0.1, 0.3]
+    shifted = f8([v + 10.0 for v in t], [v - 3.0 for v in x], [v + 5.0 for v in y])
+    assert shifted == pytest.approx(ab, abs=1e-12)
+    scaled_hy = (0.7, 4.0, 5.0, 0.3, 0.25, 0.6)  # h doubled, omega halved
+    scaled = f8([2.0 * v for v in t], [2.0 * v for v in x], [2.0 * v for v in y], scaled_hy)
+    assert scaled == pytest.approx(ab, abs=1e-12)
 
 
 def test_ess_of_ar1_chain():
