@@ -314,7 +314,8 @@ hawkes_status hawkes_mlp_train_step_noalloc(float *d_params, float *d_adam_m, fl
                                             hipStream_t stream);
 /* Per-event network inputs for the subset (slot order), d_feat [m][12] FP32.
  * For free event m, with r2_e = (x_e - x_m)^2 + (y_e - y_m)^2 and dt_e = t_e - t_m:
- *   0..2  log1p(#{e != m : r2_e < r^2}) for r = h, 3h, tau_x (events in a disc)
+ *   0, 1  log1p(#{e != m : r2_e < r^2}) for r = h, 3h (events in a disc)
+ *   2     log1p(#{e : r2_e < (3h)^2, 0 < dt_e <= 6/omega}) (later neighbours)
  *   3..5  r = h: log1p of the events in the disc with -1/omega <= dt_e < 0,
  *         with 0 < dt_e <= 1/omega, and with 0 < dt_e <= 3/omega
  *   6, 7  the first two for r = 3h

@@ -3,7 +3,8 @@
 
 For a free event m at (x_m, t_m), with r2_e = (x_e - x_m)^2 + (y_e - y_m)^2 and
 dt_e = t_e - t_m:
-  f0..f2  log1p(#{e != m : r2_e < r^2}) for r = h, 3h, tau_x
+  f0, f1  log1p(#{e != m : r2_e < r^2}) for r = h, 3h
+  f2      log1p(#{e : r2_e < (3h)^2, 0 < dt_e <= 6/omega})  (the terms of f8)
   f3..f5  r = h:  log1p(#{e : r2_e < r^2, -1/omega <= dt_e < 0}),
                   log1p(#{e : r2_e < r^2, 0 < dt_e <= 1/omega}),
                   log1p(#{e : r2_e < r^2, 0 < dt_e <= 3/omega})
@@ -30,7 +31,7 @@ def features(t, x, y, idx, z, hyper, t0, gx0, gy0):
     x = np.asarray(x, np.float64)
     y = np.asarray(y, np.float64)
     idx = np.asarray(idx, np.int64)
-    _, tau_x, _, _, omega, h = [float(v) for v in hyper]
+    _, _, _, _, omega, h = [float(v) for v in hyper]
     n = t.shape[0]
     T1 = float(t.max())
     span = T1 - t0
@@ -43,7 +44,7 @@ def features(t, x, y, idx, z, hyper, t0, gx0, gy0):
         dy = y - y[m]
         r2 = dx * dx + dy * dy
         dt = t - t[m]
-        for c, rad in enumerate((h, 3.0 * h, tau_x)):
+        for c, rad in enumerate((h, 3.0 * h)):
             F[r, c] = np.log1p(np.sum(r2 < rad * rad) - 1)
         for base, rad in ((3, h), (6, 3.0 * h)):
             near = r2 < rad * rad
@@ -52,6 +53,7 @@ def features(t, x, y, idx, z, hyper, t0, gx0, gy0):
             if base == 3:
                 F[r, base + 2] = np.log1p(np.sum(near & (dt > 0.0) & (dt <= w3)))
         sel = (r2 < (3.0 * h) * (3.0 * h)) & (dt > 0.0) & (dt <= w6)
+        F[r, 2] = np.log1p(np.sum(sel))
         s_m = np.sum(np.exp(-2.0 * omega * dt[sel] - r2[sel] / (h * h)))
         F[r, 8] = max(np.log2(s_m) if s_m > 0.0 else -np.inf, -32.0) / 8.0
         F[r, 9] = z[r]

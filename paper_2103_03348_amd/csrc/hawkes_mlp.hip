@@ -194,7 +194,7 @@ __global__ void k_adam(float *__restrict__ params, const double *__restrict__ gr
 // definition: a spatial grid of cells of size 3h over all events (counting
 // sort: per-cell counts, one exclusive scan, a scatter of the events' times
 // and coordinates into cell order) gives each free event the candidates in the
-// cells that a disc of radius tau_x (the largest radius) around it touches;
+// cells that a disc of radius 3h (the largest radius) around it touches;
 // the candidates are then tested exactly.  Distances are dx * dx + dy * dy and
 // radii r * r, each rounded once in FP64 (no contraction), so every count is
 // the same integer as the definition's.
@@ -270,7 +270,7 @@ __global__ void k_cell_scatter(const double *__restrict__ t, const double *__res
 }
 
 // One wavefront per free event: the lanes split the candidates of the cells a
-// disc of radius tau_x touches, count, and the counts are summed across the
+// disc of radius 3h touches, count, and the counts are summed across the
 // wavefront (integers: exact in any order).
 //
 // Feature 8 is the forward sum of the squared excitation kernel,
@@ -297,11 +297,11 @@ __global__ __launch_bounds__(256) void k_features(const double *__restrict__ t, 
     const int k = slot[r];
     const int64_t e = cidx[k];
     const double xm = xy[2 * e], ym = xy[2 * e + 1], tm = t[e];
-    const double r0 = h * h, h3 = 3.0 * h, r1 = h3 * h3, r2c = tau_x * tau_x;
+    const double r0 = h * h, h3 = 3.0 * h, r1 = h3 * h3;
     const double w1 = 1.0 / omega, w3 = 3.0 / omega, w6 = 6.0 / omega;
     const double inv_h2 = 1.0 / (h * h);
-    const int x_lo = cell_x(xm - tau_x, G), x_hi = cell_x(xm + tau_x, G);
-    const int y_lo = cell_y(ym - tau_x, G), y_hi = cell_y(ym + tau_x, G);
+    const int x_lo = cell_x(xm - h3, G), x_hi = cell_x(xm + h3, G);
+    const int y_lo = cell_y(ym - h3, G), y_hi = cell_y(ym + h3, G);
     int c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double amax = -INFINITY;  // largest exponent of feature 8's terms
     for (int yy = y_lo; yy <= y_hi; ++yy) {
@@ -311,19 +311,19 @@ __global__ __launch_bounds__(256) void k_features(const double *__restrict__ t, 
             const double d2 = dx * dx + dy * dy;
             const double dt = ct[q] - tm;
             const bool prev = dt >= -w1 && dt < 0.0, next = dt > 0.0 && dt <= w1, next3 = dt > 0.0 && dt <= w3;
-            if (d2 < r2c) {
-                c[2] += 1;
-                if (d2 < r1) {
-                    c[1] += 1;
-                    c[6] += prev;
-                    c[7] += next;
-                    if (dt > 0.0 && dt <= w6) amax = fmax(amax, -2.0 * omega * dt - d2 * inv_h2);
-                    if (d2 < r0) {
-                        c[0] += 1;
-                        c[3] += prev;
-                        c[4] += next;
-                        c[5] += next3;
-                    }
+            if (d2 < r1) {
+                c[1] += 1;
+                c[6] += prev;
+                c[7] += next;
+                if (dt > 0.0 && dt <= w6) {
+                    c[2] += 1;
+                    amax = fmax(amax, -2.0 * omega * dt - d2 * inv_h2);
+                }
+                if (d2 < r0) {
+                    c[0] += 1;
+                    c[3] += prev;
+                    c[4] += next;
+                    c[5] += next3;
                 }
             }
         }
@@ -338,12 +338,9 @@ __global__ __launch_bounds__(256) void k_features(const double *__restrict__ t, 
     // feature 8's terms relative to the largest, in fixed point (2^36 units)
     long long ksum = 0;
     if (amax > -INFINITY) {
-        // only the cells the disc of radius 3h touches
-        const int x3_lo = cell_x(xm - h3, G), x3_hi = cell_x(xm + h3, G);
-        const int y3_lo = cell_y(ym - h3, G), y3_hi = cell_y(ym + h3, G);
-        for (int yy = y3_lo; yy <= y3_hi; ++yy) {
+        for (int yy = y_lo; yy <= y_hi; ++yy) {
             const int64_t row = (int64_t)yy * G.nx;
-            for (int q = start[row + x3_lo] + lane; q < start[row + x3_hi + 1]; q += HK_WAVE) {
+            for (int q = start[row + x_lo] + lane; q < start[row + x_hi + 1]; q += HK_WAVE) {
                 const double dx = cx[q] - xm, dy = cy[q] - ym;
                 const double d2 = dx * dx + dy * dy;
                 const double dt = ct[q] - tm;
@@ -359,7 +356,8 @@ __global__ __launch_bounds__(256) void k_features(const double *__restrict__ t, 
     if (lane == 0) {
         float f[MLP_IN];
         // the event itself is inside every disc
-        for (int a = 0; a < 3; ++a) f[a] = (float)log1p((double)(c[a] - 1));
+        for (int a = 0; a < 2; ++a) f[a] = (float)log1p((double)(c[a] - 1));
+        f[2] = (float)log1p((double)c[2]);
         for (int a = 3; a < 8; ++a) f[a] = (float)log1p((double)c[a]);
         // log2 S_m = log2(ksum) - 36 + a_max / ln 2 (S_m = 0: the floor)
         const double l2s = ksum > 0 ? log2((double)ksum) - 36.0 + amax * 1.4426950408889634 : -INFINITY;

@@ -497,8 +497,8 @@ def test_features_small_hand_case():
     # distances from e2: e0 0.25, e1 0.180, e3 6.9, e4 0.559, e5 1.52
     F = features.features(t, x, y, np.array([0, 2]), np.array([0.1, -0.2]), hy, 0.0, -1.0, -1.0)
     L = np.log1p
-    # e0: within h = 0.3: e1, e2; within 0.9: + e4; within 2: + e5
-    assert F[0, 0] == L(2) and F[0, 1] == L(3) and F[0, 2] == L(4)
+    # e0: within h = 0.3: e1, e2; within 0.9: + e4; later within 0.9 and 12 time units: e1, e2, e4
+    assert F[0, 0] == L(2) and F[0, 1] == L(3) and F[0, 2] == L(3)
     # e0, r = h: no earlier event; later within 2 time units: e1 (dt 0.5), e2 (dt 2.0, closed end)
     assert F[0, 3] == L(0) and F[0, 4] == L(2) and F[0, 5] == L(2)
     # e0, r = 3h: no earlier event, e1 and e2 within 2 time units
@@ -507,8 +507,8 @@ def test_features_small_hand_case():
     # e1 (dt 0.5, r^2 0.02), e2 (dt 2.0, r^2 0.0625), e4 (dt 6.5, r^2 0.25), by hand
     # exp(-0.7222) = 0.485672, exp(-2.6944) = 0.067580, exp(-9.2778) = 0.0000935
     assert 2.0 ** (8.0 * F[0, 8]) == pytest.approx(0.485672 + 0.067580 + 0.0000935, rel=2e-6)
-    # e2: within h: e0, e1; within 3h: + e4; within 2: + e5 (1.52)
-    assert F[1, 0] == L(2) and F[1, 1] == L(3) and F[1, 2] == L(4)
+    # e2: within h: e0, e1; within 3h: + e4; later within 3h and 12 time units: e4 (e5 ties)
+    assert F[1, 0] == L(2) and F[1, 1] == L(3) and F[1, 2] == L(1)
     # e2, r = h: earlier within [-2, 0): e1 (dt -1.5); e0 (dt -2.0, closed end) too
     assert F[1, 3] == L(2) and F[1, 4] == L(0) and F[1, 5] == L(0)
     # e2, r = 3h: e0, e1 earlier; no later event within 2 time units
