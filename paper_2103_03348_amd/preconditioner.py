@@ -88,8 +88,10 @@ class LearnedPreconditioner:
         X = X.contiguous()
         T = T.contiguous()
         hist = []
+        # every step's batch rows drawn up front and copied once
+        all_rows = torch.as_tensor(rng.integers(0, n, size=(steps, B)).astype(np.int32), device=self.dev)
         for it in range(steps):
-            rows = torch.as_tensor(rng.integers(0, n, size=B).astype(np.int32), device=self.dev)
+            rows = all_rows[it]
             self.step_no += 1
             _lib.check(_lib.lib().hawkes_mlp_train_step(_lib.ptr(self.params), _lib.ptr(self.adam_m),
                                                         _lib.ptr(self.adam_v), self.step_no, ctypes.c_float(lr),
