@@ -103,8 +103,12 @@ int64_t hawkes_plan_size(hawkes_plan p);
  *   d_negH_theta  [n] -d2 loglik / d theta_j^2 (Eq. 5)        -- may be NULL
  *   d_negH_hyper  [6] -d2 loglik / d p^2 for the six hyperparameters -- may be NULL
  * One row pass over the causal pairs always runs (it gives lambda); a column
- * pass runs iff d_grad_theta or d_negH_theta is non-NULL.  When some lambda_i
- * is zero, loglik is -inf and the sticky status becomes HAWKES_E_ZERO_INTENSITY. */
+ * pass runs iff d_grad_theta or d_negH_theta is non-NULL.  The pair terms are
+ * FP32; an event whose intensity from them falls below (c_b + c_e) n 2^-96
+ * (all its terms near or below FP32's range: an event far from every other
+ * one) has its lambda_i and derivative sums recomputed from the definitions in
+ * FP64, so lambda_i keeps FP64's range.  When some lambda_i is zero in FP64,
+ * loglik is -inf and the sticky status becomes HAWKES_E_ZERO_INTENSITY. */
 hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, const double *d_theta,
                           double *d_loglik, double *d_grad_theta, double *d_grad_hyper,
                           double *d_negH_theta, double *d_negH_hyper, hipStream_t stream);

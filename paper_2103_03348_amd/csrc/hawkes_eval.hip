@@ -565,7 +565,8 @@ constexpr int HK_FIN_WAVES = 8;
 template <int MODE>
 __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const double *__restrict__ theta,
                                            const int *__restrict__ perm, int64_t n, const FinConst &fc,
-                                           const double (*part)[HK_NROW][HK_WAVE], int lane, int64_t i,
+                                           const double (*part)[HK_NROW][HK_WAVE],
+                                           const double (*exact)[HK_WAVE], bool is_exact, int lane, int64_t i,
                                            double *__restrict__ lam, double *__restrict__ lw,
                                            double *__restrict__ a_out, double *__restrict__ blockpart,
                                            int *__restrict__ status) {
@@ -573,21 +574,47 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
 #pragma unroll
     for (int k = 0; k < HK_NSUM; ++k) s[k] = 0.0;
     if (i < n) {
-        double acc[HK_NROW];
+        // the ten sums in natural units: B0, B1 (r^2), B2 (dt^2), B11, B22,
+        // X0, X1 (dt), X2 (r^2), X11, X22, from the pair passes' partials or,
+        // for a row recomputed in FP64, from k_fin's exact sums
+        double B0, B1, B2, B11, B22, X0, X1, X2, X11, X22;
+        if (is_exact) {
+            B0 = exact[0][lane];
+            B1 = exact[1][lane];
+            B2 = exact[2][lane];
+            B11 = exact[3][lane];
+            B22 = exact[4][lane];
+            X0 = exact[5][lane];
+            X1 = exact[6][lane];
+            X2 = exact[7][lane];
+            X11 = exact[8][lane];
+            X22 = exact[9][lane];
+        } else {
+            double acc[HK_NROW];
 #pragma unroll
-        for (int k = 0; k < HK_NROW; ++k) {
-            double v = part[0][k][lane];
-            for (int q = 1; q < HK_FIN_WAVES; ++q) v += part[q][k][lane];
-            acc[k] = v;
+            for (int k = 0; k < HK_NROW; ++k) {
+                double v = part[0][k][lane];
+                for (int q = 1; q < HK_FIN_WAVES; ++q) v += part[q][k][lane];
+                acc[k] = v;
+            }
+            // moments corrected for the mean exp2 bias and, when the first moments
+            // are present, for the rounding of the FP32 ratio rex
+            double b0 = acc[0], x0 = acc[5];
+            if (MODE >= HK_MODE_GRAD) {
+                const double ln2 = 0.6931471805599453;
+                x0 -= ln2 * fc.rho_ex * acc[7];
+            }
+            B0 = b0 * fc.corr;
+            X0 = x0 * fc.corr;
+            B1 = acc[1] * fc.corr * fc.Kx;
+            B2 = acc[2] * fc.corr * fc.Kt;
+            X1 = acc[6] * fc.corr * fc.inv_st;
+            X2 = acc[7] * fc.corr * fc.Kh;
+            B11 = acc[3] * fc.corr * fc.Kx * fc.Kx;
+            B22 = acc[4] * fc.corr * fc.Kt * fc.Kt;
+            X11 = acc[8] * fc.corr * fc.inv_st * fc.inv_st;
+            X22 = acc[9] * fc.corr * fc.Kh * fc.Kh;
         }
-        // moments corrected for the mean exp2 bias and, when the first moments
-        // are present, for the rounding of the FP32 ratio rex
-        double b0 = acc[0], x0 = acc[5];
-        if (MODE >= HK_MODE_GRAD) {
-            const double ln2 = 0.6931471805599453;
-            x0 -= ln2 * fc.rho_ex * acc[7];
-        }
-        const double B0 = b0 * fc.corr, X0 = x0 * fc.corr;
         const double lamv = fc.c_b * B0 + fc.c_e * X0;
         lam[i] = lamv;
         if (!(lamv > 0.0)) {
@@ -599,8 +626,6 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
         lw[i] = lamv > 0.0 ? fmax(fc.log2_ce - s[0] * 1.4426950408889634, HK_EXP_FLOOR) : HK_EXP_FLOOR;
         const double inv = 1.0 / lamv;
         if (MODE >= HK_MODE_GRAD) {
-            const double B1 = acc[1] * fc.corr * fc.Kx, B2 = acc[2] * fc.corr * fc.Kt;
-            const double X1 = acc[6] * fc.corr * fc.inv_st, X2 = acc[7] * fc.corr * fc.Kh;
             const double tx = fc.tau_x, tt = fc.tau_t, om = fc.omega, hh = fc.h;
             double d1[6];
             d1[0] = fc.cb1 * B0;
@@ -612,8 +637,6 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
 #pragma unroll
             for (int p = 0; p < 6; ++p) s[1 + p] = d1[p] * inv;
             if (MODE >= HK_MODE_HESS) {
-                const double B11 = acc[3] * fc.corr * fc.Kx * fc.Kx, B22 = acc[4] * fc.corr * fc.Kt * fc.Kt;
-                const double X11 = acc[8] * fc.corr * fc.inv_st * fc.inv_st, X22 = acc[9] * fc.corr * fc.Kh * fc.Kh;
                 const double tx2 = tx * tx, tt2 = tt * tt, hh2 = hh * hh;
                 double d2[6];
                 d2[0] = 0.0;
@@ -658,13 +681,48 @@ __device__ __forceinline__ void fin_events(const double *__restrict__ ts, const 
 }
 
 
+// The ten sums of row i straight from the definitions (Sec. 2.1): b_ij over
+// every j != i, theta_j E_ij over the strictly earlier j, each term in FP64
+// (the range of the oracle), this thread's share j = t, t + nt, ...
+__device__ void exact_row_sums(const double *__restrict__ ts, const double *__restrict__ xs,
+                               const double *__restrict__ ys, const double *__restrict__ theta,
+                               const int *__restrict__ perm, const int *__restrict__ g, int64_t n,
+                               const FinConst &fc, int64_t i, int t, int nt, double (&m)[HK_NROW]) {
+    const double ti = ts[i], xi = xs[i], yi = ys[i];
+    const int gi = g[i];
+    const double kb = 0.5 / (fc.tau_x * fc.tau_x), kt = 0.5 / (fc.tau_t * fc.tau_t);
+    const double kh = 0.5 / (fc.h * fc.h);
+    for (int64_t j = t; j < n; j += nt) {
+        if (j == i) continue;
+        const double dx = xi - xs[j], dy = yi - ys[j];
+        const double r2 = dx * dx + dy * dy;
+        const double dt = ti - ts[j], dt2 = dt * dt;
+        const double b = exp(-(r2 * kb) - dt2 * kt);
+        m[0] += b;
+        m[1] += b * r2;
+        m[2] += b * dt2;
+        m[3] += b * r2 * r2;
+        m[4] += b * dt2 * dt2;
+        if (j < gi) {
+            const double te = theta[perm[j]] * exp(-fc.omega * dt - r2 * kh);
+            m[5] += te;
+            m[6] += te * dt;
+            m[7] += te * r2;
+            m[8] += te * dt2;
+            m[9] += te * r2 * r2;
+        }
+    }
+}
+
 // Finalisation, one block per 64-event chunk.  The HK_FIN_WAVES wavefronts
 // first split the partial sums of the chunk's events between them (row pieces
 // and column partials of the later row tiles, round robin; these reads are the
 // kernel's cost, so many are kept in flight), the partials are combined in a
 // fixed order through LDS, and the first wavefront finishes the events.
 template <int MODE>
-__global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__restrict__ ts, const double *__restrict__ theta,
+__global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__restrict__ ts, const double *__restrict__ xs,
+                                             const double *__restrict__ ys, const int *__restrict__ g,
+                                             const double *__restrict__ theta,
                                              const int *__restrict__ perm, int64_t n, int ntiles,
                                              const int *__restrict__ row_item0, const int *__restrict__ row_nseg,
                                              const float *__restrict__ rowpart, const float *__restrict__ colpart,
@@ -719,7 +777,40 @@ __global__ __launch_bounds__(HK_FIN_WAVES * HK_WAVE) void k_fin(const double *__
         for (int k = 0; k < HK_NROW; ++k) part[wq][k][lane] = acc[k];
     }
     __syncthreads();
-    if (wq == 0) fin_events<MODE>(ts, theta, perm, n, fc, part, lane, i, lam, lw, a_out, blockpart,
+    // rows whose intensity from the partials is below fc.lam_exact (their FP32
+    // terms may have lost more than 2^-30 of it) are recomputed here in FP64 by
+    // the whole block, one row at a time; every wavefront derives the same mask
+    __shared__ double exact[HK_NROW][HK_WAVE];
+    __shared__ double red[HK_FIN_WAVES][HK_NROW];
+    double b0 = part[0][0][lane], x0 = part[0][5][lane];
+    for (int q = 1; q < HK_FIN_WAVES; ++q) {
+        b0 += part[q][0][lane];
+        x0 += part[q][5][lane];
+    }
+    const bool low = i < n && fc.c_b * b0 + fc.c_e * x0 < fc.lam_exact;
+    const uint64_t low_mask = __ballot(low);
+    for (uint64_t mk = low_mask; mk != 0; mk &= mk - 1) {
+        const int rr = __ffsll((unsigned long long)mk) - 1;
+        double m[HK_NROW];
+#pragma unroll
+        for (int k = 0; k < HK_NROW; ++k) m[k] = 0.0;
+        exact_row_sums(ts, xs, ys, theta, perm, g, n, fc, (int64_t)blockIdx.x * HK_WAVE + rr, threadIdx.x,
+                       HK_FIN_WAVES * HK_WAVE, m);
+#pragma unroll
+        for (int k = 0; k < HK_NROW; ++k) m[k] = wave_sum_f64(m[k]);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < HK_NROW; ++k) red[wq][k] = m[k];
+        }
+        __syncthreads();
+        if (threadIdx.x < HK_NROW) {
+            double v = red[0][threadIdx.x];
+            for (int q = 1; q < HK_FIN_WAVES; ++q) v += red[q][threadIdx.x];
+            exact[threadIdx.x][rr] = v;
+        }
+        __syncthreads();
+    }
+    if (wq == 0) fin_events<MODE>(ts, theta, perm, n, fc, part, exact, low, lane, i, lam, lw, a_out, blockpart,
                                   status);
 }
 
@@ -776,11 +867,11 @@ __device__ __forceinline__ double col_exponent(const ColRow &r, double xj, doubl
 }
 
 
-template <bool WITH_H, bool MASKED, bool DOT>
+template <bool SPLIT, bool MASKED, bool DOT>
 __device__ __forceinline__ float col_term(const ColRow *__restrict__ rows, const int *__restrict__ rg, int s,
                                           int jcol, double xj, double yj, double dj) {
     const double e = col_exponent<DOT>(rows[s], xj, yj, dj);
-    float T = WITH_H ? exp2_split(e) : __builtin_amdgcn_ldexpf(fexp2((float)e), rows[s].n);
+    float T = SPLIT ? exp2_split(e) : __builtin_amdgcn_ldexpf(fexp2((float)e), rows[s].n);
     if (MASKED) {
         if (!(jcol < rg[s])) T = 0.0f;
     }
@@ -796,15 +887,15 @@ __device__ __forceinline__ float col_term(const ColRow *__restrict__ rows, const
 #define HK_COL_UNROLL 2
 #endif
 constexpr int kColUnroll = HK_COL_UNROLL;
-template <bool WITH_H, bool MASKED, bool DOT>
+template <bool WITH_H, bool SPLIT, bool MASKED, bool DOT>
 __device__ __forceinline__ void col_sweep(const ColRow *__restrict__ rows, const int *__restrict__ rg, int jcol,
                                           double xj, double yj, double dj, float &G, float &H) {
 #pragma clang fp contract(off)
     float G1 = 0.0f, H1 = 0.0f;
 #pragma unroll kColUnroll
     for (int s = 0; s < HK_WAVE; s += 2) {
-        const float e0 = col_term<WITH_H, MASKED, DOT>(rows, rg, s, jcol, xj, yj, dj);
-        const float e1 = col_term<WITH_H, MASKED, DOT>(rows, rg, s + 1, jcol, xj, yj, dj);
+        const float e0 = col_term<SPLIT, MASKED, DOT>(rows, rg, s, jcol, xj, yj, dj);
+        const float e1 = col_term<SPLIT, MASKED, DOT>(rows, rg, s + 1, jcol, xj, yj, dj);
         G += e0;
         G1 += e1;
         if (WITH_H) {
@@ -824,6 +915,7 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
                                                   double *__restrict__ colG, const PairConst kc) {
     __shared__ ColRow rows[HK_WAVE];
     __shared__ int rg[HK_WAVE];
+    __shared__ int chunk_split;  // Eq. 4 alone: the staged chunk splits every exponent exactly
     // uniform wavefront index: the per-wave bounds select the sweep with scalar branches
     const int tid = threadIdx.x, wvi = __builtin_amdgcn_readfirstlane(tid / HK_WAVE);
     const int q_end = block0[blockIdx.x + 1];
@@ -864,24 +956,35 @@ __global__ __launch_bounds__(HK_TILE) void k_col(const double *__restrict__ ts, 
                 }
                 r.c = fmax(cr, HK_EXP_FLOOR);
                 r.n = 0;
-                if (!WITH_H && lwi > HK_EXP_FLOOR) {
+                // the staging wavefront holds the chunk's 64 rows
+                const bool split = !WITH_H && __ballot(lwi > HK_LW_SPLIT_MAX) != 0;
+                if (!WITH_H && !split && lwi > HK_EXP_FLOOR) {
                     const double nw = rint(lwi);
                     r.n = (int)nw;
                     r.c -= nw;
                 }
                 rows[tid] = r;
                 rg[tid] = g[i];
+                if (tid == 0) chunk_split = split;
             }
             __syncthreads();
             const int gmax = rg[HK_WAVE - 1], gmin = rg[0];
+            const bool split = WITH_H || chunk_split != 0;
             // optional underflow cutoff: rows that all start more than dt_cut_ex
             // after the wave's latest column give excitation terms below 2^-160
             if (gmax > wave_first && !(Tc - wave_tmax > kc.dt_cut_ex)) {
                 float G = 0.0f, H = 0.0f;
-                if (gmin <= wave_first + HK_WAVE - 1)
-                    col_sweep<WITH_H, true, DOT>(rows, rg, jcol, uxj, uyj, dj, G, H);
-                else
-                    col_sweep<WITH_H, false, DOT>(rows, rg, jcol, uxj, uyj, dj, G, H);
+                if (gmin <= wave_first + HK_WAVE - 1) {
+                    if (split)
+                        col_sweep<WITH_H, true, true, DOT>(rows, rg, jcol, uxj, uyj, dj, G, H);
+                    else
+                        col_sweep<WITH_H, false, true, DOT>(rows, rg, jcol, uxj, uyj, dj, G, H);
+                } else {
+                    if (split)
+                        col_sweep<WITH_H, true, false, DOT>(rows, rg, jcol, uxj, uyj, dj, G, H);
+                    else
+                        col_sweep<WITH_H, false, false, DOT>(rows, rg, jcol, uxj, uyj, dj, G, H);
+                }
                 Gd += (double)G;
                 if (WITH_H) Hd += (double)H;
             }
@@ -1005,6 +1108,7 @@ void hk_make_consts(const hawkes_plan p, const hawkes_hyper *hy, PairConst *kc, 
     fc->Kx = -2.0 * hy->tau_x * hy->tau_x * ln2;
     fc->Kh = -2.0 * hy->h * hy->h * ln2;
     fc->corr = corr;
+    fc->lam_exact = (fc->c_b + fc->c_e) * (double)p->n * 0x1p-96;
     fc->t0 = p->t0;
     fc->t1 = p->t1;
 }
@@ -1082,7 +1186,8 @@ extern "C" hawkes_status hawkes_eval(hawkes_plan p, const hawkes_hyper *hyper, c
                        p->theta_v, p->chunk_precise, p->tstep, p->g, p->row_items, p->row_block0, p->colpart_off,             \
                        p->rowpart, p->colpart, kc)
 #define HK_FIN(M)                                                                                              \
-    hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->ts, d_theta,       \
+    hipLaunchKernelGGL(k_fin<M>, dim3(p->nchunks), dim3(HK_FIN_WAVES * HK_WAVE), 0, stream, p->ts, p->xs, p->ys, \
+                       p->g, d_theta,                                                                          \
                        p->perm, p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart, fc,             \
                        p->lam, p->lw, p->a, p->blockpart, p->status)
     if (mode == HK_MODE_LOGLIK) HK_ROW(HK_MODE_LOGLIK);

@@ -192,7 +192,9 @@ __global__ void k_sub_zero_subset(const int *__restrict__ pos, int64_t m, float 
 
 // lambda_static_i from the row pass partials (log-likelihood mode: B0, X0) and
 // the integral term of everything that does not depend on the subset rates.
-__global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ ts, const double *__restrict__ theta,
+__global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ ts, const double *__restrict__ xs,
+                                                    const double *__restrict__ ys, const int *__restrict__ g,
+                                                    const double *__restrict__ theta,
                                                     const int *__restrict__ perm, const float *__restrict__ theta_s,
                                                     int64_t n, int ntiles, const int *__restrict__ row_item0,
                                                     const int *__restrict__ row_nseg,
@@ -213,7 +215,28 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
             x0 += rp[5 * HK_TILE];
         }
         for (int J = I; J < ntiles; ++J) b0 += (double)colpart[colpart_off[J] + i];
-        lam_static[i] = fc.c_b * b0 * fc.corr + fc.c_e * x0 * fc.corr;
+        double ls = fc.c_b * b0 * fc.corr + fc.c_e * x0 * fc.corr;
+        if (ls < fc.lam_exact) {
+            // the FP32 pair terms may have lost more than 2^-30 of this row's
+            // static intensity: recompute it from the definitions in FP64
+            // (background over every j != i, excitation from the earlier
+            // fixed-rate events; theta_s is zero on the subset)
+            const double xi = xs[i], yi = ys[i], tsi = ts[i];
+            const int gi = g[i];
+            const double kb = 0.5 / (fc.tau_x * fc.tau_x), kt = 0.5 / (fc.tau_t * fc.tau_t);
+            const double kh = 0.5 / (fc.h * fc.h);
+            double B0 = 0.0, X0 = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                const double dx = xi - xs[j], dy = yi - ys[j];
+                const double r2 = dx * dx + dy * dy;
+                const double dt = tsi - ts[j];
+                B0 += exp(-(r2 * kb) - dt * dt * kt);
+                if (j < gi && theta_s[j] != 0.0f) X0 += theta[perm[j]] * exp(-fc.omega * dt - r2 * kh);
+            }
+            ls = fc.c_b * B0 + fc.c_e * X0;
+        }
+        lam_static[i] = ls;
         // integral term: background (all events) + excitation of the fixed-rate events
         const double ti = ts[i];
         const double u1 = (fc.t1 - ti) / fc.tau_t, u0 = (fc.t0 - ti) / fc.tau_t;
@@ -309,8 +332,17 @@ __global__ __launch_bounds__(256) void k_sub_theta(
 // chunk's first entry time as in the full row pass (FP64 factors, spatial
 // exponent in the loop) unless the chunk spans more than HK_SUB_FACT_SPAN /
 // omega in time.  The exponent is formed in FP64 from coordinates pre-scaled by
-// sqrt(-kex) (and, unsplit, the FP64 time term) and rounded once, so it carries
-// no rounded FP32 constant.
+// sqrt(-kex), so it carries no rounded FP32 constant; the split form rounds the
+// spatial exponent once to FP32, the unsplit one adds the FP64 time term and
+// splits the whole exponent into an exact power of two and an FP32 fraction
+// (rounding it whole would give a term an error that grows with its decay).
+
+// 2^e for an FP64 exponent: exact integer part, FP32 fraction (a term's
+// relative error then does not grow with |e|)
+__device__ __forceinline__ float sub_exp2_split(double e) {
+    const double n = rint(e);
+    return __builtin_amdgcn_ldexpf(fexp2((float)(e - n)), (int)n);
+}
 
 template <bool MASKED, bool FACT>
 __device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, const float *__restrict__ rv,
@@ -322,7 +354,9 @@ __device__ __forceinline__ void sub_row_sweep(const double2 *__restrict__ rxy, c
         const double2 pk = rxy[s];
         const double dx = xr - pk.x, dy = yr - pk.y;
         const double aed = -fma(dx, dx, dy * dy);
-        float E = fexp2(FACT ? (float)aed : (float)fma(tsi - rtd[s], kc.kw_d, aed));
+        // unsplit (a wide batch): the whole exponent, time term included, is
+        // split into an exact power of two and an FP32 fraction
+        float E = FACT ? fexp2((float)aed) : sub_exp2_split(fmax(fma(tsi - rtd[s], kc.kw_d, aed), HK_EXP_FLOOR));
         if (MASKED && !(rpos[s] < gr)) E = 0.0f;
         acc += (double)(E * rv[s]);
     }
@@ -384,10 +418,13 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
         if (chunk_tmin - sts[cend - 1] > kc.dt_cut_ex) continue;
         const bool fact = qwide[q] == 0;
         {
+            // entries past the item's range carry rate 0 and a time of -inf: the
+            // unsplit exponent is then -inf and the term exactly 0 (a later
+            // entry's own time could make it +inf, and inf * 0 a NaN)
             const bool valid = c0 + lane < cend;
             rxy[lane] = pxy;
             rv[lane] = valid ? pv : 0.0f;
-            rtd[lane] = pt;
+            rtd[lane] = valid ? pt : -INFINITY;
             rpos[lane] = valid ? pp : 0x7fffffff;
         }
         __syncthreads();
@@ -426,6 +463,10 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_row(
 __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const double *__restrict__ lam_static,
                                                  const int *__restrict__ ritem0, const int *__restrict__ rnseg,
                                                  const double *__restrict__ xpart, const double *__restrict__ ts,
+                                                 const double *__restrict__ xs, const double *__restrict__ ys,
+                                                 const int *__restrict__ g, const int *__restrict__ pos,
+                                                 const float *__restrict__ tv, const double *__restrict__ sts,
+                                                 const int *__restrict__ qwide, int64_t m,
                                                  int64_t n, int64_t npad, const FinConst fc,
                                                  double *__restrict__ lam, double *__restrict__ lw,
                                                  double *__restrict__ blockpart, int *__restrict__ status) {
@@ -434,10 +475,10 @@ __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const do
     const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x / HK_WAVE);
     const int64_t i0 = (int64_t)b * HK_WAVE;  // the chunk's first event
     const int64_t i = i0 + lane;
-    // wavefront 0's own operands are fetched before the reduction, so that their
-    // latency overlaps the partial-sum reads
+    // the static part is fetched before the reduction, so that its latency
+    // overlaps the partial-sum reads
     double lst = 0.0;
-    if (wq == 0 && i < n) lst = lam_static[i];
+    if (i < n) lst = lam_static[i];
     {
         double x = 0.0;
         if (i < n) {
@@ -459,13 +500,47 @@ __global__ __launch_bounds__(SUB_ROWFIN_WAVES * HK_WAVE) void k_sub_fin(const do
         part[wq][lane] = x;
     }
     __syncthreads();
+    double x = part[0][lane];
+#pragma unroll
+    for (int k = 1; k < SUB_ROWFIN_WAVES; ++k) x += part[k][lane];
+    // rows whose intensity is below fc.lam_exact (the FP32 terms may have lost
+    // more than 2^-30 of it) take the subset excitation from the definitions
+    // in FP64, the whole block on one row at a time; every wavefront derives
+    // the same mask
+    __shared__ double xred[SUB_ROWFIN_WAVES];
+    __shared__ double xexact[HK_WAVE];
+    const bool low = i < n && lst + fc.c_e * fc.corr * x < fc.lam_exact;
+    for (uint64_t mk = __ballot(low); mk != 0; mk &= mk - 1) {
+        const int rr = __ffsll((unsigned long long)mk) - 1;
+        const int64_t ir = i0 + rr;
+        const double xi = xs[ir], yi = ys[ir], ti = ts[ir];
+        const int gi = g[ir];
+        const double kh = 0.5 / (fc.h * fc.h);
+        double xs_sum = 0.0;
+        for (int64_t r = threadIdx.x; r < m; r += SUB_ROWFIN_WAVES * HK_WAVE) {
+            const int pk = pos[r];
+            if (pk >= gi) continue;  // entries are in time order; only earlier events excite
+            const double dx = xi - xs[pk], dy = yi - ys[pk];
+            const double r2 = dx * dx + dy * dy;
+            // tv carries theta_r exp(omega (t_r - T_q)) on a split chunk q
+            const int64_t q = r / HK_WAVE;
+            const double tq = qwide[q] ? sts[r] : sts[q * HK_WAVE];
+            xs_sum += (double)tv[r] * exp(-fc.omega * (ti - tq) - r2 * kh);
+        }
+        for (int off = 32; off > 0; off >>= 1) xs_sum += __shfl_xor(xs_sum, off);
+        if (lane == 0) xred[wq] = xs_sum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double v = xred[0];
+            for (int k = 1; k < SUB_ROWFIN_WAVES; ++k) v += xred[k];
+            xexact[rr] = v;
+        }
+        __syncthreads();
+    }
     if (wq != 0) return;
     double v = 0.0;
     if (i < n) {
-        double x = part[0][lane];
-#pragma unroll
-        for (int k = 1; k < SUB_ROWFIN_WAVES; ++k) x += part[k][lane];
-        const double l = lst + fc.c_e * fc.corr * x;
+        const double l = low ? lst + fc.c_e * xexact[lane] : lst + fc.c_e * fc.corr * x;
         lam[i] = l;
         if (!(l > 0.0)) atomicOr(status, isnan(l) ? HK_ST_NONFINITE : HK_ST_ZERO);
         v = log(l);
@@ -496,12 +571,7 @@ struct SubColRow {  // one staged row
     int n;          // Eq. 4 alone: rint(lw_i) (0 for a row at the floor), applied exactly
 };
 
-__device__ __forceinline__ float sub_exp2_split(double e) {
-    const double n = rint(e);
-    return __builtin_amdgcn_ldexpf(fexp2((float)(e - n)), (int)n);
-}
-
-template <bool WITH_H, bool MASKED, bool DOT>
+template <bool WITH_H, bool SPLIT, bool MASKED, bool DOT>
 __device__ __forceinline__ void sub_col_sweep(const SubColRow *__restrict__ rows, const int *__restrict__ rg, int pj,
                                               double xk, double yk, double dk, float &G, float &H) {
 #pragma unroll kSubUnroll
@@ -514,7 +584,7 @@ __device__ __forceinline__ void sub_col_sweep(const SubColRow *__restrict__ rows
             const double dx = r.u.x - xk, dy = r.u.y - yk;
             e = fma(-dx, dx, fma(-dy, dy, r.c + dk));
         }
-        float T = WITH_H ? sub_exp2_split(e) : __builtin_amdgcn_ldexpf(fexp2((float)e), r.n);
+        float T = SPLIT ? sub_exp2_split(e) : __builtin_amdgcn_ldexpf(fexp2((float)e), r.n);
         if (MASKED && !(pj < rg[s])) T = 0.0f;
         G += T;
         if (WITH_H) H = fmaf(T, T, H);
@@ -574,6 +644,7 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
         }
         const double Tc = ts[(int64_t)c * HK_WAVE];
         if (Tc - q_tmax > kc.dt_cut_ex) break;  // cutoff: all later rows too far
+        bool split = WITH_H;
         {
             const double ux = px * kc.sx, uy = py * kc.sx;
             double cr = pl + kc.kw_d * (pt - t_ref);
@@ -587,8 +658,10 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
             w.c = fmax(cr, HK_EXP_FLOOR);
             w.n = 0;
             // a row whose weight is at the floor (zero weight, padding) keeps its
-            // whole exponent in c, which then stays at the floor
-            if (!WITH_H && pl > HK_EXP_FLOOR) {
+            // whole exponent in c, which then stays at the floor; a chunk with a
+            // row of large weight splits every exponent exactly
+            split = !WITH_H && __ballot(pl > HK_LW_SPLIT_MAX) != 0;
+            if (!WITH_H && !split && pl > HK_EXP_FLOOR) {
                 const double nw = rint(pl);
                 w.n = (int)nw;
                 w.c -= nw;
@@ -599,10 +672,17 @@ __global__ __launch_bounds__(HK_WAVE) void k_sub_col(const double *__restrict__ 
         __syncthreads();
         float G = 0.0f, H = 0.0f;
         // rows whose tie groups all start after the chunk's last entry need no mask
-        if (pos_last < rg[0])
-            sub_col_sweep<WITH_H, false, DOT>(rows, rg, pj, pxy.x, pxy.y, dk, G, H);
-        else
-            sub_col_sweep<WITH_H, true, DOT>(rows, rg, pj, pxy.x, pxy.y, dk, G, H);
+        if (pos_last < rg[0]) {
+            if (WITH_H || split)
+                sub_col_sweep<WITH_H, true, false, DOT>(rows, rg, pj, pxy.x, pxy.y, dk, G, H);
+            else
+                sub_col_sweep<WITH_H, false, false, DOT>(rows, rg, pj, pxy.x, pxy.y, dk, G, H);
+        } else {
+            if (WITH_H || split)
+                sub_col_sweep<WITH_H, true, true, DOT>(rows, rg, pj, pxy.x, pxy.y, dk, G, H);
+            else
+                sub_col_sweep<WITH_H, false, true, DOT>(rows, rg, pj, pxy.x, pxy.y, dk, G, H);
+        }
         Gd += (double)G;
         if (WITH_H) Hd += (double)H;
         __syncthreads();
@@ -1024,7 +1104,8 @@ hawkes_status ensure_static(hawkes_plan p, const hawkes_hyper *hy, const double 
                        s->m, p->n, p->npad, p->theta_s, p->status);
     hipLaunchKernelGGL(k_sub_zero_subset, dim3(nblk(s->m, 256)), dim3(256), 0, stream, s->pos, s->m, p->theta_s);
     hk_launch_row_loglik(p, kc, stream);
-    hipLaunchKernelGGL(k_sub_static, dim3(p->nfin_blocks), dim3(256), 0, stream, p->ts, d_theta, p->perm, p->theta_s,
+    hipLaunchKernelGGL(k_sub_static, dim3(p->nfin_blocks), dim3(256), 0, stream, p->ts, p->xs, p->ys, p->g, d_theta,
+                       p->perm, p->theta_s,
                        p->n, p->ntiles, p->row_item0, p->row_nseg, p->rowpart, p->colpart,
                        p->colpart_off, fc,
                        s->lam_static, p->blockpart);
@@ -1050,8 +1131,8 @@ static void sub_rows(hawkes_plan p, const double *z, const double *off, double *
     hipLaunchKernelGGL(k_sub_row, dim3(s->n_ritems), dim3(HK_WAVE), 0, stream, p->ts, p->xs, p->ys, p->g, s->pos,
                        s->tv, s->sxy, s->sts, s->qwide, s->qstep, s->ritems, kc, s->xpart);
     hipLaunchKernelGGL(k_sub_fin, dim3(p->nchunks), dim3(SUB_ROWFIN_WAVES * HK_WAVE), 0, stream, s->lam_static,
-                       s->ritem0, s->rnseg,
-                       s->xpart, p->ts, p->n, p->npad, fc, p->lam, s->lw, p->blockpart, p->status);
+                       s->ritem0, s->rnseg, s->xpart, p->ts, p->xs, p->ys, p->g, s->pos, s->tv, s->sts, s->qwide,
+                       s->m, p->n, p->npad, fc, p->lam, s->lw, p->blockpart, p->status);
 }
 
 // The column half: Eq. 4 (and Eq. 5) on the subset, optionally with the fused

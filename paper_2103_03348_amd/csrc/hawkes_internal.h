@@ -57,6 +57,14 @@
 // below 2^-32 of a unit term says only that no later event is near).
 #define HK_KSUM_LOG2_FLOOR (-32.0)
 
+// Eq. 4 alone: the column passes take the integer part of a row's weight
+// lw_i = log2(c_e / lambda_i) out of each exponent exactly and round the rest,
+// the pair's own decay, once to FP32.  For a row of large weight (a low
+// intensity) that rest can be large on terms that still carry a column's sum,
+// so a chunk holding a row with lw_i above HK_LW_SPLIT_MAX splits every
+// exponent exactly instead (integer part and FP32 fraction).
+#define HK_LW_SPLIT_MAX 8.0
+
 // Time offset given to padding events: their pair terms underflow to exactly
 // zero while every square stays finite in FP32.
 #define HK_PAD_DT 1.0e15
@@ -200,6 +208,11 @@ struct FinConst {
     // row pass accumulates.  (The background's exponent carries no rounded
     // constant; the excitation's time term is exact or formed in FP64.)
     double rho_ex;         // (rex_f - rex) / rex_f: the row pass forms a_e = a_b rex_f
+    // The pair passes' FP32 terms lose what falls below FP32's normal range
+    // (2^-126 per term): at most (c_b + c_e) n 2^-126 of lambda_i.  A row whose
+    // lambda_i comes out below lam_exact = (c_b + c_e) n 2^-96, where that loss
+    // could exceed 2^-30 of it, is recomputed exactly in FP64 by k_fin.
+    double lam_exact;
 };
 
 bool hk_hyper_ok(const hawkes_hyper *h);

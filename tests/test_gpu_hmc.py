@@ -44,14 +44,18 @@ def _subset_grad(plan, es, theta, refresh=0, want_h=True):
     return float(ll.item()), g.cpu().numpy(), (h.cpu().numpy() if want_h else None)
 
 
-@pytest.mark.parametrize("cfg", ["small", "allfree", "dense", "n23422"])
+@pytest.mark.parametrize("cfg", ["small", "allfree", "dense", "isolated", "n23422"])
 def test_subset_grad_matches_oracle(gpu, cfg):
     """Eq. 1, 4, 5 restricted to the free rates, by the cached-static O(N M) path
     (allfree: every rate free, so the static part holds the background only;
     dense: the latest 2,500 of 3,000 events free, so that late row chunks have
     up to 40 row items each and their finalisation takes more than one round of
-    batched reads)."""
-    if cfg == "small":
+    batched reads; isolated: 2,500 events over 1e5 time units, 60 of whose
+    intensities lie below 1e-38, down to 6e-110, recomputed in FP64 by the
+    static part and the row finalisation)."""
+    if cfg == "isolated":
+        es = synth.small(2500, seed=9, t_end=1e5, all_free=False)
+    elif cfg == "small":
         es = synth.small(1500, seed=21, ties=6, all_free=False)
     elif cfg == "allfree":
         es = synth.small(333, seed=22, ties=5, all_free=True)
@@ -88,7 +92,7 @@ def test_subset_grad_matches_oracle(gpu, cfg):
     assert np.max(np.abs(g2 - gi2) / np.maximum(np.abs(gi2) + 2 * a, 1e-300)) < 1e-6
 
 
-@pytest.mark.parametrize("cfg", ["small", "dense", "sparse", "n23422"])
+@pytest.mark.parametrize("cfg", ["small", "dense", "sparse", "isolated", "n23422"])
 def test_subset_grad_only_matches_oracle(gpu, cfg):
     """Eq. 4 alone on the subset (the leapfrog's gradient): its column pass
     applies the row weight's integer part exactly and rounds the rest of each
@@ -104,6 +108,8 @@ def test_subset_grad_only_matches_oracle(gpu, cfg):
         es = dataclasses.replace(es, subset=sub, z=np.log(es.theta[sub]))
     elif cfg == "sparse":
         es = synth.small(2000, seed=33, t_end=2400.0, ties=2, all_free=False)
+    elif cfg == "isolated":
+        es = synth.small(2500, seed=9, t_end=1e5, all_free=False)
     else:
         es = synth.config(1)
     plan, idx = _setup(es)

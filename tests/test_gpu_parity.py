@@ -38,7 +38,7 @@ SMALL = [
 ]
 
 
-def _check(es, gpu, ref, l_tol=1e-9, tiny=False):
+def _check(es, gpu, ref, l_tol=1e-9, tiny=False, hh_mag=None):
     e = errors(es, gpu, ref)
     print(f"\n[{es.name} n={es.n}] " + " ".join(
         f"{k}={v:.3e}" if np.isscalar(v) else f"{k}={np.max(v):.3e}" for k, v in e.items()), flush=True)
@@ -55,6 +55,8 @@ def _check(es, gpu, ref, l_tol=1e-9, tiny=False):
     hy = np.asarray(es.hyper)
     gscale = np.maximum(np.abs(ref["grad_hyper"]), n / hy)
     hscale = np.maximum(np.abs(ref["negH_hyper"]), n / hy ** 2)
+    if hh_mag is not None:
+        hscale = np.maximum(hscale, hh_mag)
     htol = 1e-6 if n >= 256 else 1e-5
     assert np.all(e["gh_abs"] / gscale < htol), e["gh_abs"] / gscale
     assert np.all(e["Hh_abs"] / hscale < htol), e["Hh_abs"] / hscale
@@ -400,4 +402,89 @@ def test_grad_only_matches_oracle(gpu, case):
     g_rel = float(np.max(np.abs(g - ref["grad_theta"]) / np.maximum(a + (ref["grad_theta"] + a), 1e-300)))
     print(f"\ngrad only {case}: g {g_rel:.3e}")
     assert st == 0
+    assert g_rel < 1e-6
+
+
+def _isolated_set(case):
+    """Event sets in which some events are so far from every other one that all
+    of their pair terms lie below FP32's range (the oracle's lambda of those
+    events is ~1e-110 and ~1e-50, finite in FP64)."""
+    if case == "sparse_range":
+        # 2,500 events over 1e5 time units: the smallest intensity is ~4e-110
+        return synth.small(2500, seed=9, t_end=1e5)
+    base = synth.small(1000, seed=44)
+    tau_x = base.hyper[1]
+    # three events 15 tau_x outside the set, each beyond a different extreme
+    # event and at its time: their largest background term is exp(-112.5)
+    # (1.4e-49, below FP32's range), their excitation terms underflow in FP64
+    # as well (h < tau_x)
+    e_xmax, e_xmin, e_ymax = np.argmax(base.x), np.argmin(base.x), np.argmax(base.y)
+    d = 15.0 * tau_x
+    x_far = np.array([base.x[e_xmax] + d, base.x[e_xmin] - d, base.x[e_ymax]])
+    y_far = np.array([base.y[e_xmax], base.y[e_xmin], base.y[e_ymax] + d])
+    t_far = base.t[[e_xmax, e_xmin, e_ymax]]
+    t = np.concatenate([base.t, t_far])
+    x = np.concatenate([base.x, x_far])
+    y = np.concatenate([base.y, y_far])
+    theta = np.concatenate([base.theta, np.ones(3)])
+    return synth.EventSet(t, x, y, theta, base.subset, base.z, base.hyper, base.t0, "far")
+
+
+def _hyper_hessian_magnitude(es):
+    """sum_i |lambda''_i| / lambda_i + (lambda'_i / lambda_i)^2 per hyperparameter
+    (the per-event terms whose sum is the likelihood part of the hyperparameter
+    Hessian diagonal), from the oracle's per-event pair sums and the
+    derivatives of lambda_i in the six hyperparameters."""
+    mu0, tx, tt, th0, om, h = [float(v) for v in es.hyper]
+    cb, ce = oracle.constants(es.hyper)
+    S = oracle.row_sums(es.t, es.x, es.y, es.theta, es.hyper)
+    B0, B1, B2, B11, B22, X0, X1, X2, X11, X22 = S.T
+    lam = cb * B0 + ce * X0
+    d1 = [cb * B0 / mu0, cb * (-2 * B0 / tx + B1 / tx ** 3), cb * (-B0 / tt + B2 / tt ** 3),
+          ce * X0 / th0, ce * (X0 / om - X1), ce * (-2 * X0 / h + X2 / h ** 3)]
+    d2 = [0.0 * B0, cb * (6 * B0 / tx ** 2 - 7 * B1 / tx ** 4 + B11 / tx ** 6),
+          cb * (2 * B0 / tt ** 2 - 5 * B2 / tt ** 4 + B22 / tt ** 6), 0.0 * X0, ce * (X11 - 2 * X1 / om),
+          ce * (6 * X0 / h ** 2 - 7 * X2 / h ** 4 + X22 / h ** 6)]
+    return np.array([np.sum(np.abs(d2[p]) / lam + (d1[p] / lam) ** 2) for p in range(6)])
+
+
+@pytest.mark.parametrize("case", ["sparse_range", "far"])
+def test_isolated_events_match_oracle(gpu, case):
+    """Rows whose intensity from the FP32 pair terms falls below
+    (c_b + c_e) n 2^-96 are recomputed in FP64 by the row finalisation: every
+    output matches the oracle, where the FP32 terms alone would give
+    lambda_i = 0 and loglik = -inf.  On the sparse set the hyperparameter
+    Hessian's per-event terms cancel about 40-fold (their magnitudes sum to
+    ~1e6 against a diagonal of ~8e4 for omega), so its entries are held to
+    1e-6 of that magnitude, the scale of the FP32 terms' rounding."""
+    es = _isolated_set(case)
+    ref = oracle.evaluate_es(es)
+    assert np.isfinite(ref["loglik"]) and ref["lam"].min() < 1e-38
+    gpu_r = run_gpu(es)
+    _check(es, gpu_r, ref, tiny=True, hh_mag=_hyper_hessian_magnitude(es))
+
+
+@pytest.mark.parametrize("case", ["sparse_range", "far"])
+def test_isolated_events_grad_only_matches_oracle(gpu, case):
+    """Eq. 4 alone on the same sets: the chunks that hold a row of large weight
+    log2(c_e / lambda_i) split every exponent exactly."""
+    import torch
+
+    from paper_2103_03348_amd.hawkes import Plan
+
+    es = _isolated_set(case)
+    plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
+    th = torch.as_tensor(es.theta, device="cuda:0")
+    out = plan.eval(th, es.hyper, loglik=True, grad_theta=True)
+    g = out["grad_theta"].cpu().numpy()
+    ll = float(out["loglik"].item())
+    st = plan.status()
+    plan.close()
+    ref = oracle.evaluate_es(es, want=("loglik", "grad_theta"))
+    theta0, omega = es.hyper[3], es.hyper[4]
+    a = theta0 * (1.0 - np.exp(-omega * (es.t.max() - es.t)))
+    g_rel = float(np.max(np.abs(g - ref["grad_theta"]) / np.maximum(a + (ref["grad_theta"] + a), 1e-300)))
+    print(f"\nisolated grad only {case}: dl {abs(ll - ref['loglik']):.3e} g {g_rel:.3e}")
+    assert st == 0
+    assert abs(ll - ref["loglik"]) <= 2e-6 * es.n
     assert g_rel < 1e-6
