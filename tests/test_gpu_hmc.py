@@ -194,6 +194,35 @@ def test_hmc_step_replays_oracle(gpu):
         assert abs(out[6] - r["H0"]) < 1e-6 * max(1.0, abs(r["H0"]))
 
 
+def test_hmc_step_replays_oracle_isolated(gpu):
+    """hmc_step against the oracle's iteration on 2,500 events over 1e5 time
+    units (166 free rates): 60 intensities lie below FP32's range and wide
+    subset batches take the unsplit exponent; same momenta, path, energy change
+    and accept decision as the FP64 oracle.  dH and H0 to 2e-9 and 1e-9 of
+    |loglik| (its 1e-9 target at each end), the path's end to 1e-6."""
+    es = synth.small(2500, seed=9, t_end=1e5, all_free=False)
+    plan, idx = _setup(es)
+    m = es.subset.shape[0]
+    z0 = np.log(es.theta[es.subset])
+    mass = np.full(m, 6.0)
+    for counter in range(2):
+        zg, thg, out = _hmc_gpu(plan, es, z0, mass, 0.05, 8, 0.5, 91, counter)
+        assert plan.status() == 0
+        r = ohmc.hmc_iteration(es.t, es.x, es.y, es.theta, es.subset, z0, mass, es.hyper, 0.0, 0.05, 8, 0.5,
+                               91, counter)
+        print(f"\ncounter {counter}: gpu dH {out[1]:.9f} acc {out[0]} | oracle dH {r['dH']:.9f} acc {r['accepted']}")
+        assert abs(out[1] - r["dH"]) < 2e-9 * abs(r["H0"])
+        margin = abs(np.log(r["u"]) + r["dH"])
+        if margin > 1e-4:
+            assert bool(out[0]) == r["accepted"]
+        if r["accepted"]:
+            np.testing.assert_allclose(zg, r["z_proposal"], atol=1e-6)
+        else:
+            np.testing.assert_array_equal(zg, z0)
+        assert abs(out[6] - r["H0"]) < 1e-9 * abs(r["H0"])
+    plan.close()
+
+
 def test_hmc_deterministic(gpu):
     es = synth.small(300, seed=24, all_free=False)
     plan, _ = _setup(es)
