@@ -319,17 +319,24 @@ def test_underflow_cutoff_changes_nothing(gpu, cfg):
         assert rel <= 1e-12, k
 
 
-@pytest.mark.parametrize("case", ["n23422", "sparse"])
+@pytest.mark.parametrize("case", ["n23422", "sparse", "isolated"])
 def test_underflow_cutoff_matches_oracle(gpu, case):
     """The cutoff path against the FP64 oracle (which sums every pair), at the
     parity tolerances: on the N = 23,422 workload and on a sparse set (3,000
     events over 3,000 time units, so that chunk pairs more than the cutoff's
-    ~222 time units apart are skipped whole)."""
+    ~222 time units apart are skipped whole); isolated: 2,500 events over 1e5
+    time units, whose rows with every term below the cutoff get lambda_i from
+    the finalisation's FP64 recomputation."""
     import torch
 
     from paper_2103_03348_amd.hawkes import Plan
 
-    es = synth.config(1) if case == "n23422" else synth.small(3000, seed=35, t_end=3000.0, ties=3)
+    if case == "n23422":
+        es = synth.config(1)
+    elif case == "sparse":
+        es = synth.small(3000, seed=35, t_end=3000.0, ties=3)
+    else:
+        es = _isolated_set("sparse_range")
     plan = Plan.from_numpy(es.t, es.x, es.y, es.t0)
     plan.set_cutoff(True)
     th = torch.as_tensor(es.theta, device="cuda:0")
@@ -340,7 +347,10 @@ def test_underflow_cutoff_matches_oracle(gpu, case):
     g["lam"] = lam.cpu().numpy()
     g["status"] = plan.status()
     plan.close()
-    _check(es, g, oracle.evaluate_es(es))
+    if case == "isolated":
+        _check(es, g, oracle.evaluate_es(es), tiny=True, hh_mag=_hyper_hessian_magnitude(es))
+    else:
+        _check(es, g, oracle.evaluate_es(es))
 
 
 @pytest.mark.parametrize("case", ["n23422", "sparse"])
