@@ -72,3 +72,31 @@ def errors(es, gpu, ref):
         out["gh_abs"] = np.abs(gpu["grad_hyper"] - ref["grad_hyper"])
         out["Hh_abs"] = np.abs(gpu["negH_hyper"] - ref["negH_hyper"])
     return out
+
+
+def hyper_magnitudes(es):
+    """Per hyperparameter, sum_i |lambda'_i| / lambda_i and
+    sum_i |lambda''_i| / lambda_i + (lambda'_i / lambda_i)^2: the magnitudes of
+    the per-event terms whose sums are the likelihood parts of the
+    hyperparameter gradient and Hessian diagonal, from the oracle's per-event
+    pair sums and the derivatives of lambda_i in the six hyperparameters."""
+    import oracle
+
+    mu0, tx, tt, th0, om, h = [float(v) for v in es.hyper]
+    cb, ce = oracle.constants(es.hyper)
+    S = oracle.row_sums(es.t, es.x, es.y, es.theta, es.hyper)
+    B0, B1, B2, B11, B22, X0, X1, X2, X11, X22 = S.T
+    lam = cb * B0 + ce * X0
+    d1 = [cb * B0 / mu0, cb * (-2 * B0 / tx + B1 / tx ** 3), cb * (-B0 / tt + B2 / tt ** 3),
+          ce * X0 / th0, ce * (X0 / om - X1), ce * (-2 * X0 / h + X2 / h ** 3)]
+    d2 = [0.0 * B0, cb * (6 * B0 / tx ** 2 - 7 * B1 / tx ** 4 + B11 / tx ** 6),
+          cb * (2 * B0 / tt ** 2 - 5 * B2 / tt ** 4 + B22 / tt ** 6), 0.0 * X0, ce * (X11 - 2 * X1 / om),
+          ce * (6 * X0 / h ** 2 - 7 * X2 / h ** 4 + X22 / h ** 6)]
+    g_mag = np.array([np.sum(np.abs(d1[p]) / lam) for p in range(6)])
+    h_mag = np.array([np.sum(np.abs(d2[p]) / lam + (d1[p] / lam) ** 2) for p in range(6)])
+    return g_mag, h_mag
+
+
+def hyper_hessian_magnitude(es):
+    """The Hessian part of hyper_magnitudes."""
+    return hyper_magnitudes(es)[1]

@@ -28,7 +28,7 @@ import pytest
 import oracle
 from paper_2103_03348_amd import synth
 
-from gpu_helpers import errors, run_gpu
+from gpu_helpers import errors, hyper_hessian_magnitude, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -348,7 +348,7 @@ def test_underflow_cutoff_matches_oracle(gpu, case):
     g["status"] = plan.status()
     plan.close()
     if case == "isolated":
-        _check(es, g, oracle.evaluate_es(es), tiny=True, hh_mag=_hyper_hessian_magnitude(es))
+        _check(es, g, oracle.evaluate_es(es), tiny=True, hh_mag=hyper_hessian_magnitude(es))
     else:
         _check(es, g, oracle.evaluate_es(es))
 
@@ -440,24 +440,6 @@ def _isolated_set(case):
     return synth.EventSet(t, x, y, theta, base.subset, base.z, base.hyper, base.t0, "far")
 
 
-def _hyper_hessian_magnitude(es):
-    """sum_i |lambda''_i| / lambda_i + (lambda'_i / lambda_i)^2 per hyperparameter
-    (the per-event terms whose sum is the likelihood part of the hyperparameter
-    Hessian diagonal), from the oracle's per-event pair sums and the
-    derivatives of lambda_i in the six hyperparameters."""
-    mu0, tx, tt, th0, om, h = [float(v) for v in es.hyper]
-    cb, ce = oracle.constants(es.hyper)
-    S = oracle.row_sums(es.t, es.x, es.y, es.theta, es.hyper)
-    B0, B1, B2, B11, B22, X0, X1, X2, X11, X22 = S.T
-    lam = cb * B0 + ce * X0
-    d1 = [cb * B0 / mu0, cb * (-2 * B0 / tx + B1 / tx ** 3), cb * (-B0 / tt + B2 / tt ** 3),
-          ce * X0 / th0, ce * (X0 / om - X1), ce * (-2 * X0 / h + X2 / h ** 3)]
-    d2 = [0.0 * B0, cb * (6 * B0 / tx ** 2 - 7 * B1 / tx ** 4 + B11 / tx ** 6),
-          cb * (2 * B0 / tt ** 2 - 5 * B2 / tt ** 4 + B22 / tt ** 6), 0.0 * X0, ce * (X11 - 2 * X1 / om),
-          ce * (6 * X0 / h ** 2 - 7 * X2 / h ** 4 + X22 / h ** 6)]
-    return np.array([np.sum(np.abs(d2[p]) / lam + (d1[p] / lam) ** 2) for p in range(6)])
-
-
 @pytest.mark.parametrize("case", ["sparse_range", "far"])
 def test_isolated_events_match_oracle(gpu, case):
     """Rows whose intensity from the FP32 pair terms falls below
@@ -471,7 +453,7 @@ def test_isolated_events_match_oracle(gpu, case):
     ref = oracle.evaluate_es(es)
     assert np.isfinite(ref["loglik"]) and ref["lam"].min() < 1e-38
     gpu_r = run_gpu(es)
-    _check(es, gpu_r, ref, tiny=True, hh_mag=_hyper_hessian_magnitude(es))
+    _check(es, gpu_r, ref, tiny=True, hh_mag=hyper_hessian_magnitude(es))
 
 
 @pytest.mark.parametrize("case", ["sparse_range", "far"])
