@@ -163,7 +163,10 @@ hawkes_status hawkes_copy_lambda(hawkes_plan p, double *d_lambda, hipStream_t st
  * mass matrix.  Because only the subset rates move along a trajectory, the
  * library caches the part of every lambda_i that does not depend on them (the
  * background, and the excitation by fixed-rate events) once per
- * hyperparameter setting; each gradient then costs O(N M) pair terms. */
+ * hyperparameter setting; each gradient then costs O(N M) pair terms.  As in
+ * hawkes_eval, an intensity below (c_b + c_e) n 2^-96 is recomputed from the
+ * definitions in FP64 (its static part once, its subset excitation at each
+ * evaluation), so the subset path keeps FP64's range of lambda_i. */
 
 /* Declare the free-rate subset of a plan.
  *   m      subset size, 1 <= m <= n
