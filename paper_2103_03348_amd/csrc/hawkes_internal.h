@@ -157,7 +157,7 @@ const double *hk_tree_precision_diag(hawkes_plan p);
 void hk_tree_free(hawkes_plan p);
 // Blocks of a pair pass (0 = row, 1 = column) resident at once on `device`:
 // compute units times the pass kernels' occupancy.
-int64_t hk_pass_slots(int device, int pass);
+int64_t hk_pass_slots(int device, int pass, int64_t npad);
 void hk_subset_free(hawkes_plan p);
 // views of the free-rate subset for the preconditioner code
 void hk_subset_view(hawkes_plan p, int64_t *m, const int64_t **cidx, const int **pos, const int **slot);

@@ -311,12 +311,12 @@ extern "C" hawkes_status hawkes_plan_create(hawkes_plan *out, int64_t n, const d
     // block stops at its own chunk 4I + w
     Schedule rs = make_schedule(
         T, [](int) { return 0; }, [&](int I) { return C4 * (I + 1); },
-        [&](int I, int c) { return c < C4 * I ? C4 : C4 - (c - C4 * I); }, hk_pass_slots(p->device, 0));
+        [&](int I, int c) { return c < C4 * I ? C4 : C4 - (c - C4 * I); }, hk_pass_slots(p->device, 0, p->npad));
     // column pass: column tile J sweeps row chunks [4J, nchunks); wavefront w
     // starts at its own chunk 4J + w
     Schedule cs = make_schedule(
         T, [&](int J) { return C4 * J; }, [&](int) { return p->nchunks; },
-        [&](int J, int c) { return c >= C4 * (J + 1) ? C4 : 1 + (c - C4 * J); }, hk_pass_slots(p->device, 1));
+        [&](int J, int c) { return c >= C4 * (J + 1) ? C4 : 1 + (c - C4 * J); }, hk_pass_slots(p->device, 1, p->npad));
     std::vector<int64_t> cpoff(T);
     int64_t cpl = 0;
     for (int I = 0; I < T; ++I) {
