@@ -131,39 +131,43 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const float *__restrict__ param
     if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
 }
 
-// One thread per parameter: the batch sum of its gradient terms in fixed order (FP64).
+// One wavefront per parameter: lane l sums the gradient terms of samples
+// l, l + 64, ... in FP64, then a fixed butterfly of shuffles adds the 64 lane
+// sums, so the result does not depend on timing.
 __global__ __launch_bounds__(256) void k_mlp_wgrad(const float *__restrict__ X, int64_t n_rows,
                                                    const int *__restrict__ rows, int64_t B,
                                                    const float *__restrict__ h1,
                                                    const float *__restrict__ h2, const float *__restrict__ d1,
                                                    const float *__restrict__ d2, const float *__restrict__ dy,
                                                    double *__restrict__ grad) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     if (q >= MLP_NP) return;
     double acc = 0.0;
     if (q < MLP_OFF_B1) {
         const int k = q / MLP_IN, j = q % MLP_IN;
-        for (int64_t s = 0; s < B; ++s) {
+        for (int64_t s = lane; s < B; s += 64) {
             bool ok;
             const int64_t row = checked_row(rows, s, n_rows, nullptr, ok);
             if (ok) acc += (double)d1[s * MLP_H + k] * (double)X[row * MLP_IN + j];
         }
     } else if (q < MLP_OFF_W2) {
         const int k = q - MLP_OFF_B1;
-        for (int64_t s = 0; s < B; ++s) acc += (double)d1[s * MLP_H + k];
+        for (int64_t s = lane; s < B; s += 64) acc += (double)d1[s * MLP_H + k];
     } else if (q < MLP_OFF_B2) {
         const int k = (q - MLP_OFF_W2) / MLP_H, j = (q - MLP_OFF_W2) % MLP_H;
-        for (int64_t s = 0; s < B; ++s) acc += (double)d2[s * MLP_H + k] * (double)h1[s * MLP_H + j];
+        for (int64_t s = lane; s < B; s += 64) acc += (double)d2[s * MLP_H + k] * (double)h1[s * MLP_H + j];
     } else if (q < MLP_OFF_W3) {
         const int k = q - MLP_OFF_B2;
-        for (int64_t s = 0; s < B; ++s) acc += (double)d2[s * MLP_H + k];
+        for (int64_t s = lane; s < B; s += 64) acc += (double)d2[s * MLP_H + k];
     } else if (q < MLP_OFF_B3) {
         const int k = q - MLP_OFF_W3;
-        for (int64_t s = 0; s < B; ++s) acc += (double)dy[s] * (double)h2[s * MLP_H + k];
+        for (int64_t s = lane; s < B; s += 64) acc += (double)dy[s] * (double)h2[s * MLP_H + k];
     } else {
-        for (int64_t s = 0; s < B; ++s) acc += (double)dy[s];
+        for (int64_t s = lane; s < B; s += 64) acc += (double)dy[s];
     }
-    grad[q] = acc;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) grad[q] = acc;
 }
 
 __global__ void k_mlp_loss(const double *__restrict__ part, int nb, int64_t B, double *__restrict__ loss) {
@@ -445,8 +449,8 @@ static void mlp_grad_launch(const float *d_params, const float *d_x, int64_t n_r
                        d_err);
     hipLaunchKernelGGL(k_mlp_bwd, dim3(nb), dim3(256), 0, stream, d_params, y, d_target, n_rows, d_rows, B, h1, h2,
                        d1, d2, dy, lpart);
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk(MLP_NP, 256)), dim3(256), 0, stream, d_x, n_rows, d_rows, B, h1, h2,
-                       d1, d2, dy, d_grad);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((int64_t)MLP_NP * 64, 256)), dim3(256), 0, stream, d_x, n_rows, d_rows,
+                       B, h1, h2, d1, d2, dy, d_grad);
     if (d_loss) hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(64), 0, stream, lpart, (int)nb, B, d_loss);
 }
 
