@@ -203,8 +203,12 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
                                                     const int64_t *__restrict__ colpart_off, const FinConst fc,
                                                     double *__restrict__ lam_static, double *__restrict__ blockpart) {
     __shared__ double sh[HK_WAVES];
+    __shared__ double red[HK_WAVES][2];
+    __shared__ uint64_t low_mask[HK_WAVES];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (HK_WAVE - 1), wq = threadIdx.x / HK_WAVE;
     double lam_part = 0.0;
+    double ls = 1.0;
     if (i < n) {
         const int I = (int)(i / HK_TILE), r = (int)(i % HK_TILE);
         // the log-likelihood-only row pass: B0 (row and column partials) and X0
@@ -215,27 +219,53 @@ __global__ __launch_bounds__(256) void k_sub_static(const double *__restrict__ t
             x0 += rp[5 * HK_TILE];
         }
         for (int J = I; J < ntiles; ++J) b0 += (double)colpart[colpart_off[J] + i];
-        double ls = fc.c_b * b0 * fc.corr + fc.c_e * x0 * fc.corr;
-        if (ls < fc.lam_exact) {
-            // the FP32 pair terms may have lost more than 2^-30 of this row's
-            // static intensity: recompute it from the definitions in FP64
-            // (background over every j != i, excitation from the earlier
-            // fixed-rate events; theta_s is zero on the subset)
-            const double xi = xs[i], yi = ys[i], tsi = ts[i];
-            const int gi = g[i];
+        ls = fc.c_b * b0 * fc.corr + fc.c_e * x0 * fc.corr;
+    }
+    // rows whose static intensity is below fc.lam_exact (the FP32 pair terms may
+    // have lost more than 2^-30 of it) are recomputed from the definitions in
+    // FP64 by the whole block, one row at a time: background over every j != i,
+    // excitation from the earlier fixed-rate events (theta_s is zero on the subset)
+    const uint64_t mine = __ballot(i < n && ls < fc.lam_exact);
+    if (lane == 0) low_mask[wq] = mine;
+    __syncthreads();
+    for (int w = 0; w < HK_WAVES; ++w) {
+        for (uint64_t mk = low_mask[w]; mk != 0; mk &= mk - 1) {
+            const int rr = __ffsll((unsigned long long)mk) - 1;
+            const int64_t ir = blockIdx.x * (int64_t)blockDim.x + w * HK_WAVE + rr;
+            const double xi = xs[ir], yi = ys[ir], tsi = ts[ir];
+            const int gi = g[ir];
             const double kb = 0.5 / (fc.tau_x * fc.tau_x), kt = 0.5 / (fc.tau_t * fc.tau_t);
             const double kh = 0.5 / (fc.h * fc.h);
             double B0 = 0.0, X0 = 0.0;
-            for (int64_t j = 0; j < n; ++j) {
-                if (j == i) continue;
+            for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+                if (j == ir) continue;
                 const double dx = xi - xs[j], dy = yi - ys[j];
                 const double r2 = dx * dx + dy * dy;
                 const double dt = tsi - ts[j];
                 B0 += exp(-(r2 * kb) - dt * dt * kt);
                 if (j < gi && theta_s[j] != 0.0f) X0 += theta[perm[j]] * exp(-fc.omega * dt - r2 * kh);
             }
-            ls = fc.c_b * B0 + fc.c_e * X0;
+            for (int off = 32; off > 0; off >>= 1) {
+                B0 += __shfl_xor(B0, off);
+                X0 += __shfl_xor(X0, off);
+            }
+            if (lane == 0) {
+                red[wq][0] = B0;
+                red[wq][1] = X0;
+            }
+            __syncthreads();
+            if (threadIdx.x == w * HK_WAVE + rr) {
+                double b = red[0][0], x = red[0][1];
+                for (int q = 1; q < HK_WAVES; ++q) {
+                    b += red[q][0];
+                    x += red[q][1];
+                }
+                ls = fc.c_b * b + fc.c_e * x;
+            }
+            __syncthreads();
         }
+    }
+    if (i < n) {
         lam_static[i] = ls;
         // integral term: background (all events) + excitation of the fixed-rate events
         const double ti = ts[i];
